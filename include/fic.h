@@ -1,0 +1,162 @@
+/*
+ * fic.h -- C ABI of libfic.so: fractal (PIFS) image encoding and decoding on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow the problem statement of "GPU Accelerated Fractal
+ * Image Compression for Medical Imaging in Parallel Computing Platform"
+ * (arXiv 1404.0774):
+ *   - the image is split into n x n non-overlapping range blocks and 2n x 2n
+ *     domain blocks on a grid of spacing STEP, each domain contracted 2x2 and
+ *     taken under eight square symmetries (Section V, Alg. 1);
+ *   - every range is compared with every transformed domain by least squares
+ *     and the pair with the smallest residual is kept (eqs. 8-12, Alg. 2-3);
+ *   - the code of a range is {domain, transform, s, o} (Alg. 2), decoded by
+ *     iterating the partitioned IFS map (eq. 6) towards its attractor
+ *     (Section III).
+ *
+ * Conventions shared by every entry point:
+ *   - Every data pointer is a DEVICE pointer owned by the caller (for example
+ *     the data_ptr() of a torch tensor).  The library allocates nothing and
+ *     frees nothing.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls validate their arguments on the host, enqueue work on `stream`
+ *     and return without synchronising; outputs are valid once the stream
+ *     has reached the call.
+ *   - Return value: FIC_OK (0) or one of the FIC_E_* codes below.  On error
+ *     nothing has been enqueued, except for FIC_E_HIP, which reports a failed
+ *     launch.  fic_last_error() gives a message for the calling thread.
+ *   - Images are row-major, height x width, uint8 (bit_depth 8) or uint16
+ *     (bit_depth 12, values 0..4095).
+ *   - Ranges are numbered row-major: r = ry * (width / n) + rx.  Domains are
+ *     numbered row-major over their grid: d = dy * NX + dx with top-left
+ *     corner (dy * STEP, dx * STEP), NX = (width - 2n) / STEP + 1.
+ *   - Transform k in 0..7 maps the contracted domain T to the block
+ *     B[i][j] = T[sigma_k(i, j)], with m = n - 1:
+ *       0 (i, j)      identity            4 (i, m-j)    mirror left-right
+ *       1 (j, m-i)    rotate 90 ccw       5 (j, i)      transpose
+ *       2 (m-i, m-j)  rotate 180          6 (m-i, j)    mirror top-bottom
+ *       3 (m-j, i)    rotate 270 ccw      7 (m-j, m-i)  anti-transpose
+ *     The candidate index is c = 8 d + k.
+ *   - Quantisation: s = s_idx / 2^(s_bits-1) - 1;
+ *     o = o_idx * delta_o - 2^bit_depth with delta_o = 2^(bit_depth+1-o_bits).
+ */
+#ifndef FIC_H
+#define FIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fic_status {
+  FIC_OK = 0,
+  FIC_E_INVALID = 1,     /* null pointer, bad geometry, bad count */
+  FIC_E_UNSUPPORTED = 2, /* valid request outside what the kernels handle */
+  FIC_E_WORKSPACE = 3,   /* workspace smaller than fic_query reported */
+  FIC_E_HIP = 4          /* a HIP launch or runtime call failed */
+};
+
+enum fic_method {
+  FIC_METHOD_MFMA = 0,  /* search as an FP16 matrix-core contraction */
+  FIC_METHOD_DIRECT = 1 /* plain method: LDS-tiled per-candidate sums */
+};
+
+typedef struct {
+  int32_t height, width; /* pixels; multiples of range_size */
+  int32_t bit_depth;     /* 8 or 12 */
+  int32_t range_size;    /* n: 4 or 8 */
+  int32_t domain_step;   /* STEP >= 1 */
+  int32_t s_bits;        /* contrast bits, 1..8 (5 in the reference setup) */
+  int32_t o_bits;        /* offset bits, 1..bit_depth+1 (7) */
+  int32_t method;        /* enum fic_method */
+} fic_params;
+
+/* Codes, one entry per range (structure of arrays, device memory). */
+typedef struct {
+  int32_t *domain; /* d */
+  uint8_t *iso;    /* k */
+  uint8_t *s_idx;  /* contrast index */
+  uint8_t *o_idx;  /* offset index */
+  double *err;     /* residual of eq. (8) with the quantised s and o */
+} fic_codes;
+
+/*
+ * fic_query -- host only, no GPU work.  Validates `p` and reports the range
+ * and domain counts and the workspace bytes that fic_encode and
+ * fic_decode_backward need for these parameters.  Any output pointer may be
+ * NULL.  Errors: FIC_E_INVALID (null p, height or width not a multiple of n,
+ * 2n larger than a side, STEP < 1), FIC_E_UNSUPPORTED (bit_depth not 8 or 12,
+ * n not 4 or 8, s_bits/o_bits out of range, more candidates than the packed
+ * 64-bit search key can index).
+ */
+int fic_query(const fic_params *p, int64_t *n_ranges, int64_t *n_domains,
+              size_t *encode_ws_bytes, size_t *backward_ws_bytes);
+
+/*
+ * fic_encode -- exhaustive range-domain search (Alg. 2 / Alg. 3, eqs. 8-12).
+ * For every range, among all candidates c = 8 d + k, keeps the one with the
+ * smallest residual after the fit s = eq. (9) (eq. (11) when the domain has
+ * no variance), s quantised (round half up, clamped), o = eq. (10) with the
+ * quantised s, o quantised the same way.  Ties keep the smallest c.
+ *   image      device, height*width pixels (uint8 or uint16, see above)
+ *   out        device arrays of n_ranges entries each, written
+ *   workspace  device, >= encode_ws_bytes from fic_query, 256-byte aligned;
+ *              contents on entry are ignored and on return are undefined
+ * The result does not depend on `method`.
+ */
+int fic_encode(const fic_params *p, const void *image, fic_codes out,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * fic_decode -- iterate the partitioned IFS map (eq. 6) `iters` times from
+ * the constant image x0 (Section III: the attractor of a contractive map):
+ *   x_{t+1}[range r, pixel (i,j)] = s_r * mean2x2(x_t, cell sigma_k(i,j) of
+ *                                   domain d_r) + o_r
+ * in FP32.  traj receives (iters + 1) images of height*width floats,
+ * traj[0] = x0.  domain/iso/s/o hold one entry per range (device).
+ * Errors: FIC_E_INVALID (null pointers, iters < 0).
+ */
+int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
+               const float *s, const float *o, int32_t iters, float x0,
+               float *traj, void *stream);
+
+/*
+ * fic_decode_backward -- reverse pass of fic_decode with respect to s and o.
+ * Given traj from fic_decode (same codes, same iters) and grad_xT = dL/dx_T
+ * (height*width floats), writes dL/ds and dL/do (n_ranges floats each,
+ * overwritten).  Deterministic: repeated calls give identical bits.
+ *   workspace  device, >= backward_ws_bytes from fic_query
+ */
+int fic_decode_backward(const fic_params *p, const int32_t *domain,
+                        const uint8_t *iso, const float *s, const float *o,
+                        int32_t iters, const float *traj, const float *grad_xT,
+                        float *grad_s, float *grad_o, void *workspace,
+                        size_t ws_bytes, void *stream);
+
+/*
+ * Benchmark support (not needed to encode).  fic_timing_begin enables and
+ * resets phase timing: while enabled, every fic_encode records HIP events on
+ * its own stream before operand preparation, before the search, before code
+ * extraction and at its end (the most recent 256 calls are kept).
+ * fic_timing_end waits for those events, returns the number of timed calls
+ * and the summed milliseconds of each phase, and disables timing.  Not
+ * thread-safe: meant for a single benchmarking thread.  Errors: FIC_E_HIP
+ * (event creation or query failed), FIC_E_INVALID (end without begin).
+ */
+int fic_timing_begin(void);
+int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_search,
+                   double *ms_finalize);
+
+/* Message for a status code; never NULL. */
+const char *fic_status_string(int status);
+
+/* Message of the calling thread's last failed call ("" if none). */
+const char *fic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIC_H */

@@ -193,13 +193,88 @@ static int check_params(int height, int width, int bits, int n, int step,
   return OR_OK;
 }
 
+/* Alg. 3 for one range: all domains d in row-major order, all eight
+ * transforms, least squares, residual; keep the strictly smaller residual. */
+static void search_range(int width, int n, const uint16_t *img,
+                         const double *pool, int64_t ND, int bits, int s_bits,
+                         int o_bits, int64_t r, int32_t *out_domain,
+                         uint8_t *out_iso, uint8_t *out_sidx, uint8_t *out_oidx,
+                         double *out_err) {
+  const int K = n * n;
+  const int rw = width / n;
+  double b[ORACLE_MAX_N * ORACLE_MAX_N], a[ORACLE_MAX_N * ORACLE_MAX_N];
+  const int ry = (int)(r / rw), rx = (int)(r % rw);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      b[i * n + j] = (double)img[(size_t)(ry * n + i) * width + rx * n + j];
+
+  double best = INFINITY;
+  int64_t best_d = 0;
+  int best_k = 0;
+  fit_t best_f = {0, 0, 0, 0, INFINITY};
+  for (int64_t d = 0; d < ND; ++d) {
+    for (int k = 0; k < 8; ++k) {
+      oracle_isometry(pool + (size_t)d * K, n, k, a);
+      fit_t f = fit_block(a, b, K, bits, s_bits, o_bits);
+      if (f.err < best) {
+        best = f.err;
+        best_d = d;
+        best_k = k;
+        best_f = f;
+      }
+    }
+  }
+  *out_domain = (int32_t)best_d;
+  *out_iso = (uint8_t)best_k;
+  *out_sidx = (uint8_t)best_f.j;
+  *out_oidx = (uint8_t)best_f.m;
+  *out_err = best_f.err;
+}
+
+/* Alg. 1: the contracted domains of the grid, row-major. */
+static double *build_pool(int height, int width, int n, int step,
+                          const uint16_t *img, int64_t *ND) {
+  const int K = n * n;
+  const int ny = domain_axis(height, n, step), nx = domain_axis(width, n, step);
+  *ND = (int64_t)ny * nx;
+  double *pool = (double *)malloc(sizeof(double) * (size_t)(*ND) * K);
+  for (int dy = 0; dy < ny; ++dy)
+    for (int dx = 0; dx < nx; ++dx)
+      oracle_contract(img, width, dy * step, dx * step, n,
+                      pool + ((size_t)dy * nx + dx) * K);
+  return pool;
+}
+
 /*
- * Encode ranges [r_begin, r_end) of the image (row-major range index).
- * The codebook of contracted domains (Alg. 1) is built once; every range then
- * runs Alg. 3's loop: all domains d in row-major order, all eight transforms,
- * least squares, residual, keep the strictly smaller residual.
- * Outputs are indexed by r - r_begin.  n_threads <= 0 uses OpenMP's default.
+ * Encode the ranges listed in `ranges` (row-major range indices); outputs
+ * are indexed by position in the list.  n_threads <= 0 uses OpenMP's
+ * default.
  */
+int oracle_encode_list(int height, int width, int bits, int n, int step,
+                       int s_bits, int o_bits, const uint16_t *img,
+                       const int64_t *ranges, int64_t count, int n_threads,
+                       int32_t *out_domain, uint8_t *out_iso,
+                       uint8_t *out_sidx, uint8_t *out_oidx, double *out_err) {
+  if (check_params(height, width, bits, n, step, s_bits, o_bits))
+    return OR_EINVAL;
+  const int64_t R = oracle_n_ranges(height, width, n);
+  for (int64_t i = 0; i < count; ++i)
+    if (ranges[i] < 0 || ranges[i] >= R) return OR_EINVAL;
+  int64_t ND;
+  double *pool = build_pool(height, width, n, step, img, &ND);
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+  for (int64_t i = 0; i < count; ++i)
+    search_range(width, n, img, pool, ND, bits, s_bits, o_bits, ranges[i],
+                 out_domain + i, out_iso + i, out_sidx + i, out_oidx + i,
+                 out_err + i);
+  free(pool);
+  return OR_OK;
+}
+
+/* Encode the contiguous ranges [r_begin, r_end). */
 int oracle_encode(int height, int width, int bits, int n, int step, int s_bits,
                   int o_bits, const uint16_t *img, int64_t r_begin,
                   int64_t r_end, int n_threads, int32_t *out_domain,
@@ -209,57 +284,15 @@ int oracle_encode(int height, int width, int bits, int n, int step, int s_bits,
     return OR_EINVAL;
   const int64_t R = oracle_n_ranges(height, width, n);
   if (r_begin < 0 || r_end > R || r_begin > r_end) return OR_EINVAL;
-  const int K = n * n;
-  const int ny = domain_axis(height, n, step), nx = domain_axis(width, n, step);
-  const int64_t ND = (int64_t)ny * nx;
-  const int rw = width / n;
-
-  /* Alg. 1: contracted domains, row-major over the grid. */
-  double *pool = (double *)malloc(sizeof(double) * (size_t)ND * K);
-  for (int dy = 0; dy < ny; ++dy)
-    for (int dx = 0; dx < nx; ++dx)
-      oracle_contract(img, width, dy * step, dx * step, n,
-                      pool + ((size_t)dy * nx + dx) * K);
-
-#ifdef _OPENMP
-  if (n_threads > 0) omp_set_num_threads(n_threads);
-#pragma omp parallel for schedule(dynamic, 1)
-#endif
-  for (int64_t r = r_begin; r < r_end; ++r) {
-    double *b = (double *)malloc(sizeof(double) * K);
-    double *a = (double *)malloc(sizeof(double) * K);
-    const int ry = (int)(r / rw), rx = (int)(r % rw);
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j)
-        b[i * n + j] = (double)img[(size_t)(ry * n + i) * width + rx * n + j];
-
-    double best = INFINITY;
-    int64_t best_d = 0;
-    int best_k = 0;
-    fit_t best_f = {0, 0, 0, 0, INFINITY};
-    for (int64_t d = 0; d < ND; ++d) {
-      for (int k = 0; k < 8; ++k) {
-        oracle_isometry(pool + (size_t)d * K, n, k, a);
-        fit_t f = fit_block(a, b, K, bits, s_bits, o_bits);
-        if (f.err < best) {
-          best = f.err;
-          best_d = d;
-          best_k = k;
-          best_f = f;
-        }
-      }
-    }
-    const int64_t o = r - r_begin;
-    out_domain[o] = (int32_t)best_d;
-    out_iso[o] = (uint8_t)best_k;
-    out_sidx[o] = (uint8_t)best_f.j;
-    out_oidx[o] = (uint8_t)best_f.m;
-    out_err[o] = best_f.err;
-    free(a);
-    free(b);
-  }
-  free(pool);
-  return OR_OK;
+  const int64_t count = r_end - r_begin;
+  int64_t *ranges = (int64_t *)malloc(sizeof(int64_t) * (size_t)(count + 1));
+  for (int64_t i = 0; i < count; ++i) ranges[i] = r_begin + i;
+  const int rc = oracle_encode_list(height, width, bits, n, step, s_bits,
+                                    o_bits, img, ranges, count, n_threads,
+                                    out_domain, out_iso, out_sidx, out_oidx,
+                                    out_err);
+  free(ranges);
+  return rc;
 }
 
 /* ---------------------------------------------------------------------------

@@ -35,6 +35,9 @@ def lib():
         L.oracle_encode.restype = i32
         L.oracle_encode.argtypes = [i32, i32, i32, i32, i32, i32, i32, p, i64, i64, i32,
                                     p, p, p, p, p]
+        L.oracle_encode_list.restype = i32
+        L.oracle_encode_list.argtypes = [i32, i32, i32, i32, i32, i32, i32, p, p, i64, i32,
+                                         p, p, p, p, p]
         L.oracle_decode.restype = i32
         L.oracle_decode.argtypes = [i32, i32, i32, i32, p, p, p, p, i32, dbl, p]
         L.oracle_decode_backward.restype = i32
@@ -108,6 +111,23 @@ def encode(img, n, step, bits=8, s_bits=5, o_bits=7, r_begin=0, r_end=None, thre
                              _ptr(out["o_idx"]), _ptr(out["err"]))
     if rc != 0:
         raise ValueError("oracle_encode: invalid parameters")
+    return out
+
+
+def encode_ranges(img, n, step, ranges, bits=8, s_bits=5, o_bits=7, threads=0):
+    """Full search for the listed range indices; returns dict of SoA arrays."""
+    img = np.ascontiguousarray(img, dtype=np.uint16)
+    H, W = img.shape
+    rs = np.ascontiguousarray(ranges, dtype=np.int64)
+    cnt = len(rs)
+    out = dict(domain=np.zeros(cnt, np.int32), iso=np.zeros(cnt, np.uint8),
+               s_idx=np.zeros(cnt, np.uint8), o_idx=np.zeros(cnt, np.uint8),
+               err=np.zeros(cnt, np.float64))
+    rc = lib().oracle_encode_list(H, W, bits, n, step, s_bits, o_bits, _ptr(img), _ptr(rs), cnt,
+                                  threads, _ptr(out["domain"]), _ptr(out["iso"]),
+                                  _ptr(out["s_idx"]), _ptr(out["o_idx"]), _ptr(out["err"]))
+    if rc != 0:
+        raise ValueError("oracle_encode_list: invalid parameters")
     return out
 
 

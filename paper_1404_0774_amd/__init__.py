@@ -1,0 +1,13 @@
+"""Fractal (PIFS) image encoding on AMD Instinct MI355X.
+
+The compute path lives in libfic.so (hand-written HIP for gfx950, built by
+``paper_1404_0774_amd.build``); this package only marshals arguments to its C
+ABI.  PyTorch provides device memory and streams.
+"""
+from ._lib import (FicError, Params, encode, decode, decode_backward, query,
+                   dequantize, FicDecode, lib, METHOD_MFMA, METHOD_DIRECT,
+                   timing_begin, timing_end)
+
+__all__ = ["FicError", "Params", "encode", "decode", "decode_backward", "query",
+           "dequantize", "FicDecode", "lib", "METHOD_MFMA", "METHOD_DIRECT",
+           "timing_begin", "timing_end"]

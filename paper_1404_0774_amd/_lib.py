@@ -1,0 +1,232 @@
+"""ctypes binding of libfic.so (argument marshalling only).
+
+Every function here forwards to one C entry point of ``include/fic.h``; all
+arithmetic runs in the library's HIP kernels.  If the library is missing this
+module raises: there is no CPU fallback.
+"""
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfic.so")
+
+METHOD_MFMA = 0
+METHOD_DIRECT = 1
+
+_STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported parameters",
+           3: "workspace too small", 4: "HIP runtime error"}
+
+
+class FicError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("bit_depth", ctypes.c_int32), ("range_size", ctypes.c_int32),
+                ("domain_step", ctypes.c_int32), ("s_bits", ctypes.c_int32),
+                ("o_bits", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+class _Codes(ctypes.Structure):
+    _fields_ = [("domain", ctypes.c_void_p), ("iso", ctypes.c_void_p),
+                ("s_idx", ctypes.c_void_p), ("o_idx", ctypes.c_void_p),
+                ("err", ctypes.c_void_p)]
+
+
+@dataclass
+class Params:
+    height: int
+    width: int
+    bit_depth: int = 8
+    range_size: int = 8
+    domain_step: int = 4
+    s_bits: int = 5
+    o_bits: int = 7
+    method: int = METHOD_MFMA
+
+    def c(self):
+        return _Params(self.height, self.width, self.bit_depth, self.range_size,
+                       self.domain_step, self.s_bits, self.o_bits, self.method)
+
+
+_LIB = None
+
+
+def lib():
+    """Load libfic.so from the package directory (raises if it is not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1404_0774_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+        P = ctypes.POINTER(_Params)
+        L.fic_query.restype = ctypes.c_int
+        L.fic_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.fic_encode.restype = ctypes.c_int
+        L.fic_encode.argtypes = [P, vp, _Codes, vp, sz, vp]
+        L.fic_decode.restype = ctypes.c_int
+        L.fic_decode.argtypes = [P, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.fic_decode_backward.restype = ctypes.c_int
+        L.fic_decode_backward.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.fic_timing_begin.restype = ctypes.c_int
+        L.fic_timing_begin.argtypes = []
+        L.fic_timing_end.restype = ctypes.c_int
+        L.fic_timing_end.argtypes = [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_double)] * 3
+        L.fic_status_string.restype = ctypes.c_char_p
+        L.fic_status_string.argtypes = [ctypes.c_int]
+        L.fic_last_error.restype = ctypes.c_char_p
+        L.fic_last_error.argtypes = []
+        _LIB = L
+    return _LIB
+
+
+def _check(status):
+    if status != 0:
+        raise FicError(status, lib().fic_last_error().decode())
+
+
+def query(p: Params):
+    """Host-only: (n_ranges, n_domains, encode_ws_bytes, backward_ws_bytes)."""
+    nr, nd = ctypes.c_int64(), ctypes.c_int64()
+    ew, bw = ctypes.c_size_t(), ctypes.c_size_t()
+    cp = p.c()
+    _check(lib().fic_query(ctypes.byref(cp), ctypes.byref(nr), ctypes.byref(nd),
+                           ctypes.byref(ew), ctypes.byref(bw)))
+    return nr.value, nd.value, ew.value, bw.value
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes, device):
+    # 256-byte aligned view into a torch allocation
+    buf = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, buf.data_ptr() + off
+
+
+def _dev_ptr(t, dtype, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+def encode(image: torch.Tensor, p: Params, workspace=None):
+    """Encode one image (device tensor, uint8 or int16/uint16 holding 12-bit
+    values).  Returns a dict of device tensors: domain (int32), iso (uint8),
+    s_idx (uint8), o_idx (uint8), err (float64)."""
+    exp = torch.uint8 if p.bit_depth == 8 else torch.uint16
+    if image.dtype == torch.int16 and p.bit_depth == 12:
+        image = image.view(torch.uint16)
+    img_ptr = _dev_ptr(image, exp, "image")
+    if tuple(image.shape) != (p.height, p.width):
+        raise ValueError(f"image shape {tuple(image.shape)} != {(p.height, p.width)}")
+    nr, nd, ew, _ = query(p)
+    dev = image.device
+    out = dict(domain=torch.empty(nr, dtype=torch.int32, device=dev),
+               iso=torch.empty(nr, dtype=torch.uint8, device=dev),
+               s_idx=torch.empty(nr, dtype=torch.uint8, device=dev),
+               o_idx=torch.empty(nr, dtype=torch.uint8, device=dev),
+               err=torch.empty(nr, dtype=torch.float64, device=dev))
+    if workspace is None:
+        keep, ws = _workspace(ew, dev)
+    else:
+        keep, ws = workspace, workspace.data_ptr()
+        if workspace.numel() * workspace.element_size() < ew:
+            raise ValueError("workspace too small")
+    codes = _Codes(out["domain"].data_ptr(), out["iso"].data_ptr(), out["s_idx"].data_ptr(),
+                   out["o_idx"].data_ptr(), out["err"].data_ptr())
+    cp = p.c()
+    _check(lib().fic_encode(ctypes.byref(cp), ctypes.c_void_p(img_ptr), codes,
+                            ctypes.c_void_p(ws), ctypes.c_size_t(ew), _stream(dev)))
+    out["_ws"] = keep
+    return out
+
+
+def dequantize(s_idx, o_idx, p: Params):
+    """Grid values of quantised codes: s = s_idx/2^(s_bits-1) - 1, o = o_idx*delta_o - 2^bits."""
+    s = s_idx.to(torch.float32) / float(2 ** (p.s_bits - 1)) - 1.0
+    P = float(2 ** p.bit_depth)
+    o = o_idx.to(torch.float32) * (2.0 * P / 2 ** p.o_bits) - P
+    return s, o
+
+
+def decode(domain, iso, s, o, p: Params, iters=12, x0=None):
+    """Iterate the PIFS map; returns the trajectory (iters+1, H, W) float32."""
+    if x0 is None:
+        x0 = float(2 ** (p.bit_depth - 1))
+    dev = s.device
+    traj = torch.empty((iters + 1, p.height, p.width), dtype=torch.float32, device=dev)
+    cp = p.c()
+    _check(lib().fic_decode(ctypes.byref(cp), _dev_ptr(domain, torch.int32, "domain"),
+                            _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
+                            _dev_ptr(o, torch.float32, "o"), iters, ctypes.c_float(x0),
+                            traj.data_ptr(), _stream(dev)))
+    return traj
+
+
+def decode_backward(domain, iso, s, o, traj, grad_xT, p: Params):
+    """dL/ds, dL/do of the unrolled decoder given dL/dx_T."""
+    iters = traj.shape[0] - 1
+    dev = s.device
+    nr, _, _, bw = query(p)
+    gs = torch.empty(nr, dtype=torch.float32, device=dev)
+    go = torch.empty(nr, dtype=torch.float32, device=dev)
+    keep, ws = _workspace(bw, dev)
+    cp = p.c()
+    g = grad_xT.contiguous()
+    _check(lib().fic_decode_backward(ctypes.byref(cp), _dev_ptr(domain, torch.int32, "domain"),
+                                     _dev_ptr(iso, torch.uint8, "iso"),
+                                     _dev_ptr(s, torch.float32, "s"), _dev_ptr(o, torch.float32, "o"),
+                                     iters, _dev_ptr(traj, torch.float32, "traj"),
+                                     _dev_ptr(g, torch.float32, "grad_xT"), gs.data_ptr(),
+                                     go.data_ptr(), ctypes.c_void_p(ws), ctypes.c_size_t(bw),
+                                     _stream(dev)))
+    del keep
+    return gs, go
+
+
+def timing_begin():
+    """Start per-phase event timing of fic_encode calls (benchmark support)."""
+    _check(lib().fic_timing_begin())
+
+
+def timing_end():
+    """Stop timing; returns (n_calls, ms_prep, ms_search, ms_finalize) summed."""
+    n = ctypes.c_int32()
+    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib().fic_timing_end(ctypes.byref(n), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return n.value, a.value, b.value, c.value
+
+
+class FicDecode(torch.autograd.Function):
+    """x_T = decode(s, o) with domain and transform indices held fixed; the
+    backward pass is the library's hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, s, o, domain, iso, p, iters, x0):
+        s = s.contiguous()
+        o = o.contiguous()
+        traj = decode(domain, iso, s, o, p, iters, x0)
+        ctx.save_for_backward(s, o, domain, iso, traj)
+        ctx.p = p
+        return traj[-1]
+
+    @staticmethod
+    def backward(ctx, g):
+        s, o, domain, iso, traj = ctx.saved_tensors
+        gs, go = decode_backward(domain, iso, s, o, traj, g.contiguous(), ctx.p)
+        return gs, go, None, None, None, None, None

@@ -1,0 +1,323 @@
+// fic_abi.hip -- host side of the libfic C ABI: argument validation,
+// workspace layout and launch sequencing.  Validation is plain host code
+// (no HIP call), so every error path can be exercised without a GPU.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "fic_internal.h"
+
+namespace fic {
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int status, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return status;
+}
+
+int ok() {
+  g_last_error.clear();
+  return FIC_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+long long gcd_ll(long long a, long long b) {
+  while (b) {
+    long long t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Bits needed for the largest possible residual scaled to an integer.  For
+// any candidate |s_q| <= 1, pixels and contracted values lie in [0, P-1] and
+// the fitted offset overshoots the grid by at most P + delta_o - 2, so the
+// residual of eq. (8) is at most K (2P + delta_o - 3)^2.
+int residual_bits(const Geo &g) {
+  const double emax = (double)g.K * pow(2.0 * g.P + g.dlt - 3.0, 2.0);
+  const double v = emax * g.escale;
+  return (int)ceil(log2(v + 1.0));
+}
+
+// Validate the geometry and fill in Geo.  Host only.
+int make_geo(const fic_params *p, Geo &g, bool for_encode) {
+  if (!p) return fail(FIC_E_INVALID, "params is NULL");
+  const int n = p->range_size;
+  if (p->height <= 0 || p->width <= 0)
+    return fail(FIC_E_INVALID, "image size %dx%d is empty", p->height,
+                p->width);
+  if (n <= 0) return fail(FIC_E_INVALID, "range_size %d < 1", n);
+  if (p->height % n || p->width % n)
+    return fail(FIC_E_INVALID, "image %dx%d is not a multiple of range_size %d",
+                p->height, p->width, n);
+  if (2 * n > p->height || 2 * n > p->width)
+    return fail(FIC_E_INVALID, "domain side 2n = %d exceeds the image", 2 * n);
+  if (p->domain_step < 1)
+    return fail(FIC_E_INVALID, "domain_step %d < 1", p->domain_step);
+  if (p->bit_depth != 8 && p->bit_depth != 12)
+    return fail(FIC_E_UNSUPPORTED, "bit_depth %d (8 or 12)", p->bit_depth);
+  if (n != 4 && n != 8)
+    return fail(FIC_E_UNSUPPORTED, "range_size %d (4 or 8)", n);
+  if (p->s_bits < 1 || p->s_bits > 8)
+    return fail(FIC_E_UNSUPPORTED, "s_bits %d (1..8)", p->s_bits);
+  if (p->o_bits < 1 || p->o_bits > p->bit_depth + 1)
+    return fail(FIC_E_UNSUPPORTED, "o_bits %d (1..bit_depth+1)", p->o_bits);
+  if (for_encode && p->method != FIC_METHOD_MFMA &&
+      p->method != FIC_METHOD_DIRECT)
+    return fail(FIC_E_INVALID, "method %d", p->method);
+  if ((long long)p->height * p->width > (1ll << 30))
+    return fail(FIC_E_UNSUPPORTED, "image larger than 2^30 pixels");
+  if (for_encode && p->bit_depth == 12)
+    return fail(FIC_E_UNSUPPORTED, "12-bit search not built");
+
+  g.H = p->height;
+  g.W = p->width;
+  g.bits = p->bit_depth;
+  g.n = n;
+  g.K = n * n;
+  g.step = p->domain_step;
+  g.sb = p->s_bits;
+  g.ob = p->o_bits;
+  g.RW = g.W / n;
+  g.RH = g.H / n;
+  g.R = g.RW * g.RH;
+  g.NX = (g.W - 2 * n) / g.step + 1;
+  g.NY = (g.H - 2 * n) / g.step + 1;
+  g.ND = g.NX * g.NY;
+  g.R_pad = (g.R + kMfmaRangesPerWG - 1) / kMfmaRangesPerWG * kMfmaRangesPerWG;
+  g.NCB = (g.ND + 31) / 32;
+  g.NC_pad = g.NCB * 32;
+  g.P = ldexp(1.0, g.bits);
+  g.dlt = 2.0 * g.P / ldexp(1.0, g.ob);
+  g.S = ldexp(1.0, g.sb - 1);
+  g.escale = ldexp(1.0, 2 * g.sb + 2);
+  const int ebits = residual_bits(g);
+  g.cbits = 64 - ebits;
+  const long long ncand = 8ll * g.ND;
+  if (g.cbits < 1 || g.cbits > 62 || ncand > (1ll << g.cbits))
+    return fail(FIC_E_UNSUPPORTED,
+                "%lld candidates exceed the %d index bits of the search key",
+                ncand, g.cbits);
+  // sweep order: a golden-ratio stride through the domain grid, coprime to ND
+  long long st = llround(0.6180339887498949 * g.ND);
+  if (st < 1) st = 1;
+  while (gcd_ll(st, g.ND) != 1) ++st;
+  g.dom_stride = (int)st;
+  return FIC_OK;
+}
+
+EncLayout enc_layout(const Geo &g) {
+  EncLayout L;
+  const size_t planes = g.bits == 12 ? 2 : 1;
+  size_t o = 0;
+  L.off_bop = o;      o = align256(o + planes * (size_t)g.NC_pad * g.K * 2);
+  L.off_aop = o;      o = align256(o + planes * (size_t)g.R_pad * 8 * g.K * 2);
+  L.off_col_dom = o;  o = align256(o + (size_t)g.NC_pad * 4);
+  L.off_col_sa = o;   o = align256(o + (size_t)g.NC_pad * 4);
+  L.off_col_dp = o;   o = align256(o + (size_t)g.NC_pad * 4);
+  L.off_col_saa = o;  o = align256(o + (size_t)g.NC_pad * 8);
+  L.off_rng_sb = o;   o = align256(o + (size_t)g.R_pad * 8);
+  L.off_rng_sbb = o;  o = align256(o + (size_t)g.R_pad * 8);
+  L.off_best = o;     o = align256(o + (size_t)g.R_pad * 8);
+  L.off_flat = o;     o = align256(o + 4);
+  L.total = o;
+  return L;
+}
+
+EncBufs enc_bufs(const EncLayout &L, void *ws) {
+  char *w = (char *)ws;
+  EncBufs b;
+  b.bop = (_Float16 *)(w + L.off_bop);
+  b.aop = (_Float16 *)(w + L.off_aop);
+  b.col_dom = (int32_t *)(w + L.off_col_dom);
+  b.col_sa = (float *)(w + L.off_col_sa);
+  b.col_dp = (float *)(w + L.off_col_dp);
+  b.col_saa = (double *)(w + L.off_col_saa);
+  b.rng_sb = (double *)(w + L.off_rng_sb);
+  b.rng_sbb = (double *)(w + L.off_rng_sbb);
+  b.best = (unsigned long long *)(w + L.off_best);
+  b.flat_first = (int32_t *)(w + L.off_flat);
+  return b;
+}
+
+int default_chunks(const Geo &g) {
+  const int row_groups = g.R_pad / kMfmaRangesPerWG;
+  int c = (2048 + row_groups - 1) / row_groups;
+  if (c > g.NCB) c = g.NCB;
+  if (c < 1) c = 1;
+  return c;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+  return fail(FIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Phase timing for benchmarks: a pool of events, four per timed call.
+constexpr int kTimedCalls = 256;
+struct Timing {
+  bool on = false;
+  bool created = false;
+  int calls = 0;
+  hipEvent_t ev[4 * kTimedCalls];
+} g_timing;
+
+void timing_mark(int phase, hipStream_t s) {
+  if (!g_timing.on) return;
+  const int slot = g_timing.calls % kTimedCalls;
+  hipEventRecord(g_timing.ev[4 * slot + phase], s);
+}
+
+}  // namespace
+}  // namespace fic
+
+using namespace fic;
+
+extern "C" {
+
+int fic_query(const fic_params *p, int64_t *n_ranges, int64_t *n_domains,
+              size_t *encode_ws_bytes, size_t *backward_ws_bytes) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (n_ranges) *n_ranges = g.R;
+  if (n_domains) *n_domains = g.ND;
+  if (encode_ws_bytes) *encode_ws_bytes = enc_layout(g).total;
+  if (backward_ws_bytes) *backward_ws_bytes = decode_backward_ws_bytes(g);
+  return ok();
+}
+
+int fic_encode(const fic_params *p, const void *image, fic_codes out,
+               void *workspace, size_t ws_bytes, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/true);
+  if (st) return st;
+  if (!image || !workspace || !out.domain || !out.iso || !out.s_idx ||
+      !out.o_idx || !out.err)
+    return fail(FIC_E_INVALID, "null image, workspace or code pointer");
+  if (((uintptr_t)workspace) & 255)
+    return fail(FIC_E_INVALID, "workspace is not 256-byte aligned");
+  const EncLayout L = enc_layout(g);
+  if (ws_bytes < L.total)
+    return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                L.total);
+  const EncBufs b = enc_bufs(L, workspace);
+  hipStream_t s = (hipStream_t)stream;
+  timing_mark(0, s);
+  hipError_t e = launch_prep(g, image, b, s);
+  if (e != hipSuccess) return hip_fail(e, "prep");
+  timing_mark(1, s);
+  const int chunks = default_chunks(g);
+  e = (p->method == FIC_METHOD_DIRECT) ? launch_search_direct(g, b, chunks, s)
+                                       : launch_search_mfma(g, b, chunks, s);
+  if (e != hipSuccess) return hip_fail(e, "search");
+  timing_mark(2, s);
+  e = launch_finalize(g, image, b, out, s);
+  if (e != hipSuccess) return hip_fail(e, "finalize");
+  timing_mark(3, s);
+  if (g_timing.on) ++g_timing.calls;
+  return ok();
+}
+
+int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
+               const float *s, const float *o, int32_t iters, float x0,
+               float *traj, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !traj)
+    return fail(FIC_E_INVALID, "null code or trajectory pointer");
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  hipError_t e = launch_decode(g, domain, iso, s, o, iters, x0, traj,
+                               (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode");
+  return ok();
+}
+
+int fic_decode_backward(const fic_params *p, const int32_t *domain,
+                        const uint8_t *iso, const float *s, const float *o,
+                        int32_t iters, const float *traj, const float *grad_xT,
+                        float *grad_s, float *grad_o, void *workspace,
+                        size_t ws_bytes, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !traj || !grad_xT || !grad_s || !grad_o ||
+      !workspace)
+    return fail(FIC_E_INVALID, "null pointer argument");
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  if (((uintptr_t)workspace) & 255)
+    return fail(FIC_E_INVALID, "workspace is not 256-byte aligned");
+  const size_t need = decode_backward_ws_bytes(g);
+  if (ws_bytes < need)
+    return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                need);
+  hipError_t e = launch_decode_backward(g, domain, iso, s, o, iters, traj,
+                                        grad_xT, grad_s, grad_o, workspace,
+                                        (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_backward");
+  return ok();
+}
+
+int fic_timing_begin(void) {
+  if (!g_timing.created) {
+    for (int i = 0; i < 4 * kTimedCalls; ++i) {
+      hipError_t e = hipEventCreate(&g_timing.ev[i]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    }
+    g_timing.created = true;
+  }
+  g_timing.on = true;
+  g_timing.calls = 0;
+  return ok();
+}
+
+int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_search,
+                   double *ms_finalize) {
+  if (!g_timing.on) return fail(FIC_E_INVALID, "timing was not begun");
+  g_timing.on = false;
+  const int n = g_timing.calls < kTimedCalls ? g_timing.calls : kTimedCalls;
+  double acc[3] = {0, 0, 0};
+  for (int c = 0; c < n; ++c) {
+    hipError_t e = hipEventSynchronize(g_timing.ev[4 * c + 3]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    for (int ph = 0; ph < 3; ++ph) {
+      float ms = 0.0f;
+      e = hipEventElapsedTime(&ms, g_timing.ev[4 * c + ph],
+                              g_timing.ev[4 * c + ph + 1]);
+      if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+      acc[ph] += ms;
+    }
+  }
+  if (n_calls) *n_calls = n;
+  if (ms_prep) *ms_prep = acc[0];
+  if (ms_search) *ms_search = acc[1];
+  if (ms_finalize) *ms_finalize = acc[2];
+  return ok();
+}
+
+const char *fic_status_string(int status) {
+  switch (status) {
+    case FIC_OK: return "ok";
+    case FIC_E_INVALID: return "invalid argument";
+    case FIC_E_UNSUPPORTED: return "unsupported parameters";
+    case FIC_E_WORKSPACE: return "workspace too small";
+    case FIC_E_HIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char *fic_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

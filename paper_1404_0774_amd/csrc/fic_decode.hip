@@ -1,0 +1,287 @@
+// fic_decode.hip -- iterating the partitioned IFS map (eq. 6) and its
+// reverse-mode derivative with respect to the contrast s and offset o.
+//
+// Forward: one launch per iteration, one thread per output pixel:
+//   x_{t+1}[p] = s_r * ((x00 + x01) + (x10 + x11)) * 0.25 + o_r
+// where p is pixel (i, j) of range r and x.. is the 2x2 cell sigma_k(i, j)
+// of the range's domain in x_t.
+//
+// Reverse: with g_{t+1} = dL/dx_{t+1} and u_t[p] the cell mean read by p,
+//   dL/ds_r += sum_{p in r} g_{t+1}[p] u_t[p],  dL/do_r += sum_{p in r} g_{t+1}[p]
+//   g_t[q]   = sum over range pixels p whose cell contains q of s_r g_{t+1}[p] / 4.
+// The last sum is a gather, never a float atomic: a compact table lists, for
+// every domain, the ranges that use it (sorted by range index), and each
+// pixel q visits the domains covering it in increasing order.  Every sum has
+// a fixed order, so the result is bitwise reproducible.
+#include "fic_device.h"
+
+namespace fic {
+
+namespace {
+
+// Code entries come from the caller: keep every access inside the image even
+// for out-of-range values (those ranges then decode from the clamped domain).
+__device__ __forceinline__ int clamp_dom(int d, int nd) {
+  return d < 0 ? 0 : (d >= nd ? nd - 1 : d);
+}
+
+template <int N>
+__global__ void k_decode_step(Geo g, const int32_t *domain, const uint8_t *iso,
+                              const float *s, const float *o, const float *x,
+                              float *y) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= g.H * g.W) return;
+  const int py = p / g.W, px = p % g.W;
+  const int ry = py / N, rx = px / N, i = py % N, j = px % N;
+  const int r = ry * g.RW + rx;
+  const int d = clamp_dom(domain[r], g.ND);
+  int si, sj;
+  sigma(iso[r], i, j, N - 1, si, sj);
+  const int cy = (d / g.NX) * g.step + 2 * si, cx = (d % g.NX) * g.step + 2 * sj;
+  const float *c = x + (size_t)cy * g.W + cx;
+  const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
+  y[p] = fmaf(s[r], u, o[r]);
+}
+
+__global__ void k_fill_f32(float *p, long long n, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_i32n(int32_t *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// --- the domain -> ranges table (built once per call) ---------------------
+
+__global__ void k_count_domains(Geo g, const int32_t *domain, int32_t *cnt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < g.R) atomicAdd(&cnt[clamp_dom(domain[r], g.ND)], 1);
+}
+
+// Exclusive scan of cnt[0..n) into off[0..n]; one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int n,
+                                               int32_t *off) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int b0 = t * per, b1 = min(b0 + per, n);
+  int s = 0;
+  for (int i = b0; i < b1; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t ? part[t - 1] : 0;
+  for (int i = b0; i < b1; ++i) {
+    off[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+__global__ void k_fill_lists(Geo g, const int32_t *domain, const int32_t *off,
+                             int32_t *cursor, int32_t *list) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.R) return;
+  const int d = clamp_dom(domain[r], g.ND);
+  list[off[d] + atomicAdd(&cursor[d], 1)] = r;
+}
+
+// Order each domain's list by range index (insertion sort; lists are short
+// unless many ranges share one domain).
+__global__ void k_sort_lists(Geo g, const int32_t *off, int32_t *list) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= g.ND) return;
+  const int b0 = off[d], b1 = off[d + 1];
+  for (int i = b0 + 1; i < b1; ++i) {
+    const int v = list[i];
+    int j = i - 1;
+    while (j >= b0 && list[j] > v) {
+      list[j + 1] = list[j];
+      --j;
+    }
+    list[j + 1] = v;
+  }
+}
+
+// --- reverse steps ----------------------------------------------------------
+
+// One thread per range: accumulate dL/ds and dL/do of step t (first = true
+// overwrites the outputs).
+template <int N>
+__global__ void k_grad_so(Geo g, const int32_t *domain, const uint8_t *iso,
+                          const float *x, const float *gnext, float *grad_s,
+                          float *grad_o, int first) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= g.R) return;
+  const int ry = r / g.RW, rx = r % g.RW;
+  const int d = clamp_dom(domain[r], g.ND), k = iso[r];
+  const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
+  float as = 0.0f, ao = 0.0f;
+  for (int i = 0; i < N; ++i)
+    for (int j = 0; j < N; ++j) {
+      int si, sj;
+      sigma(k, i, j, N - 1, si, sj);
+      const float *c = x + (size_t)(Y + 2 * si) * g.W + X + 2 * sj;
+      const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
+      const float gv = gnext[(size_t)(ry * N + i) * g.W + rx * N + j];
+      as = fmaf(gv, u, as);
+      ao += gv;
+    }
+  if (first) {
+    grad_s[r] = as;
+    grad_o[r] = ao;
+  } else {
+    grad_s[r] += as;
+    grad_o[r] += ao;
+  }
+}
+
+// Inverse of sigma_k: the output pixel (i, j) that reads cell (ci, cj).
+__device__ __forceinline__ void sigma_inv(int k, int ci, int cj, int m, int &i,
+                                          int &j) {
+  switch (k & 7) {
+    case 0: i = ci;     j = cj;     break;
+    case 1: i = m - cj; j = ci;     break;
+    case 2: i = m - ci; j = m - cj; break;
+    case 3: i = cj;     j = m - ci; break;
+    case 4: i = ci;     j = m - cj; break;
+    case 5: i = cj;     j = ci;     break;
+    case 6: i = m - ci; j = cj;     break;
+    default: i = m - cj; j = m - ci; break;
+  }
+}
+
+// One thread per pixel q: g_t[q] from g_{t+1}.
+template <int N>
+__global__ void k_grad_x(Geo g, const uint8_t *iso, const float *s,
+                         const int32_t *off, const int32_t *list,
+                         const float *gnext, float *gout) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= g.H * g.W) return;
+  const int qy = q / g.W, qx = q % g.W;
+  const int span = 2 * N;
+  int dy0 = qy - span + 1;
+  dy0 = dy0 <= 0 ? 0 : (dy0 + g.step - 1) / g.step;
+  int dx0 = qx - span + 1;
+  dx0 = dx0 <= 0 ? 0 : (dx0 + g.step - 1) / g.step;
+  const int dy1 = min(qy / g.step, g.NY - 1), dx1 = min(qx / g.step, g.NX - 1);
+  float acc = 0.0f;
+  for (int dy = dy0; dy <= dy1; ++dy)
+    for (int dx = dx0; dx <= dx1; ++dx) {
+      const int d = dy * g.NX + dx;
+      const int b0 = off[d], b1 = off[d + 1];
+      if (b0 == b1) continue;
+      const int ci = (qy - dy * g.step) >> 1, cj = (qx - dx * g.step) >> 1;
+      for (int e = b0; e < b1; ++e) {
+        const int r = list[e];
+        int i, j;
+        sigma_inv(iso[r], ci, cj, N - 1, i, j);
+        const int ry = r / g.RW, rx = r % g.RW;
+        const float gv = gnext[(size_t)(ry * N + i) * g.W + rx * N + j];
+        acc = fmaf(s[r] * 0.25f, gv, acc);
+      }
+    }
+  gout[q] = acc;
+}
+
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+template <int N>
+hipError_t backward_impl(const Geo &g, const int32_t *domain,
+                         const uint8_t *iso, const float *s, int iters,
+                         const float *traj, const float *grad_xT,
+                         float *grad_s, float *grad_o, void *ws,
+                         hipStream_t st) {
+  const size_t HW = (size_t)g.H * g.W;
+  char *w = (char *)ws;
+  int32_t *cnt = (int32_t *)w;      w += a256(sizeof(int32_t) * (g.ND + 1));
+  int32_t *cursor = (int32_t *)w;   w += a256(sizeof(int32_t) * (g.ND + 1));
+  int32_t *off = (int32_t *)w;      w += a256(sizeof(int32_t) * (g.ND + 1));
+  int32_t *list = (int32_t *)w;     w += a256(sizeof(int32_t) * g.R);
+  float *gbuf0 = (float *)w;        w += a256(sizeof(float) * HW);
+  float *gbuf1 = (float *)w;
+  const int bs = 256;
+  if (iters == 0) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
+                       grad_s, (long long)g.R, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
+                       grad_o, (long long)g.R, 0.0f);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(k_fill_i32n, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0,
+                     st, cnt, g.ND + 1, 0);
+  hipLaunchKernelGGL(k_fill_i32n, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0,
+                     st, cursor, g.ND + 1, 0);
+  hipLaunchKernelGGL(k_count_domains, dim3((g.R + bs - 1) / bs), dim3(bs), 0,
+                     st, g, domain, cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, g.ND, off);
+  hipLaunchKernelGGL(k_fill_lists, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
+                     g, domain, off, cursor, list);
+  hipLaunchKernelGGL(k_sort_lists, dim3((g.ND + bs - 1) / bs), dim3(bs), 0, st,
+                     g, off, list);
+  const float *gnext = grad_xT;
+  float *bufs[2] = {gbuf0, gbuf1};
+  for (int t = iters - 1; t >= 0; --t) {
+    const float *x = traj + (size_t)t * HW;
+    hipLaunchKernelGGL((k_grad_so<N>), dim3((g.R + bs - 1) / bs), dim3(bs), 0,
+                       st, g, domain, iso, x, gnext, grad_s, grad_o,
+                       t == iters - 1 ? 1 : 0);
+    if (t > 0) {
+      float *gout = bufs[t & 1];
+      hipLaunchKernelGGL((k_grad_x<N>), dim3((HW + bs - 1) / bs), dim3(bs), 0,
+                         st, g, iso, s, off, list, gnext, gout);
+      gnext = gout;
+    }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+size_t decode_backward_ws_bytes(const Geo &g) {
+  const size_t HW = (size_t)g.H * g.W;
+  return 3 * a256(sizeof(int32_t) * (g.ND + 1)) + a256(sizeof(int32_t) * g.R) +
+         2 * a256(sizeof(float) * HW);
+}
+
+hipError_t launch_decode(const Geo &g, const int32_t *domain,
+                         const uint8_t *iso, const float *s, const float *o,
+                         int iters, float x0, float *traj, hipStream_t st) {
+  const long long HW = (long long)g.H * g.W;
+  const int bs = 256;
+  const dim3 grid((unsigned)((HW + bs - 1) / bs));
+  hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
+  for (int t = 0; t < iters; ++t) {
+    const float *x = traj + (size_t)t * HW;
+    float *y = traj + (size_t)(t + 1) * HW;
+    if (g.n == 8)
+      hipLaunchKernelGGL(k_decode_step<8>, grid, dim3(bs), 0, st, g, domain,
+                         iso, s, o, x, y);
+    else
+      hipLaunchKernelGGL(k_decode_step<4>, grid, dim3(bs), 0, st, g, domain,
+                         iso, s, o, x, y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
+                                  const uint8_t *iso, const float *s,
+                                  const float *o, int iters, const float *traj,
+                                  const float *grad_xT, float *grad_s,
+                                  float *grad_o, void *ws, hipStream_t st) {
+  (void)o;
+  if (g.n == 8)
+    return backward_impl<8>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
+                            grad_o, ws, st);
+  return backward_impl<4>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
+                          grad_o, ws, st);
+}
+
+}  // namespace fic

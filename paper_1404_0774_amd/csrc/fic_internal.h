@@ -1,0 +1,80 @@
+// fic_internal.h -- host/device shared definitions of libfic (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fic.h"
+
+namespace fic {
+
+// Geometry and quantisation constants of one encode, passed by value to
+// every kernel.
+struct Geo {
+  int H, W;          // image size
+  int bits;          // 8 or 12
+  int n, K;          // range side, pixels per range (n*n)
+  int step;          // domain grid spacing
+  int sb, ob;        // contrast / offset bits
+  int RW, RH, R;     // ranges per row, per column, total
+  int NX, NY, ND;    // domain grid
+  int R_pad;         // ranges rounded up to the search tile
+  int NCB;           // column blocks of 32 domains
+  int NC_pad;        // NCB * 32
+  int cbits;         // low bits of the search key that hold the candidate
+  int dom_stride;    // sweep order: column c holds domain (c * dom_stride) % ND
+  double escale;     // 2^(2 sb + 2): residual * escale is an integer
+  double P;          // 2^bits
+  double dlt;        // offset step
+  double S;          // 2^(sb - 1)
+};
+
+// Device buffers carved out of the caller's workspace.
+struct EncBufs {
+  _Float16 *bop;     // [NC_pad][K] contracted domain cell sums, sweep order
+                     //   (12-bit: two planes, hi then lo, each [NC_pad][K])
+  _Float16 *aop;     // [R_pad * 8][K] range pixels permuted per transform
+                     //   (12-bit: two planes)
+  int32_t *col_dom;  // [NC_pad] domain index of a column, -1 for padding
+  float *col_sa;     // [NC_pad] sum of cell sums of the column's domain
+  float *col_dp;     // [NC_pad] prune denominator: D' rounded down;
+                     //   0 for the first flat domain, +inf for later flat
+                     //   domains and padding
+  double *col_saa;   // [NC_pad] sum of squared cell sums
+  double *rng_sb;    // [R_pad] sum of range pixels
+  double *rng_sbb;   // [R_pad] sum of squared range pixels
+  unsigned long long *best; // [R_pad] packed (residual, candidate) keys
+  int32_t *flat_first;      // [1] smallest flat domain index (ND if none)
+};
+
+// Byte layout of the encode workspace.
+struct EncLayout {
+  size_t off_bop, off_aop, off_col_dom, off_col_sa, off_col_dp, off_col_saa;
+  size_t off_rng_sb, off_rng_sbb, off_best, off_flat;
+  size_t total;
+};
+
+// Launchers (one per kernel file).  All return hipError_t of the launch.
+hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
+                       hipStream_t st);
+hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
+                              hipStream_t st);
+hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
+                                hipStream_t st);
+hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
+                           fic_codes out, hipStream_t st);
+hipError_t launch_decode(const Geo &g, const int32_t *domain,
+                         const uint8_t *iso, const float *s, const float *o,
+                         int iters, float x0, float *traj, hipStream_t st);
+hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
+                                  const uint8_t *iso, const float *s,
+                                  const float *o, int iters, const float *traj,
+                                  const float *grad_xT, float *grad_s,
+                                  float *grad_o, void *ws, hipStream_t st);
+size_t decode_backward_ws_bytes(const Geo &g);
+
+// Search tile: ranges per workgroup of the matrix-core search.
+constexpr int kMfmaRangesPerWG = 32;  // 4 waves x 2 row blocks x 4 ranges
+constexpr int kDirectRangesPerWG = 32;
+
+}  // namespace fic

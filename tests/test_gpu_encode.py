@@ -1,0 +1,116 @@
+"""GPU parity of the range-domain search (both kernels) against the CPU
+oracle: identical codes and residuals, element by element."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1404_0774_amd as F
+from oracle import oracle as O
+from fic_inputs import gen_image
+from planted import planted_image, PLANTS_64_N8
+
+pytestmark = pytest.mark.gpu
+KEYS = ("domain", "iso", "s_idx", "o_idx", "err")
+METHODS = [F.METHOD_MFMA, F.METHOD_DIRECT]
+
+
+def gpu_encode(img, n, step, bits, method, ranges=None):
+    H, W = img.shape
+    p = F.Params(H, W, bits, n, step, method=method)
+    dt = torch.uint8 if bits == 8 else torch.int16
+    t = torch.from_numpy(np.ascontiguousarray(img).astype(np.uint8 if bits == 8 else np.int16)).to("cuda")
+    out = F.encode(t, p)
+    torch.cuda.synchronize()
+    res = {k: out[k].cpu().numpy() for k in KEYS}
+    if ranges is not None:
+        res = {k: v[ranges] for k, v in res.items()}
+    return res
+
+
+def assert_same(gpu, ora, label=""):
+    for k in KEYS:
+        if not np.array_equal(gpu[k], ora[k]):
+            bad = np.nonzero(gpu[k] != ora[k])[0]
+            i = bad[0]
+            raise AssertionError(f"{label} {k}: {len(bad)} mismatches, first at {i}: "
+                                 + ", ".join(f"{q}={gpu[q][i]}/{ora[q][i]}" for q in KEYS))
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_plain_64x64_config(method):
+    # 64x64 u8, 4x4 ranges, 8x8 domains at stride 4: the plain full-search setup
+    img = gen_image(64, 64, 8, 1)
+    assert_same(gpu_encode(img, 4, 4, 8, method), O.encode(img, 4, 4), "plain64")
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("H,W,n,step,seed", [
+    (96, 80, 4, 2, 11),     # 480 ranges (ragged tile), 1665 domains (ragged block)
+    (128, 96, 8, 4, 12),    # n = 8, 192 ranges, 609 domains
+    (40, 56, 4, 3, 13),     # odd stride
+    (8, 8, 4, 4, 14),       # smallest image: 4 ranges, one domain
+    (16, 64, 8, 1, 15),     # one domain row, stride 1
+])
+def test_parity_small_images(method, H, W, n, step, seed):
+    img = gen_image(H, W, 8, seed)
+    assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), f"{H}x{W}")
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("kind", ["zeros", "const", "max", "checker", "noise", "levels"])
+def test_parity_degenerate_images(method, kind):
+    H = W = 48
+    rng = np.random.default_rng(5)
+    img = {"zeros": np.zeros((H, W)), "const": np.full((H, W), 101),
+           "max": np.full((H, W), 255),
+           "checker": (np.indices((H, W)).sum(0) % 2) * 255,
+           "noise": rng.integers(0, 256, (H, W)),
+           "levels": rng.integers(0, 3, (H, W)) * 85}[kind].astype(np.uint8)
+    for (n, step) in [(4, 4), (8, 2)]:
+        assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), kind)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_planted_codes(method):
+    H = W = 64
+    n, step = 8, 4
+    plants = PLANTS_64_N8
+    img = planted_image(H, W, n, step, 8, 23, plants).astype(np.uint8)
+    gpu = gpu_encode(img, n, step, 8, method)
+    assert_same(gpu, O.encode(img, n, step), "planted")
+    nx = (W - 2 * n) // step + 1
+    for (r, (dy, dx), k, s, o) in plants:
+        assert gpu["err"][r] == 0.0 and gpu["domain"][r] == dy * nx + dx and gpu["iso"][r] == k
+
+
+def _sample_ranges(R, seed, count):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([[0, R - 1], np.arange(0, R, R // 32), rng.integers(0, R, count)]))
+
+
+def test_u8_512_full_size_sampled_and_methods_agree():
+    # 512x512 u8, 8x8 ranges, 16x16 domains at stride 4 (4096 x 125,000 candidates)
+    img = gen_image(512, 512, 8, 2)
+    mf = gpu_encode(img, 8, 4, 8, F.METHOD_MFMA)
+    di = gpu_encode(img, 8, 4, 8, F.METHOD_DIRECT)
+    assert_same(mf, di, "mfma-vs-direct")
+    rs = _sample_ranges(4096, 0, 96)
+    ora = O.encode_ranges(img, 8, 4, rs)
+    assert_same({k: mf[k][rs] for k in KEYS}, ora, "u8_512 sampled")
+
+
+def test_decode_workload_encode_sampled():
+    # 256x256 u8, 4x4 ranges, 8x8 domains at stride 4
+    img = gen_image(256, 256, 8, 5)
+    mf = gpu_encode(img, 4, 4, 8, F.METHOD_MFMA)
+    rs = _sample_ranges(4096, 1, 64)
+    ora = O.encode(img, 4, 4)
+    assert_same({k: mf[k][rs] for k in KEYS}, {k: ora[k][rs] for k in KEYS}, "decode256")
+    assert_same(mf, ora, "decode256 full")
+
+
+def test_deterministic_repeat():
+    img = gen_image(128, 128, 8, 9)
+    a = gpu_encode(img, 8, 2, 8, F.METHOD_MFMA)
+    for _ in range(3):
+        assert_same(gpu_encode(img, 8, 2, 8, F.METHOD_MFMA), a, "repeat")

@@ -7,7 +7,7 @@ import pytest
 from oracle import oracle as O
 from fic_inputs import gen_image
 from brute import brute_encode
-from planted import planted_image
+from planted import planted_image, PLANTS_64_N8
 
 KEYS = ("domain", "iso", "s_idx", "o_idx", "err")
 
@@ -57,6 +57,15 @@ def test_planted_codes_recovered(bits):
         assert ora["s_idx"][r] == int((s + 1) * 16) and ora["o_idx"][r] == int((o + P) / dlt)
 
 
+def test_planted_codes_n8():
+    img = planted_image(64, 64, 8, 4, 8, 23, PLANTS_64_N8)
+    ora = O.encode(img, 8, 4)
+    for (r, (dy, dx), k, s, o) in PLANTS_64_N8:
+        assert ora["err"][r] == 0.0
+        assert ora["domain"][r] == dy * 13 + dx and ora["iso"][r] == k
+        assert ora["s_idx"][r] == int((s + 1) * 16) and ora["o_idx"][r] == int((o + 256) / 4)
+
+
 @pytest.mark.parametrize("bits,n,step", [(8, 4, 4), (8, 4, 2), (12, 4, 4)])
 def test_min_error_invariant_under_transpose(bits, n, step):
     # the transform set is closed under transposition and the grid is symmetric,
@@ -90,6 +99,15 @@ def test_range_subset_equals_full():
     part = O.encode(img, 4, 4, r_begin=100, r_end=140)
     for k in KEYS:
         np.testing.assert_array_equal(full[k][100:140], part[k])
+
+
+def test_range_list_equals_full():
+    img = gen_image(64, 64, 8, 1)
+    full = O.encode(img, 4, 4)
+    rs = np.array([255, 0, 17, 17, 128])
+    part = O.encode_ranges(img, 4, 4, rs)
+    for k in KEYS:
+        np.testing.assert_array_equal(full[k][rs], part[k])
 
 
 def test_invalid_parameters_rejected():
