@@ -152,9 +152,11 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   return b;
 }
 
+// Column chunks per row group: about two workgroups per compute unit
+// (256 CUs) in one launch.
 int default_chunks(const Geo &g) {
   const int row_groups = g.R_pad / kMfmaRangesPerWG;
-  int c = (2048 + row_groups - 1) / row_groups;
+  int c = (512 + row_groups - 1) / row_groups;
   if (c > g.NCB) c = g.NCB;
   if (c < 1) c = 1;
   return c;

@@ -74,7 +74,7 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
 size_t decode_backward_ws_bytes(const Geo &g);
 
 // Search tile: ranges per workgroup of the matrix-core search.
-constexpr int kMfmaRangesPerWG = 32;  // 4 waves x 2 row blocks x 4 ranges
+constexpr int kMfmaRangesPerWG = 64;  // 4 waves x 4 row blocks x 4 ranges
 constexpr int kDirectRangesPerWG = 32;
 
 }  // namespace fic
