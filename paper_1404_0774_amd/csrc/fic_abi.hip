@@ -221,8 +221,13 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   if (e != hipSuccess) return hip_fail(e, "prep");
   timing_mark(1, s);
   const int chunks = default_chunks(g);
-  e = (p->method == FIC_METHOD_DIRECT) ? launch_search_direct(g, b, chunks, s)
-                                       : launch_search_mfma(g, b, chunks, s);
+  // the first column block is fitted densely to seed every range's bound
+  const int seeded = g.NCB >= 16 ? 1 : 0;
+  e = launch_seed_dense(g, b, seeded, s);
+  if (e != hipSuccess) return hip_fail(e, "seed");
+  e = (p->method == FIC_METHOD_DIRECT)
+          ? launch_search_direct(g, b, chunks, seeded, s)
+          : launch_search_mfma(g, b, chunks, seeded, s);
   if (e != hipSuccess) return hip_fail(e, "search");
   timing_mark(2, s);
   e = launch_finalize(g, image, b, out, s);

@@ -57,10 +57,12 @@ struct EncLayout {
 // Launchers (one per kernel file).  All return hipError_t of the launch.
 hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
                        hipStream_t st);
+hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
+                             hipStream_t st);
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
-                              hipStream_t st);
+                              int seeded_blocks, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                hipStream_t st);
+                                int seeded_blocks, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
                            fic_codes out, hipStream_t st);
 hipError_t launch_decode(const Geo &g, const int32_t *domain,

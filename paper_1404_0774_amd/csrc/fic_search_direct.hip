@@ -33,6 +33,7 @@ __device__ __noinline__ float eval_survivor_d(float Gf, int col, int r, int k,
 // t / 8 of the tile, columns 4 (t mod 8) .. +3 of each 32-column block.
 template <int K>
 __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
+                                                          int cb_begin,
                                                           int cb_per_chunk) {
   __shared__ __attribute__((aligned(16))) float As[K][256];  // [p][8 rs + k]
   __shared__ __attribute__((aligned(16))) float Bs[K][32];   // [p][column]
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
   const float bbar = (float)(Sb / K);
   float wp = prune_weight(key_err(b.best[r], g), Sb, Sbb, g);
 
-  const int cb0 = blockIdx.x * cb_per_chunk;
+  const int cb0 = cb_begin + blockIdx.x * cb_per_chunk;
   const int cb1 = min(cb0 + cb_per_chunk, g.NCB);
   for (int cb = cb0; cb < cb1; ++cb) {
     __syncthreads();
@@ -110,17 +111,19 @@ __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
 }  // namespace
 
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                hipStream_t st) {
-  const int cbpc = (g.NCB + chunks - 1) / chunks;
-  const int nchunks = (g.NCB + cbpc - 1) / cbpc;
+                                int seeded_blocks, hipStream_t st) {
+  const int rest = g.NCB - seeded_blocks;
+  if (rest <= 0) return hipSuccess;
+  const int cbpc = (rest + chunks - 1) / chunks;
+  const int nchunks = (rest + cbpc - 1) / cbpc;
   dim3 grid(nchunks, g.R_pad / kDirectRangesPerWG);
   if (g.bits != 8) return hipErrorInvalidValue;
   if (g.K == 64)
     hipLaunchKernelGGL(k_search_direct_u8<64>, grid, dim3(256), 0, st, g, b,
-                       cbpc);
+                       seeded_blocks, cbpc);
   else
     hipLaunchKernelGGL(k_search_direct_u8<16>, grid, dim3(256), 0, st, g, b,
-                       cbpc);
+                       seeded_blocks, cbpc);
   return hipGetLastError();
 }
 
