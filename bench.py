@@ -1,10 +1,13 @@
-"""Benchmark of the range-domain search on one MI355X.
+"""Benchmark of the PIFS range-domain search on one MI355X.
 
 A step is one fic_encode of a 512x512 8-bit synthetic slice with 8x8 ranges
 and 16x16 domains at stride 4 (4096 ranges x 15,625 domains x 8 transforms =
-5.12e8 candidate comparisons): operand preparation, the matrix-core search
-with its fused fit/quantise/residual epilogue, and code extraction, with the
-image already resident in HBM.  Prints one JSON line.
+5.12e8 candidate comparisons): operand preparation, the dense seed block, the
+matrix-core search with its fused fit/quantise/residual epilogue, and code
+extraction, with the image already resident in HBM.  Secondary fields cover
+the plain (direct) kernel on the same slice, the 512x512 12-bit slice at
+stride 2, and the 256x256 decode workload (decoder, adjoint, refinement).
+Prints one JSON line.
 """
 import argparse
 import json
@@ -25,13 +28,35 @@ def psnr(x, ref, peak):
     return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
 
 
+def time_encode(F, torch, timg, p, ws, steps, warmup):
+    """Mean ms per fic_encode and per phase (library HIP events on the stream)."""
+    dev = timg.device
+    for _ in range(warmup):
+        out = F.encode(timg, p, workspace=ws)
+    torch.cuda.synchronize(dev)
+    F.timing_begin()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        out = F.encode(timg, p, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize(dev)
+    ncalls, ms_prep, ms_search, ms_fin = F.timing_end()
+    return out, e0.elapsed_time(e1) / steps, ms_prep / ncalls, ms_search / ncalls, ms_fin / ncalls
+
+
+def codes_np(out):
+    return {k: out[k].cpu().numpy() for k in ("domain", "iso", "s_idx", "o_idx", "err")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=512, help="ranges timed on the CPU oracle")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--cpu-sample", type=int, default=4096, help="ranges timed on the CPU oracle")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -45,6 +70,9 @@ def main():
     from fic_inputs import gen_image
 
     dev = torch.device("cuda:0")
+    t_wall0 = time.time()
+
+    # ---- headline: 512x512 u8, n = 8, stride 4 -------------------------------
     H = W = 512
     n, step, bits = 8, 4, 8
     img = gen_image(H, W, bits, 2)
@@ -52,42 +80,22 @@ def main():
     p = F.Params(H, W, bits, n, step, method=F.METHOD_MFMA)
     R, ND, ws_bytes, _ = F.query(p)
     cand = 8 * R * ND
-    K = n * n
-    flops = 2.0 * K * cand            # MFMA FLOPs of the search contraction
+    flops = 2.0 * n * n * cand            # MFMA FLOPs of the search contraction
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
 
-    def run(method, steps):
-        p.method = method
-        for _ in range(args.warmup):
-            out = F.encode(timg, p, workspace=ws)
-        torch.cuda.synchronize(dev)
-        F.timing_begin()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            out = F.encode(timg, p, workspace=ws)
-        e1.record()
-        torch.cuda.synchronize(dev)
-        ncalls, ms_prep, ms_search, ms_fin = F.timing_end()
-        total = e0.elapsed_time(e1)
-        return out, total / steps, ms_prep / ncalls, ms_search / ncalls, ms_fin / ncalls
-
-    t_wall0 = time.time()
-    out_m, ms_m, prep_m, search_m, fin_m = run(F.METHOD_MFMA, args.steps)
-    codes_m = {k: out_m[k].cpu().numpy() for k in ("domain", "iso", "s_idx", "o_idx", "err")}
+    out_m, ms_m, prep_m, search_m, fin_m = time_encode(F, torch, timg, p, ws, args.steps, args.warmup)
+    codes_m = codes_np(out_m)
+    p.method = F.METHOD_DIRECT
     dsteps = max(2, args.steps // 4)
-    out_d, ms_d, prep_d, search_d, fin_d = run(F.METHOD_DIRECT, dsteps)
-    codes_d = {k: out_d[k].cpu().numpy() for k in ("domain", "iso", "s_idx", "o_idx", "err")}
+    out_d, ms_d, _, search_d, _ = time_encode(F, torch, timg, p, ws, dsteps, 1)
+    codes_d = codes_np(out_d)
     same = all(np.array_equal(codes_m[k], codes_d[k]) for k in codes_m)
 
-    # decode quality of the codes (12 iterations from mid-grey, FP32)
     p.method = F.METHOD_MFMA
     s, o = F.dequantize(out_m["s_idx"], out_m["o_idx"], p)
     traj = F.decode(out_m["domain"], out_m["iso"], s.contiguous(), o.contiguous(), p, 12, 128.0)
     x = traj[-1].double().cpu().numpy()
     ref = img.astype(np.float64)
-    ps_raw = psnr(x, ref, 255.0)
-    ps_q = psnr(np.clip(np.rint(x), 0, 255), ref, 255.0)
 
     value = cand / (ms_m / 1e3)
     achieved = flops / (search_m / 1e3)
@@ -109,14 +117,134 @@ def main():
         "phases_ms": {"prep": prep_m, "search": search_m, "finalize": fin_m},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK, "traffic": None,
-                     "kernel": "search (matrix-core contraction + fused epilogue)",
+                     "kernel": "search phase: dense seed block + matrix-core search",
                      "flop_per_launch": flops},
         "direct": {"value": cand / (ms_d / 1e3), "ms_per_step": ms_d, "search_ms": search_d,
                    "steps": dsteps},
         "mfma_over_direct": ms_d / ms_m,
         "codes_identical_mfma_direct": bool(same),
-        "decode_psnr_db": {"T": 12, "unclamped": ps_raw, "clamped_rounded": ps_q},
+        "decode_psnr_db": {"T": 12, "unclamped": psnr(x, ref, 255.0),
+                           "clamped_rounded": psnr(np.clip(np.rint(x), 0, 255), ref, 255.0)},
     }
+
+    if not args.no_extras:
+        # ---- 512x512 12-bit, n = 8, stride 2 ------------------------------------
+        img12 = gen_image(512, 512, 12, 3)
+        t12 = torch.from_numpy(img12.astype(np.int16)).to(dev)
+        p12 = F.Params(512, 512, 12, 8, 2, method=F.METHOD_MFMA)
+        R12, ND12, ws12b, _ = F.query(p12)
+        ws12 = torch.empty(ws12b + 256, dtype=torch.uint8, device=dev)
+        c12 = 8 * R12 * ND12
+        o12, ms12, pr12, se12, fi12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
+        p12.method = F.METHOD_DIRECT
+        o12d, ms12d, _, se12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
+        same12 = all(np.array_equal(a, b) for a, b in zip(codes_np(o12).values(), codes_np(o12d).values()))
+        result["ct12_512"] = {
+            "workload": "512x512 12-bit slice, 8x8 ranges, 16x16 domains stride 2",
+            "candidates": c12, "value": c12 / (ms12 / 1e3), "unit": "comparisons/s",
+            "ms_per_step": ms12, "phases_ms": {"prep": pr12, "search": se12, "finalize": fi12},
+            "mfma_frac": 2.0 * 4 * 64 * c12 / (se12 / 1e3) / MFMA_FP16_PEAK,
+            "direct_value": c12 / (ms12d / 1e3), "mfma_over_direct": ms12d / ms12,
+            "codes_identical_mfma_direct": bool(same12)}
+
+        # ---- 256x256 u8, n = 4, stride 4: encode, decode, adjoint, refine ---------
+        img5 = gen_image(256, 256, 8, 5)
+        t5 = torch.from_numpy(img5).to(dev)
+        p5 = F.Params(256, 256, 8, 4, 4, method=F.METHOD_MFMA)
+        R5, ND5, ws5b, bw5 = F.query(p5)
+        ws5 = torch.empty(ws5b + 256, dtype=torch.uint8, device=dev)
+        o5, ms5, _, _, _ = time_encode(F, torch, t5, p5, ws5, args.steps, 2)
+        s5, o5v = F.dequantize(o5["s_idx"], o5["o_idx"], p5)
+        s5, o5v = s5.contiguous(), o5v.contiguous()
+        T = 12
+        HW = 256 * 256
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            tr5 = F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T, 128.0)
+        torch.cuda.synchronize(dev)
+        e0.record()
+        for _ in range(20):
+            tr5 = F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T, 128.0)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        ms_dec = e0.elapsed_time(e1) / 20
+        gxt = (2.0 * (tr5[-1] - t5.float()) / HW).contiguous()
+        for _ in range(3):
+            F.decode_backward(o5["domain"], o5["iso"], s5, o5v, tr5, gxt, p5)
+        torch.cuda.synchronize(dev)
+        e0.record()
+        for _ in range(20):
+            F.decode_backward(o5["domain"], o5["iso"], s5, o5v, tr5, gxt, p5)
+        e1.record()
+        torch.cuda.synchronize(dev)
+        ms_bwd = e0.elapsed_time(e1) / 20
+        # algorithmic bytes: each iteration reads x_t and writes x_{t+1} once
+        # (4 B each per pixel) and reads the codes (13 B per range); the
+        # adjoint also reads the trajectory image and the domain->range table
+        dec_bytes = T * (2 * 4 * HW + 13 * R5)
+        bwd_bytes = T * (3 * 4 * HW + 13 * R5 + 4 * (ND5 + R5))
+        x0 = tr5[-1].double().cpu().numpy()
+        ref5 = img5.astype(np.float64)
+        sr, orf = s5.clone(), o5v.clone()
+        t0 = time.time()
+        loss = F.refine(o5["domain"], o5["iso"], sr, orf, t5, p5, iters=T, steps=50)
+        torch.cuda.synchronize(dev)
+        ms_ref = (time.time() - t0) * 1e3
+        xr = F.decode(o5["domain"], o5["iso"], sr, orf, p5, T, 128.0)[-1].double().cpu().numpy()
+        sq = torch.clamp(torch.floor((sr + 1.0) * 16 + 0.5), 0, 31)
+        oq = torch.clamp(torch.floor((orf + 256.0) / 4 + 0.5), 0, 127)
+        sqv, oqv = F.dequantize(sq.to(torch.uint8), oq.to(torch.uint8), p5)
+        xq = F.decode(o5["domain"], o5["iso"], sqv.contiguous(), oqv.contiguous(), p5, T, 128.0)[-1].double().cpu().numpy()
+        result["decode256"] = {
+            "workload": "256x256 uint8, 4x4 ranges, 8x8 domains stride 4; decoder T = 12 from 128",
+            "encode_value": 8 * R5 * ND5 / (ms5 / 1e3), "encode_ms": ms5,
+            "decode_ms": ms_dec, "decode_gbps": dec_bytes / (ms_dec / 1e3) / 1e9,
+            "decode_hbm_frac": dec_bytes / (ms_dec / 1e3) / HBM_PEAK,
+            "adjoint_ms": ms_bwd, "adjoint_gbps": bwd_bytes / (ms_bwd / 1e3) / 1e9,
+            "adjoint_hbm_frac": bwd_bytes / (ms_bwd / 1e3) / HBM_PEAK,
+            "psnr_db": psnr(x0, ref5, 255.0),
+            "refine": {"steps": 50, "lr_s": 5e-3, "lr_o": 0.5, "ms": ms_ref,
+                       "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
+                       "psnr_db": psnr(xr, ref5, 255.0), "psnr_requantised_db": psnr(xq, ref5, 255.0)}}
+
+        # ---- 64 uneven slices, 8x8 ranges, 16x16 domains stride 8 ---------------
+        from fic_inputs import batch_sides
+        sides = batch_sides(64)
+        bimgs = [torch.from_numpy(gen_image(sd, sd, 8, 4000 + i)).to(dev) for i, sd in enumerate(sides)]
+        bparams = [F.Params(sd, sd, 8, 8, 8) for sd in sides]
+        bat = F.Batch(bimgs, bparams)
+        bcand = sum(8 * F.query(bp)[0] * F.query(bp)[1] for bp in bparams)
+        for _ in range(2):
+            bat.run()
+        torch.cuda.synchronize(dev)
+        graph = torch.cuda.CUDAGraph()
+        gs = torch.cuda.Stream(device=dev)
+        gs.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(gs):
+            with torch.cuda.graph(graph, stream=gs):
+                bat.run()
+        torch.cuda.current_stream(dev).wait_stream(gs)
+        torch.cuda.synchronize(dev)
+        nrep = max(3, args.steps // 2)
+        lat = []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        total = 0.0
+        for _ in range(nrep):
+            e0.record()
+            graph.replay()
+            e1.record()
+            torch.cuda.synchronize(dev)
+            total += e0.elapsed_time(e1)
+            tk = bat.ticks.cpu().numpy().astype(np.int64)
+            lat.append((tk[1:] - tk[0]) / 100.0)   # 100 MHz ticks -> us
+        ms_b = total / nrep
+        lat = np.concatenate(lat)
+        result["batch64"] = {
+            "workload": "64 uint8 slices, sides from {256..512}^2, 8x8 ranges, 16x16 domains stride 8; one graph replay",
+            "slices": 64, "candidates": bcand, "ms_per_batch": ms_b,
+            "slices_per_s": 64 / (ms_b / 1e3), "value": bcand / (ms_b / 1e3), "unit": "comparisons/s",
+            "latency_us_p50": float(np.percentile(lat, 50)), "latency_us_p99": float(np.percentile(lat, 99)),
+            "latency_note": "device clock at each slice's search completion minus search start"}
 
     if not args.no_cpu_baseline:
         from oracle import oracle as O
@@ -127,7 +255,7 @@ def main():
         match = all(np.array_equal(ora[k], codes_m[k][rs]) for k in ora)
         result["cpu_baseline"] = {"value": len(rs) * 8 * ND / dt, "unit": "comparisons/s",
                                   "cores": O.max_threads(), "kind": "oracle",
-                                  "sample": f"{len(rs)} of {R} ranges (every {R // len(rs)}th), full domain search each; {dt:.1f} s",
+                                  "sample": f"{len(rs)} of {R} ranges of the same slice, full domain search each; {dt:.1f} s",
                                   "codes_match_gpu": bool(match)}
     result["wall_s"] = time.time() - t_wall0
     print(json.dumps(result), flush=True)

@@ -110,6 +110,39 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * Batched encode of many slices of uneven size (each slice an independent
+ * fic_encode problem; the paper encodes one image per kernel launch).
+ * All slices must share bit_depth (8), range_size, s_bits and o_bits; size
+ * and domain_step may differ.
+ *
+ * fic_batch_query -- host only: workspace bytes for the batch.
+ * fic_batch_prepare -- host, synchronous: validates the slices, lays out the
+ *   workspace (every slice's encode buffers, a slice table and a work list
+ *   ordered largest slice first) and copies the table and work list to the
+ *   device.  images[s] and out[s] are the slice's device image and device
+ *   code arrays, as in fic_encode.  Call it whenever the slice shapes or
+ *   pointers change, outside any stream capture.
+ * fic_encode_batch -- enqueues the batch on `stream`: one launch per phase
+ *   for all slices (operand preparation, dense seed block, search, code
+ *   extraction); the search runs as a persistent grid that takes work items
+ *   from a device counter.  It performs no allocation and no host-device
+ *   copy, so a stream capture of it can be replayed as a graph.  `ticks`
+ *   (device, n_slices + 1 entries, may be NULL) receives the GPU's 100 MHz
+ *   clock at the start of the search ([0]) and when each slice's search
+ *   finished ([1 + s]).  Codes equal those of fic_encode per slice.
+ * Errors: FIC_E_INVALID, FIC_E_UNSUPPORTED (not 8-bit; slice geometry as in
+ * fic_query), FIC_E_WORKSPACE, FIC_E_HIP.
+ */
+int fic_batch_query(const fic_params *slices, int32_t n_slices,
+                    size_t *ws_bytes);
+int fic_batch_prepare(const fic_params *slices, int32_t n_slices,
+                      const void *const *images, const fic_codes *out,
+                      void *workspace, size_t ws_bytes);
+int fic_encode_batch(const fic_params *slices, int32_t n_slices,
+                     void *workspace, size_t ws_bytes, uint64_t *ticks,
+                     void *stream);
+
+/*
  * fic_decode -- iterate the partitioned IFS map (eq. 6) `iters` times from
  * the constant image x0 (Section III: the attractor of a contractive map):
  *   x_{t+1}[range r, pixel (i,j)] = s_r * mean2x2(x_t, cell sigma_k(i,j) of
@@ -134,6 +167,68 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
                         int32_t iters, const float *traj, const float *grad_xT,
                         float *grad_s, float *grad_o, void *workspace,
                         size_t ws_bytes, void *stream);
+
+/*
+ * fic_refine -- adjust s and o of fixed codes to lower the error of their
+ * decoded attractor against the image (the collage theorem of Section III
+ * bounds that error; here it is minimised directly).  Domain and transform
+ * indices are held exact.  Runs `steps` Adam steps (beta1 0.9, beta2 0.999,
+ * eps 1e-8, learning rates lr_s and lr_o) on
+ *     L = mean((x_T - I)^2),   x_T = fic_decode(iters, x0),
+ * with gradients from fic_decode_backward; s is kept in [-0.999, 0.999].
+ *   s, o      device, n_ranges floats each, updated in place
+ *   image     device, the original image (uint8 / uint16 as in fic_encode)
+ *   loss      device, steps + 1 doubles: L before each step and after the last
+ *   workspace device, >= fic_refine_workspace bytes, 256-byte aligned
+ * Errors: FIC_E_INVALID (null pointers, negative iters/steps/rates),
+ * FIC_E_WORKSPACE.
+ */
+int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
+               float *s, float *o, const void *image, int32_t iters, float x0,
+               int32_t steps, float lr_s, float lr_o, double *loss,
+               void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes fic_refine needs for these parameters and iters (host). */
+int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
+
+/*
+ * Launch-shape tuning (host only; no GPU work).  The search grid splits the
+ * candidate table of eq. (8) into row groups of ranges and column chunks of
+ * domains; these entries choose how many chunks, how many leading 32-column
+ * blocks a dense pass fits first to seed each range's bound, and how many
+ * column blocks one work item of the batched search covers.  Any choice
+ * yields the same codes; only speed changes.  An entry applies to encodes
+ * with equal bit_depth, range_size and method and at least `min_domains`
+ * domains; among those the largest min_domains wins.  A field of 0 (-1 for
+ * seed_blocks) keeps the built-in default.  Values are clamped to the
+ * problem (at least one chunk; seed_blocks below the column block count).
+ *
+ * fic_set_tuning -- replaces the table with n_entries entries (0 clears it).
+ *   Errors: FIC_E_INVALID (NULL entries with n > 0, a field out of range:
+ *   bit_depth 8|12, range_size 4|8, method, min_domains >= 0,
+ *   col_chunks 0..4096, seed_blocks -1..64, item_blocks 0..4096).
+ * fic_load_tuning -- replaces the table with the entries of a JSON file:
+ *   every object holding a "bit_depth" key is one entry, read from the
+ *   integer keys named like the fields below; other keys are ignored.
+ *   Errors: FIC_E_INVALID (unreadable file, malformed JSON, a bad entry);
+ *   on error the table is unchanged.
+ * fic_get_tuning -- the resolved shape fic_encode would use for `p`
+ *   (min_domains reports the domain count of `p`).  Errors as fic_query.
+ * The table is process-wide and guarded by a lock; calls may come from any
+ * thread, but changing it while another thread encodes gives that encode
+ * either the old or the new shape.
+ */
+typedef struct {
+  int32_t bit_depth, range_size, method; /* key */
+  int32_t min_domains;                   /* applies from this domain count */
+  int32_t col_chunks;  /* column chunks per row group of the search grid */
+  int32_t seed_blocks; /* 32-column blocks fitted densely first; -1 default */
+  int32_t item_blocks; /* batched search: column blocks per work item */
+} fic_tuning;
+
+int fic_set_tuning(const fic_tuning *entries, int32_t n_entries);
+int fic_load_tuning(const char *json_path);
+int fic_get_tuning(const fic_params *p, fic_tuning *out);
 
 /*
  * Benchmark support (not needed to encode).  fic_timing_begin enables and

@@ -12,6 +12,8 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfic.so")
+# launch shapes measured by the autotuner; loaded with the library if present
+TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 METHOD_MFMA = 0
 METHOD_DIRECT = 1
@@ -37,6 +39,17 @@ class _Codes(ctypes.Structure):
     _fields_ = [("domain", ctypes.c_void_p), ("iso", ctypes.c_void_p),
                 ("s_idx", ctypes.c_void_p), ("o_idx", ctypes.c_void_p),
                 ("err", ctypes.c_void_p)]
+
+
+class Tuning(ctypes.Structure):
+    """One launch-shape entry (fic_tuning of include/fic.h)."""
+    _fields_ = [("bit_depth", ctypes.c_int32), ("range_size", ctypes.c_int32),
+                ("method", ctypes.c_int32), ("min_domains", ctypes.c_int32),
+                ("col_chunks", ctypes.c_int32), ("seed_blocks", ctypes.c_int32),
+                ("item_blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 @dataclass
@@ -76,16 +89,60 @@ def lib():
         L.fic_decode.argtypes = [P, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.fic_decode_backward.restype = ctypes.c_int
         L.fic_decode_backward.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        PP = ctypes.POINTER(_Params)
+        L.fic_batch_query.restype = ctypes.c_int
+        L.fic_batch_query.argtypes = [PP, i32, ctypes.POINTER(sz)]
+        L.fic_batch_prepare.restype = ctypes.c_int
+        L.fic_batch_prepare.argtypes = [PP, i32, ctypes.POINTER(vp), ctypes.POINTER(_Codes), vp, sz]
+        L.fic_encode_batch.restype = ctypes.c_int
+        L.fic_encode_batch.argtypes = [PP, i32, vp, sz, vp, vp]
+        L.fic_refine.restype = ctypes.c_int
+        L.fic_refine.argtypes = [P, vp, vp, vp, vp, vp, i32, ctypes.c_float, i32, ctypes.c_float,
+                                 ctypes.c_float, vp, vp, sz, vp]
+        L.fic_refine_workspace.restype = ctypes.c_int
+        L.fic_refine_workspace.argtypes = [P, i32, ctypes.POINTER(sz)]
         L.fic_timing_begin.restype = ctypes.c_int
         L.fic_timing_begin.argtypes = []
         L.fic_timing_end.restype = ctypes.c_int
         L.fic_timing_end.argtypes = [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_double)] * 3
+        TP = ctypes.POINTER(Tuning)
+        L.fic_set_tuning.restype = ctypes.c_int
+        L.fic_set_tuning.argtypes = [TP, i32]
+        L.fic_load_tuning.restype = ctypes.c_int
+        L.fic_load_tuning.argtypes = [ctypes.c_char_p]
+        L.fic_get_tuning.restype = ctypes.c_int
+        L.fic_get_tuning.argtypes = [P, TP]
         L.fic_status_string.restype = ctypes.c_char_p
         L.fic_status_string.argtypes = [ctypes.c_int]
         L.fic_last_error.restype = ctypes.c_char_p
         L.fic_last_error.argtypes = []
         _LIB = L
+        if os.path.exists(TUNING_PATH):
+            _check(L.fic_load_tuning(TUNING_PATH.encode()))
     return _LIB
+
+
+def set_tuning(entries):
+    """Replace the launch-shape table; entries are dicts with Tuning's fields
+    (missing col_chunks / item_blocks = 0 and seed_blocks = -1: defaults)."""
+    arr = (Tuning * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = Tuning(e["bit_depth"], e["range_size"], e["method"], e.get("min_domains", 0),
+                        e.get("col_chunks", 0), e.get("seed_blocks", -1), e.get("item_blocks", 0))
+    _check(lib().fic_set_tuning(arr, len(entries)))
+
+
+def load_tuning(path):
+    """Replace the launch-shape table with the entries of a JSON file."""
+    _check(lib().fic_load_tuning(os.fsencode(path)))
+
+
+def get_tuning(p: "Params"):
+    """The launch shape fic_encode resolves for these parameters (dict)."""
+    t = Tuning()
+    cp = p.c()
+    _check(lib().fic_get_tuning(ctypes.byref(cp), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def _check(status):
@@ -156,6 +213,53 @@ def encode(image: torch.Tensor, p: Params, workspace=None):
     return out
 
 
+class Batch:
+    """A prepared batch of slices (device images, codes and workspace kept
+    alive here).  run() enqueues fic_encode_batch on the current stream."""
+
+    def __init__(self, images, params):
+        if len(images) != len(params) or not images:
+            raise ValueError("need one Params per image")
+        self.params = list(params)
+        n = len(images)
+        self._cp = (_Params * n)(*[p.c() for p in params])
+        nbytes = ctypes.c_size_t()
+        _check(lib().fic_batch_query(self._cp, n, ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        dev = images[0].device
+        self._keep, self._ws = _workspace(self.ws_bytes, dev)
+        self.images = []
+        self.codes = []
+        for img, p in zip(images, params):
+            exp = torch.uint8 if p.bit_depth == 8 else torch.uint16
+            if img.dtype == torch.int16 and p.bit_depth == 12:
+                img = img.view(torch.uint16)
+            _dev_ptr(img, exp, "image")
+            if tuple(img.shape) != (p.height, p.width):
+                raise ValueError("image shape does not match its Params")
+            nr = (p.height // p.range_size) * (p.width // p.range_size)
+            self.images.append(img)
+            self.codes.append(dict(domain=torch.empty(nr, dtype=torch.int32, device=dev),
+                                   iso=torch.empty(nr, dtype=torch.uint8, device=dev),
+                                   s_idx=torch.empty(nr, dtype=torch.uint8, device=dev),
+                                   o_idx=torch.empty(nr, dtype=torch.uint8, device=dev),
+                                   err=torch.empty(nr, dtype=torch.float64, device=dev)))
+        self.ticks = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+        ptrs = (ctypes.c_void_p * n)(*[im.data_ptr() for im in self.images])
+        outs = (_Codes * n)(*[_Codes(c["domain"].data_ptr(), c["iso"].data_ptr(),
+                                     c["s_idx"].data_ptr(), c["o_idx"].data_ptr(),
+                                     c["err"].data_ptr()) for c in self.codes])
+        _check(lib().fic_batch_prepare(self._cp, n, ptrs, outs, ctypes.c_void_p(self._ws),
+                                       ctypes.c_size_t(self.ws_bytes)))
+
+    def run(self):
+        dev = self.images[0].device
+        _check(lib().fic_encode_batch(self._cp, len(self.images), ctypes.c_void_p(self._ws),
+                                      ctypes.c_size_t(self.ws_bytes),
+                                      ctypes.c_void_p(self.ticks.data_ptr()), _stream(dev)))
+        return self.codes
+
+
 def dequantize(s_idx, o_idx, p: Params):
     """Grid values of quantised codes: s = s_idx/2^(s_bits-1) - 1, o = o_idx*delta_o - 2^bits."""
     s = s_idx.to(torch.float32) / float(2 ** (p.s_bits - 1)) - 1.0
@@ -197,6 +301,32 @@ def decode_backward(domain, iso, s, o, traj, grad_xT, p: Params):
                                      _stream(dev)))
     del keep
     return gs, go
+
+
+def refine(domain, iso, s, o, image, p: Params, iters=12, steps=50, lr_s=5e-3, lr_o=0.5,
+           x0=None):
+    """Adam refinement of (s, o) against the decoded attractor's error, indices
+    fixed.  s and o (float32 device tensors) are updated in place; returns the
+    loss before each step and after the last (float64 device tensor)."""
+    if x0 is None:
+        x0 = float(2 ** (p.bit_depth - 1))
+    dev = s.device
+    exp = torch.uint8 if p.bit_depth == 8 else torch.uint16
+    if image.dtype == torch.int16 and p.bit_depth == 12:
+        image = image.view(torch.uint16)
+    nbytes = ctypes.c_size_t()
+    cp = p.c()
+    _check(lib().fic_refine_workspace(ctypes.byref(cp), iters, ctypes.byref(nbytes)))
+    keep, ws = _workspace(nbytes.value, dev)
+    loss = torch.empty(steps + 1, dtype=torch.float64, device=dev)
+    _check(lib().fic_refine(ctypes.byref(cp), _dev_ptr(domain, torch.int32, "domain"),
+                            _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
+                            _dev_ptr(o, torch.float32, "o"), _dev_ptr(image, exp, "image"), iters,
+                            ctypes.c_float(x0), steps, ctypes.c_float(lr_s), ctypes.c_float(lr_o),
+                            loss.data_ptr(), ctypes.c_void_p(ws), ctypes.c_size_t(nbytes.value),
+                            _stream(dev)))
+    loss._ws = keep
+    return loss
 
 
 def timing_begin():

@@ -79,8 +79,6 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
     return fail(FIC_E_INVALID, "method %d", p->method);
   if ((long long)p->height * p->width > (1ll << 30))
     return fail(FIC_E_UNSUPPORTED, "image larger than 2^30 pixels");
-  if (for_encode && p->bit_depth == 12)
-    return fail(FIC_E_UNSUPPORTED, "12-bit search not built");
 
   g.H = p->height;
   g.W = p->width;
@@ -99,6 +97,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.R_pad = (g.R + kMfmaRangesPerWG - 1) / kMfmaRangesPerWG * kMfmaRangesPerWG;
   g.NCB = (g.ND + 31) / 32;
   g.NC_pad = g.NCB * 32;
+  g.n_dwg = (int)(((long long)g.NC_pad * n + 255) / 256);
   g.P = ldexp(1.0, g.bits);
   g.dlt = 2.0 * g.P / ldexp(1.0, g.ob);
   g.S = ldexp(1.0, g.sb - 1);
@@ -125,13 +124,12 @@ EncLayout enc_layout(const Geo &g) {
   L.off_bop = o;      o = align256(o + planes * (size_t)g.NC_pad * g.K * 2);
   L.off_aop = o;      o = align256(o + planes * (size_t)g.R_pad * 8 * g.K * 2);
   L.off_col_dom = o;  o = align256(o + (size_t)g.NC_pad * 4);
-  L.off_col_sa = o;   o = align256(o + (size_t)g.NC_pad * 4);
-  L.off_col_dp = o;   o = align256(o + (size_t)g.NC_pad * 4);
+  L.off_col_sadp = o; o = align256(o + (size_t)g.NC_pad * 8);
   L.off_col_saa = o;  o = align256(o + (size_t)g.NC_pad * 8);
   L.off_rng_sb = o;   o = align256(o + (size_t)g.R_pad * 8);
   L.off_rng_sbb = o;  o = align256(o + (size_t)g.R_pad * 8);
   L.off_best = o;     o = align256(o + (size_t)g.R_pad * 8);
-  L.off_flat = o;     o = align256(o + 4);
+  L.off_flat = o;     o = align256(o + (size_t)g.n_dwg * 4);
   L.total = o;
   return L;
 }
@@ -142,24 +140,13 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   b.bop = (_Float16 *)(w + L.off_bop);
   b.aop = (_Float16 *)(w + L.off_aop);
   b.col_dom = (int32_t *)(w + L.off_col_dom);
-  b.col_sa = (float *)(w + L.off_col_sa);
-  b.col_dp = (float *)(w + L.off_col_dp);
+  b.col_sadp = (float2 *)(w + L.off_col_sadp);
   b.col_saa = (double *)(w + L.off_col_saa);
   b.rng_sb = (double *)(w + L.off_rng_sb);
   b.rng_sbb = (double *)(w + L.off_rng_sbb);
   b.best = (unsigned long long *)(w + L.off_best);
-  b.flat_first = (int32_t *)(w + L.off_flat);
+  b.flat_min = (int32_t *)(w + L.off_flat);
   return b;
-}
-
-// Column chunks per row group: about two workgroups per compute unit
-// (256 CUs) in one launch.
-int default_chunks(const Geo &g) {
-  const int row_groups = g.R_pad / kMfmaRangesPerWG;
-  int c = (512 + row_groups - 1) / row_groups;
-  if (c > g.NCB) c = g.NCB;
-  if (c < 1) c = 1;
-  return c;
 }
 
 int hip_fail(hipError_t e, const char *what) {
@@ -182,6 +169,18 @@ void timing_mark(int phase, hipStream_t s) {
 }
 
 }  // namespace
+
+// Shared with the batch front end (fic_batch.hip).
+int make_geo_for_batch(const fic_params *p, Geo &g) {
+  return make_geo(p, g, /*for_encode=*/true);
+}
+size_t enc_workspace_bytes(const Geo &g) { return enc_layout(g).total; }
+EncBufs enc_workspace_bufs(const Geo &g, void *ws) {
+  return enc_bufs(enc_layout(g), ws);
+}
+int abi_fail(int status, const char *msg) { return fail(status, "%s", msg); }
+int abi_ok() { return ok(); }
+
 }  // namespace fic
 
 using namespace fic;
@@ -220,14 +219,16 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   hipError_t e = launch_prep(g, image, b, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   timing_mark(1, s);
-  const int chunks = default_chunks(g);
-  // the first column block is fitted densely to seed every range's bound
-  const int seeded = g.NCB >= 16 ? 1 : 0;
-  e = launch_seed_dense(g, b, seeded, s);
+  // leading column blocks are fitted densely to seed every range's bound
+  const Tune t = resolve_tune(g, p->method);
+  e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
-  e = (p->method == FIC_METHOD_DIRECT)
-          ? launch_search_direct(g, b, chunks, seeded, s)
-          : launch_search_mfma(g, b, chunks, seeded, s);
+  if (p->method == FIC_METHOD_DIRECT)
+    e = launch_search_direct(g, b, t.chunks, t.seed_blocks, s);
+  else if (g.bits == 12)
+    e = launch_search_mfma12(g, b, t.chunks, t.seed_blocks, s);
+  else
+    e = launch_search_mfma(g, b, t.chunks, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "search");
   timing_mark(2, s);
   e = launch_finalize(g, image, b, out, s);
@@ -274,6 +275,41 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
                                         grad_xT, grad_s, grad_o, workspace,
                                         (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode_backward");
+  return ok();
+}
+
+int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  if (!bytes) return fail(FIC_E_INVALID, "bytes is NULL");
+  *bytes = refine_ws_bytes(g, iters);
+  return ok();
+}
+
+int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
+               float *s, float *o, const void *image, int32_t iters, float x0,
+               int32_t steps, float lr_s, float lr_o, double *loss,
+               void *workspace, size_t ws_bytes, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !image || !loss || !workspace)
+    return fail(FIC_E_INVALID, "null pointer argument");
+  if (iters < 0 || steps < 0)
+    return fail(FIC_E_INVALID, "iters %d or steps %d < 0", iters, steps);
+  if (!(lr_s >= 0.0f) || !(lr_o >= 0.0f))
+    return fail(FIC_E_INVALID, "learning rates must be >= 0");
+  if (((uintptr_t)workspace) & 255)
+    return fail(FIC_E_INVALID, "workspace is not 256-byte aligned");
+  const size_t need = refine_ws_bytes(g, iters);
+  if (ws_bytes < need)
+    return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                need);
+  hipError_t e = launch_refine(g, domain, iso, s, o, image, iters, x0, steps,
+                               lr_s, lr_o, loss, workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "refine");
   return ok();
 }
 

@@ -243,6 +243,66 @@ hipError_t backward_impl(const Geo &g, const int32_t *domain,
   return hipGetLastError();
 }
 
+// --- refinement: loss gradient and Adam ------------------------------------
+
+// g = dL/dx for L = mean((x - I)^2), and per-block partial sums of (x - I)^2
+// (tree in LDS, fixed order).
+template <typename Pix>
+__global__ __launch_bounds__(256) void k_mse_grad(long long HW, const float *x,
+                                                  const Pix *img, float *gout,
+                                                  double *partial) {
+  __shared__ double red[256];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double d2 = 0.0;
+  if (i < HW) {
+    const float d = x[i] - (float)img[i];
+    gout[i] = 2.0f * d / (float)HW;
+    // the loss takes the difference exactly (both operands fit a double)
+    const double dd = (double)x[i] - (double)img[i];
+    d2 = dd * dd;
+  }
+  red[threadIdx.x] = d2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// loss[slot] = sum(partial) / HW, summed by one workgroup in a fixed order.
+__global__ __launch_bounds__(256) void k_loss(const double *partial, int n,
+                                              long long HW, double *loss,
+                                              int slot) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss[slot] = red[0] / (double)HW;
+}
+
+// One Adam step on (s, o); c1, c2 are the bias corrections 1 - beta^t.
+__global__ void k_adam(int R, float *s, float *o, const float *gs,
+                       const float *go, float *mom, float lr_s, float lr_o,
+                       float b1, float b2, float c1, float c2, float eps,
+                       float s_lim) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float *ms = mom, *vs = mom + R, *mo = mom + 2 * R, *vo = mom + 3 * R;
+  ms[r] = b1 * ms[r] + (1.0f - b1) * gs[r];
+  vs[r] = b2 * vs[r] + (1.0f - b2) * gs[r] * gs[r];
+  mo[r] = b1 * mo[r] + (1.0f - b1) * go[r];
+  vo[r] = b2 * vo[r] + (1.0f - b2) * go[r] * go[r];
+  const float ss = s[r] - lr_s * (ms[r] / c1) / (sqrtf(vs[r] / c2) + eps);
+  s[r] = fminf(fmaxf(ss, -s_lim), s_lim);
+  o[r] = o[r] - lr_o * (mo[r] / c1) / (sqrtf(vo[r] / c2) + eps);
+}
+
 }  // namespace
 
 size_t decode_backward_ws_bytes(const Geo &g) {
@@ -282,6 +342,63 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                             grad_o, ws, st);
   return backward_impl<4>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
                           grad_o, ws, st);
+}
+
+}  // namespace fic
+
+namespace fic {
+
+size_t refine_ws_bytes(const Geo &g, int iters) {
+  const size_t HW = (size_t)g.H * g.W;
+  const size_t nb = (HW + 255) / 256;
+  return a256(sizeof(float) * HW * (size_t)(iters + 1)) +  // trajectory
+         a256(sizeof(float) * HW) +                        // dL/dx_T
+         a256(sizeof(float) * 2 * g.R) +                   // dL/ds, dL/do
+         a256(sizeof(float) * 4 * g.R) +                   // Adam moments
+         a256(sizeof(double) * nb) +                       // loss partials
+         decode_backward_ws_bytes(g);
+}
+
+hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                         float *s, float *o, const void *image, int iters,
+                         float x0, int steps, float lr_s, float lr_o,
+                         double *loss, void *ws, hipStream_t st) {
+  const size_t HW = (size_t)g.H * g.W;
+  const int nb = (int)((HW + 255) / 256);
+  char *w = (char *)ws;
+  float *traj = (float *)w;   w += a256(sizeof(float) * HW * (size_t)(iters + 1));
+  float *gx = (float *)w;     w += a256(sizeof(float) * HW);
+  float *gso = (float *)w;    w += a256(sizeof(float) * 2 * g.R);
+  float *mom = (float *)w;    w += a256(sizeof(float) * 4 * g.R);
+  double *part = (double *)w; w += a256(sizeof(double) * nb);
+  void *bws = w;
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, s_lim = 0.999f;
+  hipLaunchKernelGGL(k_fill_f32, dim3((4 * g.R + 255) / 256), dim3(256), 0, st,
+                     mom, (long long)4 * g.R, 0.0f);
+  float p1 = 1.0f, p2 = 1.0f;
+  for (int step = 0; step <= steps; ++step) {
+    hipError_t e = launch_decode(g, domain, iso, s, o, iters, x0, traj, st);
+    if (e != hipSuccess) return e;
+    const float *xT = traj + (size_t)iters * HW;
+    if (g.bits == 12)
+      hipLaunchKernelGGL(k_mse_grad<uint16_t>, dim3(nb), dim3(256), 0, st,
+                         (long long)HW, xT, (const uint16_t *)image, gx, part);
+    else
+      hipLaunchKernelGGL(k_mse_grad<uint8_t>, dim3(nb), dim3(256), 0, st,
+                         (long long)HW, xT, (const uint8_t *)image, gx, part);
+    hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, st, part, nb,
+                       (long long)HW, loss, step);
+    if (step == steps) break;
+    e = launch_decode_backward(g, domain, iso, s, o, iters, traj, gx, gso,
+                               gso + g.R, bws, st);
+    if (e != hipSuccess) return e;
+    p1 *= b1;
+    p2 *= b2;
+    hipLaunchKernelGGL(k_adam, dim3((g.R + 255) / 256), dim3(256), 0, st, g.R,
+                       s, o, gso, gso + g.R, mom, lr_s, lr_o, b1, b2, 1.0f - p1,
+                       1.0f - p2, eps, s_lim);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace fic

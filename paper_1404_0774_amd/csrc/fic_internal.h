@@ -20,6 +20,7 @@ struct Geo {
   int NX, NY, ND;    // domain grid
   int R_pad;         // ranges rounded up to the search tile
   int NCB;           // column blocks of 32 domains
+  int n_dwg;         // workgroups of the domain preparation
   int NC_pad;        // NCB * 32
   int cbits;         // low bits of the search key that hold the candidate
   int dom_stride;    // sweep order: column c holds domain (c * dom_stride) % ND
@@ -36,22 +37,46 @@ struct EncBufs {
   _Float16 *aop;     // [R_pad * 8][K] range pixels permuted per transform
                      //   (12-bit: two planes)
   int32_t *col_dom;  // [NC_pad] domain index of a column, -1 for padding
-  float *col_sa;     // [NC_pad] sum of cell sums of the column's domain
-  float *col_dp;     // [NC_pad] prune denominator: D' rounded down;
-                     //   0 for the first flat domain, +inf for later flat
-                     //   domains and padding
+  float2 *col_sadp;  // [NC_pad] (sum of the column's cell sums SA,
+                     //   prune denominator D' rounded down; +inf for flat
+                     //   domains and padding)
   double *col_saa;   // [NC_pad] sum of squared cell sums
   double *rng_sb;    // [R_pad] sum of range pixels
   double *rng_sbb;   // [R_pad] sum of squared range pixels
   unsigned long long *best; // [R_pad] packed (residual, candidate) keys
-  int32_t *flat_first;      // [1] smallest flat domain index (ND if none)
+  int32_t *flat_min;  // [domain-prep workgroups] smallest flat domain index
+                      //   seen by each workgroup (INT_MAX if none)
 };
 
 // Byte layout of the encode workspace.
 struct EncLayout {
-  size_t off_bop, off_aop, off_col_dom, off_col_sa, off_col_dp, off_col_saa;
+  size_t off_bop, off_aop, off_col_dom, off_col_sadp, off_col_saa;
   size_t off_rng_sb, off_rng_sbb, off_best, off_flat;
   size_t total;
+};
+
+// One slice of a batch, as the batched kernels see it (device table).
+struct SliceDesc {
+  Geo g;
+  EncBufs b;
+  const void *image;
+  fic_codes out;
+  int seed_blocks;  // column blocks the dense seed pass fits
+};
+
+// Device side of a batch (all pointers into the caller's workspace).
+struct BatchDev {
+  SliceDesc *tab;             // [n]
+  int4 *items;                // [n_items]: slice, row group, first block, end
+  int *phase_off;             // [4][n + 1] workgroup offsets per phase:
+                              //   domain prep, range prep, seed, finalize
+  int *items_per_slice;       // [n]
+  int *remaining;             // [n] unfinished search items per slice
+  int *counter;               // [1] next search item
+  unsigned long long *ticks;  // [n + 1] start tick, completion tick per slice
+  int n, n_items;
+  int phase_total[4];         // workgroups per phase
+  int bits, rsize;            // common to every slice
 };
 
 // Launchers (one per kernel file).  All return hipError_t of the launch.
@@ -61,6 +86,8 @@ hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st);
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
                               int seeded_blocks, hipStream_t st);
+hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
+                                int seeded_blocks, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
                                 int seeded_blocks, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
@@ -74,9 +101,37 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                                   const float *grad_xT, float *grad_s,
                                   float *grad_o, void *ws, hipStream_t st);
 size_t decode_backward_ws_bytes(const Geo &g);
+hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st);
+hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st);
+hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st);
+hipError_t launch_finalize_batch(const BatchDev &bd, hipStream_t st);
+size_t refine_ws_bytes(const Geo &g, int iters);
+hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                         float *s, float *o, const void *image, int iters,
+                         float x0, int steps, float lr_s, float lr_o,
+                         double *loss, void *ws, hipStream_t st);
 
 // Search tile: ranges per workgroup of the matrix-core search.
 constexpr int kMfmaRangesPerWG = 64;  // 4 waves x 4 row blocks x 4 ranges
+constexpr int kMfma12RangesPerWG = 16;
 constexpr int kDirectRangesPerWG = 32;
+
+// Launch shape of one encode, resolved from the tuning table (fic_tuning.hip)
+// with the library defaults for anything the table leaves open.  Always
+// 1 <= chunks <= NCB - seed_blocks and 0 <= seed_blocks < NCB.
+struct Tune {
+  int chunks;       // column chunks per row group of the search grid
+  int seed_blocks;  // leading column blocks fitted densely before the search
+  int item_blocks;  // batched search: column blocks per work item
+};
+Tune resolve_tune(const Geo &g, int method);
+
+// Shared by the host files (defined in fic_abi.hip, which owns the
+// thread-local error state).
+int abi_fail(int status, const char *msg);
+int abi_ok();
+int make_geo_for_batch(const fic_params *p, Geo &g);  // encode validation
+size_t enc_workspace_bytes(const Geo &g);
+EncBufs enc_workspace_bufs(const Geo &g, void *ws);
 
 }  // namespace fic

@@ -22,67 +22,60 @@ __device__ __forceinline__ T group_sum(T v, int width) {
   return v;
 }
 
-__global__ void k_fill_i32(int32_t *p, int v) { *p = v; }
-
-// One thread per (column, group of 8 cells).  Column c of the sweep holds
-// domain d = (c * dom_stride) mod ND; its 2x2 cell sums A (4x the contracted
-// value of Alg. 1) are written as exact FP16 integers.  12-bit images store
-// A = 128 A_hi + A_lo as two planes.  Flat domains (no variance) are marked
-// +inf in col_dp: they all fit any range with s = 0 and the same offset
-// (eqs. 11-12), so only the first of them, seeded per range, can be kept;
-// the smallest flat index is reduced per workgroup, then atomically.
-template <typename Pix, int K>
-__global__ __launch_bounds__(256) void k_prep_domains(Geo g, const Pix *img,
-                                                      EncBufs b) {
-  constexpr int GRP = K / 8;  // threads per column
+// One thread per (column, cell row): N threads per column.  Column c of the
+// sweep holds domain d = (c * dom_stride) mod ND; its 2x2 cell sums A (4x the
+// contracted value of Alg. 1) are written as exact FP16 integers.  12-bit
+// images store A = 128 A_hi + A_lo as two planes.  Flat domains (no
+// variance) get +inf as their prune denominator: they all fit any range with
+// s = 0 and the same offset (eqs. 11-12), so only the first of them, seeded
+// per range, can be kept.  Each workgroup records the smallest flat domain
+// index it saw.
+template <typename Pix, int N>
+__device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
+                                                  const EncBufs &b, int bid) {
+  constexpr int K = N * N;
+  typedef _Float16 halfN __attribute__((ext_vector_type(N)));
   __shared__ int s_flat;
   if (threadIdx.x == 0) s_flat = INT_MAX;
   __syncthreads();
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  const long long col = t / GRP;
-  const int part = (int)(t % GRP);
+  const long long t = (long long)bid * blockDim.x + threadIdx.x;
+  const long long col = t / N;
+  const int i = (int)(t % N);
   const bool live = col < g.NC_pad;
-  const int n = g.n;
   long long SA = 0, SAA = 0;
   int d = -1;
-  _Float16 hi[8], lo[8];
+  halfN vh, vl;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) hi[e] = lo[e] = (_Float16)0.0f;
+  for (int j = 0; j < N; ++j) vh[j] = vl[j] = (_Float16)0.0f;
   if (live && col < g.ND) {
     d = (int)((col * (long long)g.dom_stride) % g.ND);
     const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
+    const Pix *r0 = img + (size_t)(Y + 2 * i) * g.W + X;
+    const Pix *r1 = r0 + g.W;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int q = part * 8 + e, i = q / n, j = q % n;
-      const int A = cell_sum(img, g.W, Y + 2 * i, X + 2 * j);
+    for (int j = 0; j < N; ++j) {
+      const int A = (int)r0[2 * j] + (int)r0[2 * j + 1] + (int)r1[2 * j] +
+                    (int)r1[2 * j + 1];
       SA += A;
       SAA += (long long)A * A;
       if (g.bits == 12) {
-        hi[e] = (_Float16)(float)(A >> 7);
-        lo[e] = (_Float16)(float)(A & 127);
+        vh[j] = (_Float16)(float)(A >> 7);
+        vl[j] = (_Float16)(float)(A & 127);
       } else {
-        hi[e] = (_Float16)(float)A;
+        vh[j] = (_Float16)(float)A;
       }
     }
   }
   if (live) {
-    typedef _Float16 half8 __attribute__((ext_vector_type(8)));
-    half8 vh, vl;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      vh[e] = hi[e];
-      vl[e] = lo[e];
-    }
-    *(half8 *)(b.bop + (size_t)col * K + part * 8) = vh;
+    *(halfN *)(b.bop + (size_t)col * K + i * N) = vh;
     if (g.bits == 12)
-      *(half8 *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + part * 8) = vl;
+      *(halfN *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + i * N) = vl;
   }
-  // the column's statistics over its GRP adjacent threads
-  SA = group_sum(SA, GRP);
-  SAA = group_sum(SAA, GRP);
-  if (live && part == 0) {
+  // the column's statistics over its N adjacent threads
+  SA = group_sum(SA, N);
+  SAA = group_sum(SAA, N);
+  if (live && i == 0) {
     b.col_dom[col] = d;
-    b.col_sa[col] = (float)SA;
     b.col_saa[col] = (double)SAA;
     float dp = __builtin_inff();
     if (d >= 0) {
@@ -92,10 +85,16 @@ __global__ __launch_bounds__(256) void k_prep_domains(Geo g, const Pix *img,
       else
         dp = round_down_f(Dp);
     }
-    b.col_dp[col] = dp;
+    b.col_sadp[col] = float2{(float)SA, dp};
   }
   __syncthreads();
-  if (threadIdx.x == 0 && s_flat != INT_MAX) atomicMin(b.flat_first, s_flat);
+  if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
+}
+
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_prep_domains(Geo g, const Pix *img,
+                                                      EncBufs b) {
+  prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
 }
 
 // One thread per range pixel (K threads per range, one wave for n = 8).
@@ -106,10 +105,22 @@ __global__ __launch_bounds__(256) void k_prep_domains(Geo g, const Pix *img,
 // candidate c = 0 (domain 0, identity) and the first flat domain, both
 // fitted exactly.
 template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_prep_ranges(Geo g, const Pix *img,
-                                                     EncBufs b) {
+__device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
+                                                 const EncBufs &b, int bid) {
   constexpr int K = N * N;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  // smallest flat domain over the domain-preparation workgroups
+  __shared__ int s_ff;
+  if (threadIdx.x == 0) s_ff = INT_MAX;
+  __syncthreads();
+  {
+    int m = INT_MAX;
+    for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
+      m = min(m, b.flat_min[i]);
+    atomicMin(&s_ff, m);
+  }
+  __syncthreads();
+  const int ff = s_ff;
+  const long long t = (long long)bid * blockDim.x + threadIdx.x;
   const int r = (int)(t / K), q = (int)(t % K);
   if (r >= g.R_pad) return;  // whole groups of K lanes leave together
   const int i = q / N, j = q % N, m = N - 1;
@@ -149,7 +160,6 @@ __global__ __launch_bounds__(256) void k_prep_ranges(Geo g, const Pix *img,
   const Fit f0 = fit_exact((double)G0, (double)SA0, (double)SAA0, (double)Sb,
                            (double)Sbb, g);
   unsigned long long key = make_key(f0.err, 0, g);
-  const int ff = *b.flat_first;
   if (ff < g.ND) {
     // a flat domain has A = const, so G = SA * Sb / K, N' = 0, s = 0
     const double SAf = 0.0;  // any constant domain gives the same fit
@@ -160,14 +170,21 @@ __global__ __launch_bounds__(256) void k_prep_ranges(Geo g, const Pix *img,
   b.best[r] = key;
 }
 
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_prep_ranges(Geo g, const Pix *img,
+                                                     EncBufs b) {
+  prep_ranges_body<Pix, N>(g, img, b, blockIdx.x);
+}
+
 // One group of K lanes per range: unpack the winning key and recompute its
 // fit from the image to produce the code (domain, transform, s index,
 // o index, residual).
 template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
-                                                  EncBufs b, fic_codes out) {
+__device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
+                                              const EncBufs &b,
+                                              const fic_codes &out, int bid) {
   constexpr int K = N * N;
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long t = (long long)bid * blockDim.x + threadIdx.x;
   const int r = (int)(t / K), q = (int)(t % K);
   if (r >= g.R) return;  // whole groups leave together (R_pad >= R)
   const unsigned long long key = b.best[r];
@@ -195,21 +212,22 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
   out.err[r] = f.err;
 }
 
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
+                                                  EncBufs b, fic_codes out) {
+  finalize_body<Pix, N>(g, img, b, out, blockIdx.x);
+}
+
 template <typename Pix>
 hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
                      hipStream_t st) {
-  // flat_first := ND (a fill kernel rather than a memset node keeps the
-  // sequence safe to capture into a graph)
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(1), 0, st, b.flat_first, g.ND);
-  const long long dthreads = (long long)g.NC_pad * (g.K / 8);
   const int bs = 256;
-  const dim3 dgrid((unsigned)((dthreads + bs - 1) / bs));
-  if (g.K == 64)
-    hipLaunchKernelGGL((k_prep_domains<Pix, 64>), dgrid, dim3(bs), 0, st, g,
-                       img, b);
+  if (g.n == 8)
+    hipLaunchKernelGGL((k_prep_domains<Pix, 8>), dim3(g.n_dwg), dim3(bs), 0, st,
+                       g, img, b);
   else
-    hipLaunchKernelGGL((k_prep_domains<Pix, 16>), dgrid, dim3(bs), 0, st, g,
-                       img, b);
+    hipLaunchKernelGGL((k_prep_domains<Pix, 4>), dim3(g.n_dwg), dim3(bs), 0, st,
+                       g, img, b);
   const dim3 rgrid((unsigned)(((long long)g.R_pad * g.K + bs - 1) / bs));
   if (g.n == 8)
     hipLaunchKernelGGL((k_prep_ranges<Pix, 8>), rgrid, dim3(bs), 0, st, g, img,
@@ -220,7 +238,97 @@ hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
   return hipGetLastError();
 }
 
+// Slice of workgroup `bid` in a phase with offsets off[0..n] (off[n] is the
+// total): the s with off[s] <= bid < off[s + 1].
+__device__ __forceinline__ int slice_of(const int *off, int n, int bid) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_batch_init(BatchDev bd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) {
+    *bd.counter = 0;
+    bd.ticks[0] = ~0ull;
+  }
+  if (i < bd.n) {
+    bd.remaining[i] = bd.items_per_slice[i];
+    bd.ticks[1 + i] = 0;
+  }
+}
+
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_prep_domains_batch(BatchDev bd) {
+  const int s = slice_of(bd.phase_off, bd.n, blockIdx.x);
+  const SliceDesc &d = bd.tab[s];
+  prep_domains_body<Pix, N>(d.g, (const Pix *)d.image, d.b,
+                            blockIdx.x - bd.phase_off[s]);
+}
+
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_prep_ranges_batch(BatchDev bd) {
+  const int *off = bd.phase_off + (bd.n + 1);
+  const int s = slice_of(off, bd.n, blockIdx.x);
+  const SliceDesc &d = bd.tab[s];
+  prep_ranges_body<Pix, N>(d.g, (const Pix *)d.image, d.b, blockIdx.x - off[s]);
+}
+
+template <typename Pix, int N>
+__global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
+  const int *off = bd.phase_off + 3 * (bd.n + 1);
+  const int s = slice_of(off, bd.n, blockIdx.x);
+  const SliceDesc &d = bd.tab[s];
+  finalize_body<Pix, N>(d.g, (const Pix *)d.image, d.b, d.out,
+                        blockIdx.x - off[s]);
+}
+
 }  // namespace
+
+hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_init, dim3((bd.n + 255) / 256), dim3(256), 0, st,
+                     bd);
+  if (bd.bits == 12) {
+    if (bd.rsize == 8) {
+      hipLaunchKernelGGL((k_prep_domains_batch<uint16_t, 8>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
+      hipLaunchKernelGGL((k_prep_ranges_batch<uint16_t, 8>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
+    } else {
+      hipLaunchKernelGGL((k_prep_domains_batch<uint16_t, 4>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
+      hipLaunchKernelGGL((k_prep_ranges_batch<uint16_t, 4>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
+    }
+  } else {
+    if (bd.rsize == 8) {
+      hipLaunchKernelGGL((k_prep_domains_batch<uint8_t, 8>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
+      hipLaunchKernelGGL((k_prep_ranges_batch<uint8_t, 8>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
+    } else {
+      hipLaunchKernelGGL((k_prep_domains_batch<uint8_t, 4>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
+      hipLaunchKernelGGL((k_prep_ranges_batch<uint8_t, 4>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
+    }
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_batch(const BatchDev &bd, hipStream_t st) {
+  const dim3 grid(bd.phase_total[3]);
+  if (bd.bits == 12) {
+    if (bd.rsize == 8)
+      hipLaunchKernelGGL((k_finalize_batch<uint16_t, 8>), grid, dim3(256), 0, st, bd);
+    else
+      hipLaunchKernelGGL((k_finalize_batch<uint16_t, 4>), grid, dim3(256), 0, st, bd);
+  } else {
+    if (bd.rsize == 8)
+      hipLaunchKernelGGL((k_finalize_batch<uint8_t, 8>), grid, dim3(256), 0, st, bd);
+    else
+      hipLaunchKernelGGL((k_finalize_batch<uint8_t, 4>), grid, dim3(256), 0, st, bd);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
                        hipStream_t st) {

@@ -27,7 +27,7 @@
 // lexicographically, so the result does not depend on the order of the work.
 #include <math.h>
 
-#include "fic_device.h"
+#include "fic_search_common.h"
 
 namespace fic {
 
@@ -56,24 +56,6 @@ struct Cand {
   float g;
   unsigned pk;
 };
-
-__device__ __forceinline__ unsigned long long load_best(
-    const unsigned long long *p) {
-  // bypass the non-coherent L1 so other workgroups' improvements are seen
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Prune weight W' = (V - K best)/K^2 of a range from its packed key, rounded
-// down (relative 2^-20) so that float rounding in the test can only let more
-// candidates through; 0 when the bound is useless, +inf for a range without
-// variance (every candidate ties with the seeded candidate 0 there).
-__device__ __forceinline__ float weight_from_key(unsigned long long key,
-                                                 double V, const Geo &g) {
-  const double K = (double)g.K;
-  const double Wd = fma(-K / g.escale, (double)(key >> g.cbits), V);
-  const float w = (float)(fmax(Wd, 0.0) * (1.0 / (K * K))) * (1.0f - 0x1p-20f);
-  return V == 0.0 ? __builtin_inff() : w;
-}
 
 // The least-squares test shared by the 8 transforms of one (range, domain)
 // pair: max_k |G_k - SA Sb/K| >= sqrt(W' D').
@@ -173,6 +155,125 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
   qn = rem;
 }
 
+// Per-wave state of the sweep (lives in registers and LDS).
+struct WaveState {
+  unsigned long long *best;  // LDS: wave's best keys
+  double2 *rstat;            // LDS: (Sb, Sbb) per range
+  QEntry *queue;             // LDS: queued pairs
+  Cand *cands;               // LDS: drain candidates
+  int qn;                    // queued pairs (wave-uniform)
+  unsigned long long gsnap;  // global keys as last seen (lanes < 16)
+  int wr0, h, cl, lane;
+};
+
+// One 32-column block: prefetch the next block into (bn, nsd), run the MFMA
+// contraction with (bf, sd), prune, queue survivors, sync every few blocks.
+template <int K>
+__device__ __forceinline__ void sweep_block(
+    const Geo &g, const EncBufs &b, WaveState &w, const half8 (&af)[kRB][K / 16],
+    float (&wp)[kSlots], const float (&bbar)[kSlots], const half8 (&bf)[K / 16],
+    float2 sd, half8 (&bn)[K / 16], float2 &nsd, int cb, int c0, int c1) {
+  constexpr int KS = K / 16;
+  const int slot = (cb - c0) % kSync;
+  const int col = cb * 32 + w.cl;
+  {
+    const int ncol = (cb + 1 < c1 ? cb + 1 : cb) * 32 + w.cl;
+    const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * w.h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
+    nsd = b.col_sadp[ncol];
+  }
+  // keep the prefetch ahead of the matrix-core work
+  __builtin_amdgcn_sched_barrier(0);
+
+  f32x16 acc[kRB];
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb) {
+    acc[rb] = f32x16{};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+      acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
+                                                       acc[rb], 0, 0, 0);
+  }
+  const float csa = sd.x, cdp = sd.y;
+
+  // Per (range, domain) pair: the 8 transforms' G are non-negative integers
+  // in FP32, so their bit patterns order like unsigned integers and max/min
+  // need no float canonicalisation.
+  float gmx[kSlots], gmn[kSlots];
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      unsigned ux = __float_as_uint(acc[rb][8 * e]), un = ux;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const unsigned u = __float_as_uint(acc[rb][8 * e + k]);
+        ux = max(ux, u);
+        un = min(un, u);
+      }
+      gmx[2 * rb + e] = __uint_as_float(ux);
+      gmn[2 * rb + e] = __uint_as_float(un);
+    }
+  bool any_pass = false;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s)
+    any_pass |= pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
+
+  if (__any(any_pass)) {
+    // append every passing pair, with its 8 G values, to the wave's queue
+    // (ballot + mbcnt give each lane its position)
+    const int cdom = b.col_dom[col];
+    const double csaa = b.col_saa[col];
+    bool drained = false;
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int s = 2 * rb + e;
+        const bool ps = pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(ps);
+        if (m == 0) continue;
+        if (ps) {
+          const int off = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          QEntry *q = &w.queue[w.qn + off];
+          q->g0 = float4{acc[rb][8 * e], acc[rb][8 * e + 1], acc[rb][8 * e + 2],
+                         acc[rb][8 * e + 3]};
+          q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
+                         acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
+          q->saa = csaa;
+          q->sa = csa;
+          q->dp = cdp;
+          q->dom = cdom;
+          q->lr = 4 * rb + 2 * w.h + e;
+        }
+        w.qn += __popcll(m);
+        if (w.qn >= 64) {
+          drain(w.queue, w.cands, w.qn, w.qn & ~63, w.best, w.rstat, g);
+          drained = true;
+        }
+      }
+    if (drained) refresh_weights(wp, w.best, w.rstat, w.h, g);
+  }
+
+  const int jn = cb - c0 + 1;  // blocks done in this chunk
+  if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
+    // merge the global snapshot taken at the previous sync, publish this
+    // wave's bests with a non-returning atomic and take a new snapshot
+    // (the last block also drains what is left in the queue)
+    if (cb + 1 == c1 && w.qn > 0)
+      drain(w.queue, w.cands, w.qn, w.qn, w.best, w.rstat, g);
+    if (w.lane < kWaveRanges) {
+      const unsigned long long m = min(w.best[w.lane], w.gsnap);
+      w.best[w.lane] = m;
+      if (m < w.gsnap) atomicMin(&b.best[w.wr0 + w.lane], m);
+      w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
+    }
+    refresh_weights(wp, w.best, w.rstat, w.h, g);
+  }
+}
+
 // grid: (chunks, R_pad / 64); block: 4 waves, each owning 16 ranges
 // (4 row blocks of 32 rows = 4 ranges x 8 transforms).  The workgroup sweeps
 // column blocks [cb_begin + x * cb_per_chunk, ...) of 32 domains each.
@@ -184,43 +285,48 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
 // to range 2 h + g / 2 and transform 4 (g mod 2) + q, so accumulators 0..7
 // of lane l hold the 8 transforms of range 2 (l / 32) and accumulators 8..15
 // those of range 2 (l / 32) + 1.
-template <int K>
-__global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
-                                                           int cb_begin,
-                                                           int cb_end,
-                                                           int cb_per_chunk) {
-  constexpr int KS = K / 16;
-  __shared__ unsigned long long s_best[4][kWaveRanges];
-  __shared__ double2 s_rstat[4][kWaveRanges];   // (Sb, Sbb) of each range
-  __shared__ QEntry s_queue[4][kQueue];
-  __shared__ Cand s_cands[4][8 * 64];
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int h = lane >> 5;
-  const int cl = lane & 31;
-  const int wr0 = blockIdx.y * (4 * kWaveRanges) + wave * kWaveRanges;
-  unsigned long long *my_best = s_best[wave];
-  double2 *rstat = s_rstat[wave];
-  QEntry *queue = s_queue[wave];
-  Cand *cands = s_cands[wave];
-  int qn = 0;  // queued survivors (wave-uniform)
+// LDS of one search workgroup.
+struct SearchLds {
+  unsigned long long best[4][kWaveRanges];
+  double2 rstat[4][kWaveRanges];  // (Sb, Sbb) of each range
+  QEntry queue[4][kQueue];
+  Cand cands[4][8 * 64];
+};
 
-  unsigned long long gsnap = ~0ull;  // global keys as last seen
-  if (lane < kWaveRanges) {
-    gsnap = load_best(&b.best[wr0 + lane]);
-    my_best[lane] = gsnap;
-    rstat[lane] = double2{b.rng_sb[wr0 + lane], b.rng_sbb[wr0 + lane]};
+// The workgroup's 64 ranges (row group rg) against column blocks [c0, c1).
+template <int K>
+__device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
+                                            SearchLds &lds, int rg, int c0,
+                                            int c1) {
+  constexpr int KS = K / 16;
+  WaveState w;
+  w.lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  w.h = w.lane >> 5;
+  w.cl = w.lane & 31;
+  w.wr0 = rg * (4 * kWaveRanges) + wave * kWaveRanges;
+  w.best = lds.best[wave];
+  w.rstat = lds.rstat[wave];
+  w.queue = lds.queue[wave];
+  w.cands = lds.cands[wave];
+  w.qn = 0;
+  w.gsnap = ~0ull;
+  if (w.lane < kWaveRanges) {
+    w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
+    w.best[w.lane] = w.gsnap;
+    w.rstat[w.lane] =
+        double2{b.rng_sb[w.wr0 + w.lane], b.rng_sbb[w.wr0 + w.lane]};
   }
 
   half8 af[kRB][KS];
   {
-    const int rho = lane & 31;
+    const int rho = w.lane & 31;
     const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
     const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb) {
       const _Float16 *src =
-          b.aop + ((size_t)(wr0 + 4 * rb + rl) * 8 + iso) * K + 8 * h;
+          b.aop + ((size_t)(w.wr0 + 4 * rb + rl) * 8 + iso) * K + 8 * w.h;
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk)
         af[rb][kk] = *(const half8 *)(src + 16 * kk);
@@ -231,138 +337,81 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   float wp[kSlots], bbar[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
-    bbar[s] = (float)(b.rng_sb[wr0 + 4 * (s >> 1) + 2 * h + (s & 1)] / K);
+    bbar[s] = (float)(b.rng_sb[w.wr0 + 4 * (s >> 1) + 2 * w.h + (s & 1)] / K);
   __builtin_amdgcn_wave_barrier();
-  refresh_weights(wp, my_best, rstat, h, g);
+  refresh_weights(wp, w.best, w.rstat, w.h, g);
 
-  const int c0 = cb_begin + blockIdx.x * cb_per_chunk;
-  const int c1 = min(c0 + cb_per_chunk, cb_end);
   if (c0 >= c1) return;
 
-  half8 bf[KS];
-  float csa, cdp;
-  int cdom;
-  double csaa;
+  // two register buffers for the streamed domain operand, used alternately
+  half8 bA[KS], bB[KS];
+  float2 sdA, sdB;
   {
-    const int col = c0 * 32 + cl;
-    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
+    const int col = c0 * 32 + w.cl;
+    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * w.h;
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bf[kk] = *(const half8 *)(bsrc + 16 * kk);
-    csa = b.col_sa[col];
-    cdp = b.col_dp[col];
-    cdom = b.col_dom[col];
-    csaa = b.col_saa[col];
+    for (int kk = 0; kk < KS; ++kk) bA[kk] = *(const half8 *)(bsrc + 16 * kk);
+    sdA = b.col_sadp[col];
   }
+  for (int cb = c0; cb < c1; cb += 2) {
+    sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
+    if (cb + 1 < c1)
+      sweep_block<K>(g, b, w, af, wp, bbar, bB, sdB, bA, sdA, cb + 1, c0, c1);
+  }
+}
 
-  for (int cb = c0; cb < c1; ++cb) {
-    const int slot = (cb - c0) % kSync;
-    // prefetch the next column block
-    half8 bn[KS];
-    const int ncol = (cb + 1 < c1 ? cb + 1 : cb) * 32 + cl;
-    {
-      const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
+// One image: grid (chunks, R_pad / 64); workgroup (x, y) sweeps row group y
+// against column blocks [cb_begin + x * cb_per_chunk, ...).
+template <int K>
+__global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
+                                                           int cb_begin,
+                                                           int cb_end,
+                                                           int cb_per_chunk) {
+  __shared__ SearchLds lds;
+  const int c0 = cb_begin + blockIdx.x * cb_per_chunk;
+  const int c1 = min(c0 + cb_per_chunk, cb_end);
+  search_rows<K>(g, b, lds, blockIdx.y, c0, c1);
+}
+
+// Many slices: a persistent grid whose workgroups take search items
+// (slice, row group, column blocks) from a shared counter, in the order of
+// the work list (largest slices first).  When a slice's last item is done,
+// the workgroup that finished it records the completion tick (100 MHz).
+template <int K>
+__global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
+  __shared__ SearchLds lds;
+  __shared__ int s_item;
+  if (threadIdx.x == 0)
+    atomicMin(&bd.ticks[0], (unsigned long long)wall_clock64());
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(bd.counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    if (it >= bd.n_items) break;
+    const int4 w = bd.items[it];
+    const SliceDesc &d = bd.tab[w.x];
+    search_rows<K>(d.g, d.b, lds, w.y, w.z, w.w);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      if (atomicSub(&bd.remaining[w.x], 1) == 1)
+        bd.ticks[1 + w.x] = (unsigned long long)wall_clock64();
     }
-    const float nsa = b.col_sa[ncol], ndp = b.col_dp[ncol];
-    const int ndom = b.col_dom[ncol];
-    const double nsaa = b.col_saa[ncol];
-
-    f32x16 acc[kRB];
-#pragma unroll
-    for (int rb = 0; rb < kRB; ++rb) {
-      acc[rb] = f32x16{};
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk)
-        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
-                                                         acc[rb], 0, 0, 0);
-    }
-
-    // Per (range, domain) pair: the 8 transforms' G are non-negative
-    // integers in FP32, so their bit patterns order like unsigned integers
-    // and max/min need no float canonicalisation.
-    float gmx[kSlots], gmn[kSlots];
-#pragma unroll
-    for (int rb = 0; rb < kRB; ++rb)
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        unsigned ux = __float_as_uint(acc[rb][8 * e]), un = ux;
-#pragma unroll
-        for (int k = 1; k < 8; ++k) {
-          const unsigned u = __float_as_uint(acc[rb][8 * e + k]);
-          ux = max(ux, u);
-          un = min(un, u);
-        }
-        gmx[2 * rb + e] = __uint_as_float(ux);
-        gmn[2 * rb + e] = __uint_as_float(un);
-      }
-    bool any_pass = false;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      any_pass |= pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
-
-    if (__any(any_pass)) {
-      // append every passing pair, with its 8 G values, to the wave's queue
-      // (ballot + mbcnt give each lane its position)
-      bool drained = false;
-#pragma unroll
-      for (int rb = 0; rb < kRB; ++rb)
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          const int s = 2 * rb + e;
-          const bool ps =
-              pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
-          const unsigned long long m = __builtin_amdgcn_ballot_w64(ps);
-          if (m == 0) continue;
-          if (ps) {
-            const int off = __builtin_amdgcn_mbcnt_hi(
-                (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
-            QEntry *q = &queue[qn + off];
-            q->g0 = float4{acc[rb][8 * e], acc[rb][8 * e + 1],
-                           acc[rb][8 * e + 2], acc[rb][8 * e + 3]};
-            q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
-                           acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
-            q->saa = csaa;
-            q->sa = csa;
-            q->dp = cdp;
-            q->dom = cdom;
-            q->lr = 4 * rb + 2 * h + e;
-          }
-          qn += __popcll(m);
-          if (qn >= 64) {
-            drain(queue, cands, qn, qn & ~63, my_best, rstat, g);
-            drained = true;
-          }
-        }
-      if (drained) refresh_weights(wp, my_best, rstat, h, g);
-    }
-
-    const int jn = cb - c0 + 1;  // blocks done in this chunk
-    if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
-      // merge the global snapshot taken at the previous sync, publish this
-      // wave's bests with a non-returning atomic and take a new snapshot
-      // (the last block also drains what is left in the queue)
-      if (cb + 1 == c1 && qn > 0)
-        drain(queue, cands, qn, qn, my_best, rstat, g);
-      if (lane < kWaveRanges) {
-        const unsigned long long m = min(my_best[lane], gsnap);
-        my_best[lane] = m;
-        if (m < gsnap) atomicMin(&b.best[wr0 + lane], m);
-        gsnap = load_best(&b.best[wr0 + lane]);
-      }
-      refresh_weights(wp, my_best, rstat, h, g);
-    }
-
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bf[kk] = bn[kk];
-    csa = nsa;
-    cdp = ndp;
-    cdom = ndom;
-    csaa = nsaa;
   }
 }
 
 }  // namespace
+
+hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st) {
+  if (bd.bits != 8) return hipErrorInvalidValue;
+  if (bd.n_items <= 0) return hipSuccess;
+  // about two workgroups per compute unit (256 CUs)
+  const int grid = bd.n_items < 512 ? bd.n_items : 512;
+  auto kern = bd.rsize == 8 ? k_search_batch_u8<64> : k_search_batch_u8<16>;
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, bd);
+  return hipGetLastError();
+}
 
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
                               int seeded_blocks, hipStream_t st) {
@@ -371,6 +420,8 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
   const int rg = g.R_pad / kMfmaRangesPerWG;
   const int rest = g.NCB - seeded_blocks;
   if (rest <= 0) return hipSuccess;
+  if (chunks > rest) chunks = rest;
+  if (chunks < 1) chunks = 1;
   const int cbpc = (rest + chunks - 1) / chunks;
   const int nchunks = (rest + cbpc - 1) / cbpc;
   auto kern = g.K == 64 ? k_search_mfma_u8<64> : k_search_mfma_u8<16>;

@@ -1,0 +1,333 @@
+// fic_search_mfma12.hip -- the matrix-core search for 12-bit images.
+//
+// 12-bit pixels (<= 4095) and their 2x2 cell sums (<= 16380) are not exact in
+// FP16, so both operands are split: b = 64 b_hi + b_lo (6 + 6 bits) and
+// A = 128 A_hi + A_lo (7 + 7 bits).  Then
+//     G = sum A b = 8192 G_hh + 64 M + G_ll,
+//     G_hh = sum A_hi b_hi,  G_ll = sum A_lo b_lo,
+//     M    = sum (A_hi * 2 b_lo + A_lo * b_hi),
+// where every partial sum is an integer below 64 * 127 * 189 < 2^24, so three
+// FP16 MFMA chains with FP32 accumulation give the three partials exactly
+// (M runs over K' = 2K products).  The factor 2 is applied to the streamed
+// A_hi fragment with packed FP16 adds (exact: values <= 254).
+//
+// The prune uses G rebuilt in FP32 (rounding error below 2^-22 G) with a
+// matching margin; queued pairs carry G rebuilt exactly in FP64, and drains
+// test and fit in FP64.  One row block (4 ranges x 8 transforms) per wave.
+#include <math.h>
+
+#include "fic_search_common.h"
+
+namespace fic {
+
+namespace {
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWR = 4;      // ranges per wave (one row block)
+constexpr int kSync = 4;    // column blocks between global syncs
+constexpr int kQueue = 128; // pairs; >= 63 + 64 lanes
+
+struct __attribute__((aligned(16))) QEntry12 {
+  double g[8];  // exact G of the 8 transforms
+  double saa;
+  float sa, dp;
+  int dom, lr;
+  int pad[2];
+};
+
+
+// Exact-safe test of one candidate in FP64: G - SA Sb/K is exact in double,
+// t = W' D' is rounded down.
+__device__ __forceinline__ bool passes_exact(double G, double sa, double Sb,
+                                             double K, float t) {
+  const double a = G - sa * Sb / K;
+  return a * a >= (double)t;
+}
+
+// Surviving transforms are listed as pair index << 3 | transform.
+__device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
+                                        int &qn, int n,
+                                        unsigned long long *best,
+                                        const double2 *rstat, const Geo &g) {
+  const int lane = threadIdx.x & 63;
+  const double K = (double)g.K;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    int nc = 0;
+    {
+      double gv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      unsigned pass = 0;
+      if (i < n) {
+        const QEntry12 &q = queue[i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gv[k] = q.g[k];
+        const double2 rs = rstat[q.lr];
+        const float t =
+            weight_from_key(best[q.lr], K * rs.y - rs.x * rs.x, g) * q.dp;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          pass |= passes_exact(gv[k], (double)q.sa, rs.x, K, t) ? (1u << k) : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool f = (pass >> k) & 1u;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(f);
+        if (f) {
+          const int off = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          cands[nc + off] = ((unsigned)i << 3) | k;
+        }
+        nc += __popcll(m);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int c = lane; c < nc; c += 64) {
+      const unsigned pk = cands[c];
+      const QEntry12 &q = queue[pk >> 3];
+      const double2 rs = rstat[q.lr];
+      const Fit f = fit_exact(q.g[pk & 7], (double)q.sa, q.saa, rs.x, rs.y, g);
+      atomicMin(&best[q.lr], make_key(f.err, 8ll * q.dom + (pk & 7), g));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const int rem = qn - n;
+  static_assert(sizeof(QEntry12) == 96, "entry is six 16-byte words");
+  uint4 t[6];
+#pragma unroll
+  for (int w = 0; w < 6; ++w) t[w] = uint4{0, 0, 0, 0};
+  if (lane < rem) {
+    const uint4 *src = (const uint4 *)&queue[n + lane];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) t[w] = src[w];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rem) {
+    uint4 *dst = (uint4 *)&queue[lane];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) dst[w] = t[w];
+  }
+  qn = rem;
+}
+
+// grid: (chunks, R_pad / 16); block: 4 waves of 4 ranges each.  Same lane
+// layout as the 8-bit kernel: accumulator v of lane l holds transform v mod 8
+// of range 2 (l / 32) + v / 8 of the wave, for domain column l mod 32.
+template <int K>
+__global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
+                                                           int cb_begin,
+                                                           int cb_end,
+                                                           int cb_per_chunk) {
+  constexpr int KS = K / 16;
+  __shared__ unsigned long long s_best[4][kWR];
+  __shared__ double2 s_rstat[4][kWR];
+  __shared__ QEntry12 s_queue[4][kQueue];
+  __shared__ unsigned s_cands[4][8 * 64];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int cl = lane & 31;
+  const int wr0 = blockIdx.y * (4 * kWR) + wave * kWR;
+  unsigned long long *my_best = s_best[wave];
+  double2 *rstat = s_rstat[wave];
+  QEntry12 *queue = s_queue[wave];
+  unsigned *cands = s_cands[wave];
+  int qn = 0;
+  const double Kd = (double)g.K;
+
+  unsigned long long gsnap = ~0ull;
+  if (lane < kWR) {
+    gsnap = load_best(&b.best[wr0 + lane]);
+    my_best[lane] = gsnap;
+    rstat[lane] = double2{b.rng_sb[wr0 + lane], b.rng_sbb[wr0 + lane]};
+  }
+
+  const size_t aplane = (size_t)g.R_pad * 8 * K;
+  const size_t bplane = (size_t)g.NC_pad * K;
+  half8 ah[KS], al[KS];
+  {
+    const int rho = lane & 31;
+    const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
+    const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
+    const _Float16 *src = b.aop + ((size_t)(wr0 + rl) * 8 + iso) * K + 8 * h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      ah[kk] = *(const half8 *)(src + 16 * kk);
+      al[kk] = *(const half8 *)(src + aplane + 16 * kk);
+    }
+  }
+
+  float wp[2], bbar[2];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double2 rs = rstat[2 * h + e];
+    bbar[e] = (float)(rs.x / Kd);
+    wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+  }
+
+  const int c0 = cb_begin + blockIdx.x * cb_per_chunk;
+  const int c1 = min(c0 + cb_per_chunk, cb_end);
+  if (c0 >= c1) return;
+
+  half8 bh[KS], bl[KS];
+  float csa, cdp;
+  int cdom;
+  double csaa;
+  {
+    const int col = c0 * 32 + cl;
+    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      bh[kk] = *(const half8 *)(bsrc + 16 * kk);
+      bl[kk] = *(const half8 *)(bsrc + bplane + 16 * kk);
+    }
+    const float2 sadp = b.col_sadp[col];
+    csa = sadp.x;
+    cdp = sadp.y;
+    cdom = b.col_dom[col];
+    csaa = b.col_saa[col];
+  }
+
+  for (int cb = c0; cb < c1; ++cb) {
+    const int slot = (cb - c0) % kSync;
+    half8 bhn[KS], bln[KS];
+    const int ncol = (cb + 1 < c1 ? cb + 1 : cb) * 32 + cl;
+    {
+      const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        bhn[kk] = *(const half8 *)(bsrc + 16 * kk);
+        bln[kk] = *(const half8 *)(bsrc + bplane + 16 * kk);
+      }
+    }
+    const float2 nsadp = b.col_sadp[ncol];
+    const float nsa = nsadp.x, ndp = nsadp.y;
+    const int ndom = b.col_dom[ncol];
+    const double nsaa = b.col_saa[ncol];
+
+    f32x16 ghh = f32x16{}, gmid = f32x16{}, gll = f32x16{};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const half8 b2 = bh[kk] + bh[kk];
+      ghh = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[kk], bh[kk], ghh, 0, 0, 0);
+      gll = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[kk], bl[kk], gll, 0, 0, 0);
+      gmid = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[kk], b2, gmid, 0, 0, 0);
+      gmid = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[kk], bl[kk], gmid, 0, 0, 0);
+    }
+
+    // G in FP32 (non-negative), max/min over the 8 transforms on bit patterns
+    f32x16 gap;
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      gap[v] = fmaf(8192.0f, ghh[v], fmaf(64.0f, gmid[v], gll[v]));
+    float gmx[2], gmn[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      unsigned ux = __float_as_uint(gap[8 * e]), un = ux;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const unsigned u = __float_as_uint(gap[8 * e + k]);
+        ux = max(ux, u);
+        un = min(un, u);
+      }
+      gmx[e] = __uint_as_float(ux);
+      gmn[e] = __uint_as_float(un);
+    }
+    bool ps[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float a0 = fmaf(-csa, bbar[e], gmx[e]);
+      const float a1 = fmaf(-csa, bbar[e], gmn[e]);
+      // margin for the FP32 rebuild of G and the rounding of a
+      const float mm = fmaf(fmaxf(fabsf(a0), fabsf(a1)), 1.0f + 0x1p-20f,
+                            gmx[e] * 0x1p-20f);
+      ps[e] = mm * mm >= wp[e] * cdp;
+    }
+
+    if (__any(ps[0] || ps[1])) {
+      bool drained = false;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(ps[e]);
+        if (m == 0) continue;
+        if (ps[e]) {
+          const int off = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          QEntry12 *q = &queue[qn + off];
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            q->g[k] = fma(8192.0, (double)ghh[8 * e + k],
+                          fma(64.0, (double)gmid[8 * e + k],
+                              (double)gll[8 * e + k]));
+          q->saa = csaa;
+          q->sa = csa;
+          q->dp = cdp;
+          q->dom = cdom;
+          q->lr = 2 * h + e;
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+          drain12(queue, cands, qn, qn & ~63, my_best, rstat, g);
+          drained = true;
+        }
+      }
+      if (drained) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double2 rs = rstat[2 * h + e];
+          wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+        }
+      }
+    }
+
+    const int jn = cb - c0 + 1;
+    if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
+      if (cb + 1 == c1 && qn > 0)
+        drain12(queue, cands, qn, qn, my_best, rstat, g);
+      if (lane < kWR) {
+        const unsigned long long m = min(my_best[lane], gsnap);
+        my_best[lane] = m;
+        if (m < gsnap) atomicMin(&b.best[wr0 + lane], m);
+        gsnap = load_best(&b.best[wr0 + lane]);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double2 rs = rstat[2 * h + e];
+        wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+      }
+    }
+
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      bh[kk] = bhn[kk];
+      bl[kk] = bln[kk];
+    }
+    csa = nsa;
+    cdp = ndp;
+    cdom = ndom;
+    csaa = nsaa;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
+                                int seeded_blocks, hipStream_t st) {
+  if (g.bits != 12) return hipErrorInvalidValue;
+  static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
+  const int rg = g.R_pad / (4 * kWR);
+  const int rest = g.NCB - seeded_blocks;
+  if (rest <= 0) return hipSuccess;
+  if (chunks > rest) chunks = rest;
+  if (chunks < 1) chunks = 1;
+  const int cbpc = (rest + chunks - 1) / chunks;
+  const int nchunks = (rest + cbpc - 1) / cbpc;
+  auto kern = g.K == 64 ? k_search_mfma_12<64> : k_search_mfma_12<16>;
+  hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b,
+                     seeded_blocks, g.NCB, cbpc);
+  return hipGetLastError();
+}
+
+}  // namespace fic

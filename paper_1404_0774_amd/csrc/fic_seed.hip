@@ -21,65 +21,87 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
 // grid: R_pad / 8 workgroups; block: 256 threads.  Thread t owns row
 // (range t / 32, transform (t / 4) mod 8) of the range operand and columns
-// 8 (t mod 4) .. +7 of each 32-column block.
-template <int K>
-__global__ __launch_bounds__(256) void k_seed_dense_u8(Geo g, EncBufs b,
-                                                       int nblocks) {
+// 8 (t mod 4) .. +7 of each 32-column block.  B12: 12-bit operands in two
+// planes (b = 64 b_hi + b_lo, A = 128 A_hi + A_lo); the four partial sums
+// are exact in FP32 and G is rebuilt exactly in FP64.  Both operands are
+// staged in LDS as FP16 pairs.
+template <int K, bool B12>
+__device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
+                                                int nblocks, int bid) {
   constexpr int KP = K / 2;                       // half2 pairs per row
-  __shared__ __attribute__((aligned(16))) half2_t sB[KP][32];
+  constexpr int NP = B12 ? 2 : 1;                 // operand planes
+  constexpr int PER = K / 8;                      // 16-byte words per row
+  __shared__ __attribute__((aligned(16))) half2_t sA[NP][KP][64];
+  __shared__ __attribute__((aligned(16))) half2_t sB[NP][KP][32];
   __shared__ float s_sa[32], s_dp[32];
   __shared__ double s_saa[32];
   __shared__ int s_dom[32];
   const int t = threadIdx.x;
   const int row = t >> 2, cgp = t & 3;
   const int rl = row >> 3, k = row & 7;
-  const int r = blockIdx.x * 8 + rl;
+  const int r = bid * 8 + rl;
 
-  half2_t a[KP];
-  {
-    const half8_t *src = (const half8_t *)(b.aop + ((size_t)r * 8 + k) * K);
+  // the workgroup's 64 rows (8 ranges x 8 transforms) of the range operand
+  for (int i = t; i < NP * 64 * PER; i += 256) {
+    const int pl = i / (64 * PER), ii = i % (64 * PER);
+    const int rw = ii / PER, p0 = (ii % PER) * 8;
+    const half8_t v = *(const half8_t *)(b.aop + (size_t)pl * g.R_pad * 8 * K +
+                                         ((size_t)bid * 64 + rw) * K + p0);
 #pragma unroll
-    for (int i = 0; i < K / 8; ++i) {
-      const half8_t v = src[i];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) a[4 * i + e] = half2_t{v[2 * e], v[2 * e + 1]};
-    }
+    for (int e = 0; e < 4; ++e)
+      sA[pl][p0 / 2 + e][rw] = half2_t{v[2 * e], v[2 * e + 1]};
   }
   const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
   unsigned long long best = ~0ull;
 
   for (int cb = 0; cb < nblocks; ++cb) {
     __syncthreads();
-    {
-      // stage the block: thread t loads 8 cell sums of column t / (K / 8)
-      constexpr int PER = K / 8;
-      for (int i = t; i < 32 * PER; i += 256) {
-        const int col = i / PER, p0 = (i % PER) * 8;
-        const half8_t v =
-            *(const half8_t *)(b.bop + ((size_t)cb * 32 + col) * K + p0);
+    for (int i = t; i < NP * 32 * PER; i += 256) {
+      const int pl = i / (32 * PER), ii = i % (32 * PER);
+      const int col = ii / PER, p0 = (ii % PER) * 8;
+      const half8_t v = *(const half8_t *)(b.bop + (size_t)pl * g.NC_pad * K +
+                                           ((size_t)cb * 32 + col) * K + p0);
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          sB[p0 / 2 + e][col] = half2_t{v[2 * e], v[2 * e + 1]};
-      }
-      if (t < 32) {
-        const int col = cb * 32 + t;
-        s_sa[t] = b.col_sa[col];
-        s_dp[t] = b.col_dp[col];
-        s_saa[t] = b.col_saa[col];
-        s_dom[t] = b.col_dom[col];
-      }
+      for (int e = 0; e < 4; ++e)
+        sB[pl][p0 / 2 + e][col] = half2_t{v[2 * e], v[2 * e + 1]};
+    }
+    if (t < 32) {
+      const int col = cb * 32 + t;
+      const float2 sadp = b.col_sadp[col];
+      s_sa[t] = sadp.x;
+      s_dp[t] = sadp.y;
+      s_saa[t] = b.col_saa[col];
+      s_dom[t] = b.col_dom[col];
     }
     __syncthreads();
 
-    float acc[8];
+    // acc[x][y][c]: range plane x against domain plane y, column c
+    float acc[NP][NP][8];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+    for (int x = 0; x < NP; ++x)
 #pragma unroll
+      for (int y = 0; y < NP; ++y)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[x][y][c] = 0.0f;
+#pragma unroll 4
     for (int pp = 0; pp < KP; ++pp) {
-      const half2_t *bp = &sB[pp][8 * cgp];
+      half2_t av[NP];
 #pragma unroll
-      for (int c = 0; c < 8; ++c)
-        acc[c] = __builtin_amdgcn_fdot2(a[pp], bp[c], acc[c], false);
+      for (int x = 0; x < NP; ++x) av[x] = sA[x][pp][row];
+#pragma unroll
+      for (int y = 0; y < NP; ++y) {
+        const half8_t b0 = *(const half8_t *)&sB[y][pp][8 * cgp];
+        const half8_t b1 = *(const half8_t *)&sB[y][pp][8 * cgp + 4];
+        const half2_t bv[8] = {half2_t{b0[0], b0[1]}, half2_t{b0[2], b0[3]},
+                               half2_t{b0[4], b0[5]}, half2_t{b0[6], b0[7]},
+                               half2_t{b1[0], b1[1]}, half2_t{b1[2], b1[3]},
+                               half2_t{b1[4], b1[5]}, half2_t{b1[6], b1[7]}};
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+#pragma unroll
+          for (int x = 0; x < NP; ++x)
+            acc[x][y][c] = __builtin_amdgcn_fdot2(av[x], bv[c], acc[x][y][c], false);
+      }
     }
 
 #pragma unroll
@@ -87,8 +109,12 @@ __global__ __launch_bounds__(256) void k_seed_dense_u8(Geo g, EncBufs b,
       const int cc = 8 * cgp + c;
       // flat domains are seeded separately; padding columns are not domains
       if (s_dp[cc] == __builtin_inff()) continue;
-      const Fit f = fit_exact((double)acc[c], (double)s_sa[cc], s_saa[cc], Sb,
-                              Sbb, g);
+      // 12-bit: G = 8192 G_hh + 128 G_(A_hi b_lo) + 64 G_(A_lo b_hi) + G_ll
+      const double G =
+          B12 ? 8192.0 * acc[0][0][c] + 128.0 * acc[1][0][c] +
+                    64.0 * acc[0][NP - 1][c] + (double)acc[NP - 1][NP - 1][c]
+              : (double)acc[0][0][c];
+      const Fit f = fit_exact(G, (double)s_sa[cc], s_saa[cc], Sb, Sbb, g);
       const unsigned long long key =
           make_key(f.err, 8ll * s_dom[cc] + k, g);
       best = key < best ? key : best;
@@ -104,19 +130,50 @@ __global__ __launch_bounds__(256) void k_seed_dense_u8(Geo g, EncBufs b,
   if ((t & 31) == 0 && r < g.R && best < b.best[r]) b.best[r] = best;
 }
 
+template <int K, bool B12>
+__global__ __launch_bounds__(256) void k_seed_dense(Geo g, EncBufs b,
+                                                    int nblocks) {
+  seed_dense_body<K, B12>(g, b, nblocks, blockIdx.x);
+}
+
+template <int K, bool B12>
+__global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
+  const int *off = bd.phase_off + 2 * (bd.n + 1);
+  int lo = 0, hi = bd.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (off[mid] <= (int)blockIdx.x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const SliceDesc &d = bd.tab[lo];
+  const int nb = min(nblocks, d.seed_blocks);
+  if (nb > 0) seed_dense_body<K, B12>(d.g, d.b, nb, blockIdx.x - off[lo]);
+}
+
 }  // namespace
+
+hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  auto kern = bd.bits == 12 ? (bd.rsize == 8 ? k_seed_batch<64, true>
+                                             : k_seed_batch<16, true>)
+                            : (bd.rsize == 8 ? k_seed_batch<64, false>
+                                             : k_seed_batch<16, false>);
+  hipLaunchKernelGGL(kern, dim3(bd.phase_total[2]), dim3(256), 0, st, bd,
+                     nblocks);
+  return hipGetLastError();
+}
 
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st) {
-  if (g.bits != 8) return hipErrorInvalidValue;
   if (nblocks <= 0) return hipSuccess;
   const dim3 grid(g.R_pad / 8);
-  if (g.K == 64)
-    hipLaunchKernelGGL(k_seed_dense_u8<64>, grid, dim3(256), 0, st, g, b,
-                       nblocks);
-  else
-    hipLaunchKernelGGL(k_seed_dense_u8<16>, grid, dim3(256), 0, st, g, b,
-                       nblocks);
+  auto kern = g.bits == 12 ? (g.K == 64 ? k_seed_dense<64, true>
+                                        : k_seed_dense<16, true>)
+                           : (g.K == 64 ? k_seed_dense<64, false>
+                                        : k_seed_dense<16, false>);
+  hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, g, b, nblocks);
   return hipGetLastError();
 }
 

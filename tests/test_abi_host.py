@@ -25,7 +25,8 @@ def declared_functions():
 
 def test_exports_every_declared_symbol():
     names = declared_functions()
-    assert {"fic_query", "fic_encode", "fic_decode", "fic_decode_backward",
+    assert {"fic_query", "fic_encode", "fic_decode", "fic_decode_backward", "fic_refine",
+            "fic_refine_workspace", "fic_timing_begin", "fic_timing_end",
             "fic_status_string", "fic_last_error"} <= set(names)
     L = F.lib()
     for n in names:
@@ -93,8 +94,129 @@ def test_decode_validates_before_gpu_work():
                                  fake, fake, 0, None) == 3
 
 
+def test_refine_validates_before_gpu_work():
+    L = F.lib()
+    p = F.Params(64, 64, 8, 4, 4).c()
+    fake = ctypes.c_void_p(1 << 20)
+    nbytes = ctypes.c_size_t()
+    assert L.fic_refine_workspace(ctypes.byref(p), 12, ctypes.byref(nbytes)) == 0
+    assert nbytes.value >= 13 * 64 * 64 * 4
+    assert L.fic_refine_workspace(ctypes.byref(p), -1, ctypes.byref(nbytes)) == 1
+    args = [fake, fake, fake, fake, fake, 12, ctypes.c_float(128), 50, ctypes.c_float(5e-3),
+            ctypes.c_float(0.5), fake, fake, nbytes.value, None]
+    bad = list(args); bad[0] = None
+    assert L.fic_refine(ctypes.byref(p), *bad) == 1
+    bad = list(args); bad[7] = -1
+    assert L.fic_refine(ctypes.byref(p), *bad) == 1
+    bad = list(args); bad[8] = ctypes.c_float(-1.0)
+    assert L.fic_refine(ctypes.byref(p), *bad) == 1
+    bad = list(args); bad[12] = 16
+    assert L.fic_refine(ctypes.byref(p), *bad) == 3
+
+
 def test_status_strings():
     L = F.lib()
     for s in range(5):
         assert L.fic_status_string(s)
     assert L.fic_status_string(99) == b"unknown status"
+
+
+def test_batch_query_validation():
+    L = F.lib()
+    P = _lib._Params
+    nbytes = ctypes.c_size_t()
+    ok = (P * 2)(F.Params(64, 64, 8, 8, 8).c(), F.Params(128, 96, 8, 8, 4).c())
+    assert L.fic_batch_query(ok, 2, ctypes.byref(nbytes)) == 0 and nbytes.value > 0
+    mixed = (P * 2)(F.Params(64, 64, 8, 8, 8).c(), F.Params(64, 64, 8, 4, 8).c())
+    assert L.fic_batch_query(mixed, 2, ctypes.byref(nbytes)) == 1
+    twelve = (P * 1)(F.Params(64, 64, 12, 8, 8).c())
+    assert L.fic_batch_query(twelve, 1, ctypes.byref(nbytes)) == 2
+    assert L.fic_batch_query(ok, 0, ctypes.byref(nbytes)) == 1
+    bad = (P * 1)(F.Params(60, 64, 8, 8, 8).c())
+    assert L.fic_batch_query(bad, 1, ctypes.byref(nbytes)) == 1
+    fake = ctypes.c_void_p(1 << 20)
+    assert L.fic_encode_batch(ok, 2, fake, 16, None, None) in (1, 3)
+
+
+@pytest.fixture
+def clean_tuning():
+    """Run with an empty launch-shape table; restore the shipped one after."""
+    F.set_tuning([])
+    yield
+    if os.path.exists(_lib.TUNING_PATH):
+        F.load_tuning(_lib.TUNING_PATH)
+    else:
+        F.set_tuning([])
+
+
+def test_tuning_defaults(clean_tuning):
+    # 512x512, n = 8, STEP 4: 4096 ranges = 64 row groups, 15,625 domains in
+    # 489 column blocks -> about two workgroups per CU (512 / 64 = 8 chunks)
+    t = F.get_tuning(F.Params(512, 512, 8, 8, 4))
+    assert t == dict(bit_depth=8, range_size=8, method=0, min_domains=15625,
+                     col_chunks=8, seed_blocks=1, item_blocks=16)
+    # 12-bit matrix-core search uses 16-range row groups: 256 groups -> 2 chunks
+    t12 = F.get_tuning(F.Params(512, 512, 12, 8, 2))
+    assert t12["col_chunks"] == 2 and t12["seed_blocks"] == 1
+    # fewer than 16 column blocks: no seed pass; chunks clamped to the blocks
+    t1 = F.get_tuning(F.Params(64, 64, 8, 4, 4))   # 225 domains -> 8 blocks
+    assert t1["seed_blocks"] == 0 and t1["col_chunks"] == 8
+
+
+def test_tuning_table_selection(clean_tuning):
+    p = F.Params(512, 512, 8, 8, 4)
+    F.set_tuning([dict(bit_depth=8, range_size=8, method=0, min_domains=0, col_chunks=4),
+                  dict(bit_depth=8, range_size=8, method=0, min_domains=10000, col_chunks=12,
+                       seed_blocks=2, item_blocks=8),
+                  dict(bit_depth=8, range_size=8, method=0, min_domains=20000, col_chunks=3),
+                  dict(bit_depth=8, range_size=8, method=1, min_domains=0, col_chunks=5)])
+    t = F.get_tuning(p)
+    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (12, 2, 8)
+    p.method = F.METHOD_DIRECT
+    t = F.get_tuning(p)
+    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (5, 1, 16)
+    small = F.Params(128, 128, 8, 8, 4)              # 841 domains: first entry
+    assert F.get_tuning(small)["col_chunks"] == 4
+    # clamping: seed below the block count, chunks within what is left
+    F.set_tuning([dict(bit_depth=8, range_size=4, method=0, col_chunks=4096, seed_blocks=64)])
+    t = F.get_tuning(F.Params(64, 64, 8, 4, 4))      # 8 column blocks
+    assert t["seed_blocks"] == 7 and t["col_chunks"] == 1
+    F.set_tuning([])
+    assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 8
+
+
+@pytest.mark.parametrize("field,value", [("bit_depth", 10), ("range_size", 6), ("method", 2),
+                                         ("min_domains", -1), ("col_chunks", -1),
+                                         ("col_chunks", 5000), ("seed_blocks", -2),
+                                         ("seed_blocks", 65), ("item_blocks", -3)])
+def test_tuning_rejects_bad_entries(clean_tuning, field, value):
+    F.set_tuning([dict(bit_depth=8, range_size=8, method=0, col_chunks=6)])
+    e = dict(bit_depth=8, range_size=8, method=0)
+    e[field] = value
+    with pytest.raises(F.FicError) as ex:
+        F.set_tuning([e])
+    assert ex.value.status == 1
+    # the table is unchanged after a rejected call
+    assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 6
+
+
+def test_tuning_json(clean_tuning, tmp_path):
+    good = tmp_path / "t.json"
+    good.write_text('{"device": "any", "entries": [\n'
+                    ' {"bit_depth": 8, "range_size": 8, "method": 0, "min_domains": 0,\n'
+                    '  "col_chunks": 6, "seed_blocks": 2, "item_blocks": 32, "ms": 0.16,\n'
+                    '  "sweep": [1, 2, {"x": null}], "ok": true}\n], "note": "a \\"quoted\\" word"}')
+    F.load_tuning(str(good))
+    t = F.get_tuning(F.Params(512, 512, 8, 8, 4))
+    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (6, 2, 32)
+    for bad in ['{"entries": [{"bit_depth": 8, "range_size": 8, "method": 0,}]}',
+                '{"entries": [{"bit_depth": 8, "range_size": 8, "method": 0, "col_chunks": 1.5}]}',
+                '{"entries": [{"bit_depth": 9, "range_size": 8, "method": 0}]}',
+                '{"entries": [', '[] x']:
+        f = tmp_path / "bad.json"
+        f.write_text(bad)
+        with pytest.raises(F.FicError):
+            F.load_tuning(str(f))
+        assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 6
+    with pytest.raises(F.FicError):
+        F.load_tuning(str(tmp_path / "missing.json"))

@@ -95,3 +95,53 @@ def test_zero_iterations():
     gs, go = F.decode_backward(dev(d, torch.int32), dev(k, torch.uint8), sd, od, traj,
                                torch.ones_like(traj[0]), p)
     assert bool((gs == 0).all()) and bool((go == 0).all())
+
+
+def _adam_reference(s, o, gs, go, lr_s, lr_o, t=1, b1=0.9, b2=0.999, eps=1e-8):
+    m_s, v_s = (1 - b1) * gs, (1 - b2) * gs * gs
+    m_o, v_o = (1 - b1) * go, (1 - b2) * go * go
+    c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+    s1 = np.clip(s - lr_s * (m_s / c1) / (np.sqrt(v_s / c2) + eps), -0.999, 0.999)
+    o1 = o - lr_o * (m_o / c1) / (np.sqrt(v_o / c2) + eps)
+    return s1, o1
+
+
+def test_refine_one_step_is_adam_on_adjoint_gradient():
+    H = W = 64
+    n, step, T = 4, 4, 12
+    img, d, k, s, o = codes_for(H, W, n, step, 35)
+    p = F.Params(H, W, 8, n, step)
+    dd, kk = dev(d, torch.int32), dev(k, torch.uint8)
+    s0, o0 = dev(s, torch.float32), dev(o, torch.float32)
+    timg = torch.from_numpy(img).cuda()
+    traj = F.decode(dd, kk, s0, o0, p, T, 128.0)
+    g = 2.0 * (traj[-1] - timg.float()) / (H * W)
+    gs, go = F.decode_backward(dd, kk, s0, o0, traj, g, p)
+    s1, o1 = s0.clone(), o0.clone()
+    loss = F.refine(dd, kk, s1, o1, timg, p, iters=T, steps=1, lr_s=5e-3, lr_o=0.5)
+    rs, ro = _adam_reference(s0.cpu().numpy().astype(np.float64), o0.cpu().numpy().astype(np.float64),
+                             gs.cpu().numpy().astype(np.float64), go.cpu().numpy().astype(np.float64),
+                             5e-3, 0.5)
+    np.testing.assert_allclose(s1.cpu().numpy(), rs, rtol=0, atol=1e-5)
+    np.testing.assert_allclose(o1.cpu().numpy(), ro, rtol=0, atol=1e-4)
+    mse0 = float(((traj[-1].double() - timg.double()) ** 2).mean())
+    assert abs(float(loss[0]) - mse0) <= 1e-9 * max(1.0, mse0)
+
+
+def test_refine_lowers_attractor_error_and_is_reproducible():
+    H = W = 64
+    n, step, T = 4, 4, 12
+    img, d, k, s, o = codes_for(H, W, n, step, 36)
+    p = F.Params(H, W, 8, n, step)
+    dd, kk = dev(d, torch.int32), dev(k, torch.uint8)
+    timg = torch.from_numpy(img).cuda()
+    runs = []
+    for _ in range(2):
+        s1, o1 = dev(s, torch.float32), dev(o, torch.float32)
+        loss = F.refine(dd, kk, s1, o1, timg, p, iters=T, steps=50)
+        runs.append((s1.cpu(), o1.cpu(), loss.cpu()))
+    loss = runs[0][2].numpy()
+    assert loss[-1] < loss[0]
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    assert torch.equal(runs[0][2], runs[1][2])
+    assert bool((runs[0][0].abs() <= 0.999).all())

@@ -114,3 +114,53 @@ def test_deterministic_repeat():
     a = gpu_encode(img, 8, 2, 8, F.METHOD_MFMA)
     for _ in range(3):
         assert_same(gpu_encode(img, 8, 2, 8, F.METHOD_MFMA), a, "repeat")
+
+
+# --- 12-bit images: hi/lo split contraction ---------------------------------
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("H,W,n,step,seed", [
+    (48, 64, 4, 2, 41),     # 192 ranges, ragged tiles
+    (64, 64, 8, 4, 42),
+    (40, 56, 4, 3, 43),
+])
+def test_parity_12bit_small(method, H, W, n, step, seed):
+    img = gen_image(H, W, 12, seed)
+    assert_same(gpu_encode(img, n, step, 12, method), O.encode(img, n, step, bits=12), f"12b {H}x{W}")
+
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("kind", ["zeros", "max", "noise", "checker"])
+def test_parity_12bit_degenerate(method, kind):
+    H = W = 48
+    rng = np.random.default_rng(7)
+    img = {"zeros": np.zeros((H, W)), "max": np.full((H, W), 4095),
+           "noise": rng.integers(0, 4096, (H, W)),
+           "checker": (np.indices((H, W)).sum(0) % 2) * 4095}[kind].astype(np.uint16)
+    for (n, step) in [(4, 4), (8, 2)]:
+        assert_same(gpu_encode(img, n, step, 12, method), O.encode(img, n, step, bits=12), kind)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_planted_codes_12bit(method):
+    H = W = 32
+    n, step, P = 4, 4, 4096
+    plants = [(63, (0, 0), 1, 0.5, 8.0 * 16), (56, (0, 5), 4, -0.5, P / 2.0),
+              (7, (5, 0), 6, 0.75, 0.0), (35, (1, 1), 3, 0.25, P / 4.0)]
+    img = planted_image(H, W, n, step, 12, 29, plants)
+    gpu = gpu_encode(img, n, step, 12, method)
+    assert_same(gpu, O.encode(img, n, step, bits=12), "planted12")
+    nx = (W - 2 * n) // step + 1
+    for (r, (dy, dx), k, s, o) in plants:
+        assert gpu["err"][r] == 0.0 and gpu["domain"][r] == dy * nx + dx and gpu["iso"][r] == k
+
+
+def test_ct12_512_full_size_sampled_and_methods_agree():
+    # 512x512 12-bit, 8x8 ranges, 16x16 domains at stride 2 (4096 x 496,008 candidates)
+    img = gen_image(512, 512, 12, 3)
+    mf = gpu_encode(img, 8, 2, 12, F.METHOD_MFMA)
+    di = gpu_encode(img, 8, 2, 12, F.METHOD_DIRECT)
+    assert_same(mf, di, "12b mfma-vs-direct")
+    rs = _sample_ranges(4096, 2, 16)
+    ora = O.encode_ranges(img, 8, 2, rs, bits=12)
+    assert_same({k: mf[k][rs] for k in KEYS}, ora, "ct12_512 sampled")
