@@ -9,10 +9,17 @@
 // Reverse: with g_{t+1} = dL/dx_{t+1} and u_t[p] the cell mean read by p,
 //   dL/ds_r += sum_{p in r} g_{t+1}[p] u_t[p],  dL/do_r += sum_{p in r} g_{t+1}[p]
 //   g_t[q]   = sum over range pixels p whose cell contains q of s_r g_{t+1}[p] / 4.
-// The last sum is a gather, never a float atomic: a compact table lists, for
-// every domain, the ranges that use it (sorted by range index), and each
-// pixel q visits the domains covering it in increasing order.  Every sum has
-// a fixed order, so the result is bitwise reproducible.
+// The last sum is a gather, never a float atomic.  A table lists, for every
+// domain, the ranges that use it in increasing range order (a stable radix
+// sort of the range -> domain map).  The lists are cut into segments of
+// kSeg ranges; per step, one thread per (segment, cell) sums the segment's
+// contributions to that cell, and one thread per pixel q adds the segments
+// of the domains covering q, domains and segments in increasing order.  A
+// domain shared by thousands of ranges (flat background) thus costs a short
+// sum per pixel, and every sum has a fixed order, so the result is bitwise
+// reproducible.
+#include <utility>
+
 #include "fic_device.h"
 
 namespace fic {
@@ -53,22 +60,25 @@ __global__ void k_fill_i32n(int32_t *p, int n, int v) {
   if (i < n) p[i] = v;
 }
 
-// --- the domain -> ranges table (built once per call) ---------------------
+// --- the domain -> ranges table --------------------------------------------
+
+constexpr int kSeg = 16;  // ranges per list segment
 
 __global__ void k_count_domains(Geo g, const int32_t *domain, int32_t *cnt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r < g.R) atomicAdd(&cnt[clamp_dom(domain[r], g.ND)], 1);
 }
 
-// Exclusive scan of cnt[0..n) into off[0..n]; one workgroup of 1024 threads.
-__global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int n,
-                                               int32_t *off) {
+// Exclusive scan of ceil(in[i] / div), i < n, into out[0..n]; one workgroup
+// of 1024 threads, each owning a contiguous slice.
+__global__ __launch_bounds__(1024) void k_scan(const int32_t *in, int n,
+                                               int div, int32_t *out) {
   __shared__ int part[1024];
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
-  const int b0 = t * per, b1 = min(b0 + per, n);
+  const int b0 = min(t * per, n), b1 = min(b0 + per, n);
   int s = 0;
-  for (int i = b0; i < b1; ++i) s += cnt[i];
+  for (int i = b0; i < b1; ++i) s += (in[i] + div - 1) / div;
   part[t] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -79,61 +89,99 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *cnt, int n,
   }
   int run = t ? part[t - 1] : 0;
   for (int i = b0; i < b1; ++i) {
-    off[i] = run;
-    run += cnt[i];
+    out[i] = run;
+    run += (in[i] + div - 1) / div;
   }
-  if (t == 1023) off[n] = part[1023];
+  if (t == 1023) out[n] = part[1023];
 }
 
-__global__ void k_fill_lists(Geo g, const int32_t *domain, const int32_t *off,
-                             int32_t *cursor, int32_t *list) {
+// Stable LSD radix sort of (domain, range) pairs by domain, 8 bits a pass,
+// blocks of 256 pairs: block histograms, one scan, stable scatter.
+__global__ void k_rs_init(Geo g, const int32_t *domain, int32_t *key,
+                          int32_t *val) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= g.R) return;
-  const int d = clamp_dom(domain[r], g.ND);
-  list[off[d] + atomicAdd(&cursor[d], 1)] = r;
+  key[r] = clamp_dom(domain[r], g.ND);
+  val[r] = r;
 }
 
-// Order each domain's list by range index (insertion sort; lists are short
-// unless many ranges share one domain).
-__global__ void k_sort_lists(Geo g, const int32_t *off, int32_t *list) {
+__global__ __launch_bounds__(256) void k_rs_hist(const int32_t *key, int n,
+                                                 int shift, int32_t *hist) {
+  __shared__ int h[256];
+  const int t = threadIdx.x, i = blockIdx.x * 256 + t;
+  h[t] = 0;
+  __syncthreads();
+  if (i < n) atomicAdd(&h[(key[i] >> shift) & 255], 1);
+  __syncthreads();
+  hist[t * gridDim.x + blockIdx.x] = h[t];  // digit-major
+}
+
+__global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin,
+                                                    const int32_t *vin, int n,
+                                                    int shift,
+                                                    const int32_t *base,
+                                                    int32_t *kout,
+                                                    int32_t *vout) {
+  __shared__ int dig[256];
+  const int t = threadIdx.x, i = blockIdx.x * 256 + t;
+  const int k = i < n ? kin[i] : 0;
+  const int dg = i < n ? (k >> shift) & 255 : -1;
+  dig[t] = dg;
+  __syncthreads();
+  if (i >= n) return;
+  int rank = 0;
+  for (int j = 0; j < t; ++j) rank += dig[j] == dg;
+  const int pos = base[dg * gridDim.x + blockIdx.x] + rank;
+  kout[pos] = k;
+  vout[pos] = vin[i];
+}
+
+// Segment table: segment s covers list entries [beg, end) of one domain.
+__global__ void k_seg_fill(Geo g, const int32_t *off, const int32_t *segoff,
+                           int2 *seg) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= g.ND) return;
-  const int b0 = off[d], b1 = off[d + 1];
-  for (int i = b0 + 1; i < b1; ++i) {
-    const int v = list[i];
-    int j = i - 1;
-    while (j >= b0 && list[j] > v) {
-      list[j + 1] = list[j];
-      --j;
-    }
-    list[j + 1] = v;
-  }
+  const int b = off[d], e = off[d + 1];
+  for (int s = segoff[d], x = b; s < segoff[d + 1]; ++s, x += kSeg)
+    seg[s] = int2{x, min(x + kSeg, e)};
 }
 
 // --- reverse steps ----------------------------------------------------------
 
-// One thread per range: accumulate dL/ds and dL/do of step t (first = true
-// overwrites the outputs).
+// One lane per range pixel, K = N^2 lanes per range (a wave holds 64 / K
+// ranges): dL/ds and dL/do of step t summed over the range by a fixed
+// butterfly (first = true overwrites the outputs).
 template <int N>
-__global__ void k_grad_so(Geo g, const int32_t *domain, const uint8_t *iso,
-                          const float *x, const float *gnext, float *grad_s,
-                          float *grad_o, int first) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= g.R) return;
-  const int ry = r / g.RW, rx = r % g.RW;
-  const int d = clamp_dom(domain[r], g.ND), k = iso[r];
-  const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
+__global__ __launch_bounds__(256) void k_grad_so(Geo g, const int32_t *domain,
+                                                 const uint8_t *iso,
+                                                 const float *x,
+                                                 const float *gnext,
+                                                 float *grad_s, float *grad_o,
+                                                 int first) {
+  constexpr int K = N * N;
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = (int)(tid / K), pix = (int)(tid % K);
+  const bool live = r < g.R;
   float as = 0.0f, ao = 0.0f;
-  for (int i = 0; i < N; ++i)
-    for (int j = 0; j < N; ++j) {
-      int si, sj;
-      sigma(k, i, j, N - 1, si, sj);
-      const float *c = x + (size_t)(Y + 2 * si) * g.W + X + 2 * sj;
-      const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
-      const float gv = gnext[(size_t)(ry * N + i) * g.W + rx * N + j];
-      as = fmaf(gv, u, as);
-      ao += gv;
-    }
+  if (live) {
+    const int i = pix / N, j = pix % N;
+    const int ry = r / g.RW, rx = r % g.RW;
+    const int d = clamp_dom(domain[r], g.ND), k = iso[r];
+    const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
+    int si, sj;
+    sigma(k, i, j, N - 1, si, sj);
+    const float *c = x + (size_t)(Y + 2 * si) * g.W + X + 2 * sj;
+    const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
+    const float gv = gnext[(size_t)(ry * N + i) * g.W + rx * N + j];
+    as = gv * u;
+    ao = gv;
+  }
+#pragma unroll
+  for (int o = K / 2; o > 0; o >>= 1) {
+    as += __shfl_xor(as, o, K);
+    ao += __shfl_xor(ao, o, K);
+  }
+  if (!live || pix != 0) return;
   if (first) {
     grad_s[r] = as;
     grad_o[r] = ao;
@@ -158,11 +206,53 @@ __device__ __forceinline__ void sigma_inv(int k, int ci, int cj, int m, int &i,
   }
 }
 
-// One thread per pixel q: g_t[q] from g_{t+1}.
+// One thread per (segment, cell): the segment's share of s_r g_{t+1}[p] / 4
+// over the range pixels p that read that cell of the domain.
+// `nseg` points at the segment count the table build wrote (the grid is
+// sized for the largest possible count).  The segment's entries are loaded
+// in three independent batches (list, codes, gradient) before the ordered
+// sum, so a thread waits for three memory round trips, not 3 kSeg.
 template <int N>
-__global__ void k_grad_x(Geo g, const uint8_t *iso, const float *s,
-                         const int32_t *off, const int32_t *list,
-                         const float *gnext, float *gout) {
+__global__ __launch_bounds__(256) void k_seg_partial(
+    Geo g, const int32_t *nseg, const int2 *seg, const int32_t *list,
+    const uint8_t *iso, const float *s, const float *gnext, float *partial) {
+  constexpr int K = N * N;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int sg = tid / K, c = tid % K, ci = c / N, cj = c % N;
+  if (sg >= *nseg) return;
+  const int2 be = seg[sg];
+  int rr[kSeg];
+#pragma unroll
+  for (int u = 0; u < kSeg; ++u)
+    rr[u] = be.x + u < be.y ? list[be.x + u] : -1;
+  float w[kSeg];
+  int pix[kSeg];
+#pragma unroll
+  for (int u = 0; u < kSeg; ++u) {
+    const int r = rr[u] < 0 ? rr[0] : rr[u];
+    int i, j;
+    sigma_inv(iso[r], ci, cj, N - 1, i, j);
+    const int ry = r / g.RW, rx = r % g.RW;
+    pix[u] = (ry * N + i) * g.W + rx * N + j;
+    w[u] = s[r] * 0.25f;
+  }
+  float gv[kSeg];
+#pragma unroll
+  for (int u = 0; u < kSeg; ++u) gv[u] = gnext[pix[u]];
+  float acc = 0.0f;
+#pragma unroll
+  for (int u = 0; u < kSeg; ++u)
+    if (rr[u] >= 0) acc = fmaf(w[u], gv[u], acc);
+  partial[tid] = acc;
+}
+
+// One thread per pixel q: g_t[q] = sum of the segment partials of the
+// cells containing q, over the domains covering q (loads batched by 8).
+template <int N>
+__global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
+                                                const float *partial,
+                                                float *gout) {
+  constexpr int K = N * N;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= g.H * g.W) return;
   const int qy = q / g.W, qx = q % g.W;
@@ -176,16 +266,16 @@ __global__ void k_grad_x(Geo g, const uint8_t *iso, const float *s,
   for (int dy = dy0; dy <= dy1; ++dy)
     for (int dx = dx0; dx <= dx1; ++dx) {
       const int d = dy * g.NX + dx;
-      const int b0 = off[d], b1 = off[d + 1];
-      if (b0 == b1) continue;
-      const int ci = (qy - dy * g.step) >> 1, cj = (qx - dx * g.step) >> 1;
-      for (int e = b0; e < b1; ++e) {
-        const int r = list[e];
-        int i, j;
-        sigma_inv(iso[r], ci, cj, N - 1, i, j);
-        const int ry = r / g.RW, rx = r % g.RW;
-        const float gv = gnext[(size_t)(ry * N + i) * g.W + rx * N + j];
-        acc = fmaf(s[r] * 0.25f, gv, acc);
+      const int s0 = segoff[d], s1 = segoff[d + 1];
+      const int cell = ((qy - dy * g.step) >> 1) * N + ((qx - dx * g.step) >> 1);
+      for (int sb = s0; sb < s1; sb += 8) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          v[u] = sb + u < s1 ? partial[(size_t)(sb + u) * K + cell] : 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (sb + u < s1) acc += v[u];
       }
     }
   gout[q] = acc;
@@ -193,54 +283,112 @@ __global__ void k_grad_x(Geo g, const uint8_t *iso, const float *s,
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-template <int N>
-hipError_t backward_impl(const Geo &g, const int32_t *domain,
-                         const uint8_t *iso, const float *s, int iters,
-                         const float *traj, const float *grad_xT,
-                         float *grad_s, float *grad_o, void *ws,
-                         hipStream_t st) {
+// Workspace of the adjoint: the table (built once per code set) and the
+// per-step buffers.
+struct AdjWs {
+  int32_t *cnt, *off, *segoff, *key0, *val0, *key1, *val1, *hist, *base;
+  int2 *seg;
+  float *partial, *gbuf0, *gbuf1;
+  int32_t *list;  // points at val0 or val1 after the sort
+  int nbr, max_seg;
+  size_t total;
+};
+
+AdjWs adj_layout(const Geo &g, void *ws) {
   const size_t HW = (size_t)g.H * g.W;
-  char *w = (char *)ws;
-  int32_t *cnt = (int32_t *)w;      w += a256(sizeof(int32_t) * (g.ND + 1));
-  int32_t *cursor = (int32_t *)w;   w += a256(sizeof(int32_t) * (g.ND + 1));
-  int32_t *off = (int32_t *)w;      w += a256(sizeof(int32_t) * (g.ND + 1));
-  int32_t *list = (int32_t *)w;     w += a256(sizeof(int32_t) * g.R);
-  float *gbuf0 = (float *)w;        w += a256(sizeof(float) * HW);
-  float *gbuf1 = (float *)w;
+  AdjWs a;
+  a.nbr = (g.R + 255) / 256;
+  a.max_seg = g.R + (g.R + kSeg - 1) / kSeg;  // non-empty domains <= R
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += a256(bytes);
+    return ws ? (char *)ws + at : nullptr;
+  };
+  a.cnt = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
+  a.off = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
+  a.segoff = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
+  a.key0 = (int32_t *)take(sizeof(int32_t) * g.R);
+  a.val0 = (int32_t *)take(sizeof(int32_t) * g.R);
+  a.key1 = (int32_t *)take(sizeof(int32_t) * g.R);
+  a.val1 = (int32_t *)take(sizeof(int32_t) * g.R);
+  a.hist = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
+  a.base = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
+  a.seg = (int2 *)take(sizeof(int2) * a.max_seg);
+  a.partial = (float *)take(sizeof(float) * (size_t)a.max_seg * g.K);
+  a.gbuf0 = (float *)take(sizeof(float) * HW);
+  a.gbuf1 = (float *)take(sizeof(float) * HW);
+  a.list = a.val0;
+  a.total = off;
+  return a;
+}
+
+// Build the domain -> ranges table for these codes.
+void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
+                         hipStream_t st) {
   const int bs = 256;
-  if (iters == 0) {
-    hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
-                       grad_s, (long long)g.R, 0.0f);
-    hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
-                       grad_o, (long long)g.R, 0.0f);
-    return hipGetLastError();
-  }
   hipLaunchKernelGGL(k_fill_i32n, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0,
-                     st, cnt, g.ND + 1, 0);
-  hipLaunchKernelGGL(k_fill_i32n, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0,
-                     st, cursor, g.ND + 1, 0);
+                     st, a.cnt, g.ND + 1, 0);
   hipLaunchKernelGGL(k_count_domains, dim3((g.R + bs - 1) / bs), dim3(bs), 0,
-                     st, g, domain, cnt);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, cnt, g.ND, off);
-  hipLaunchKernelGGL(k_fill_lists, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
-                     g, domain, off, cursor, list);
-  hipLaunchKernelGGL(k_sort_lists, dim3((g.ND + bs - 1) / bs), dim3(bs), 0, st,
-                     g, off, list);
+                     st, g, domain, a.cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, 1, a.off);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, kSeg,
+                     a.segoff);
+  hipLaunchKernelGGL(k_rs_init, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st, g,
+                     domain, a.key0, a.val0);
+  int bits = 0;
+  while ((1ll << bits) < (long long)g.ND) ++bits;
+  int32_t *kin = a.key0, *vin = a.val0, *kout = a.key1, *vout = a.val1;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(a.nbr), dim3(256), 0, st, kin, g.R,
+                       shift, a.hist);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.hist, 256 * a.nbr,
+                       1, a.base);
+    hipLaunchKernelGGL(k_rs_scatter, dim3(a.nbr), dim3(256), 0, st, kin, vin,
+                       g.R, shift, a.base, kout, vout);
+    std::swap(kin, kout);
+    std::swap(vin, vout);
+  }
+  a.list = vin;
+  hipLaunchKernelGGL(k_seg_fill, dim3((g.ND + bs - 1) / bs), dim3(bs), 0, st,
+                     g, a.off, a.segoff, a.seg);
+}
+
+// The reverse steps, with the table already built.
+template <int N>
+void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                   const float *s, int iters, const float *traj,
+                   const float *grad_xT, float *grad_s, float *grad_o,
+                   const AdjWs &a, hipStream_t st) {
+  const size_t HW = (size_t)g.H * g.W;
+  const int bs = 256;
   const float *gnext = grad_xT;
-  float *bufs[2] = {gbuf0, gbuf1};
+  float *bufs[2] = {a.gbuf0, a.gbuf1};
   for (int t = iters - 1; t >= 0; --t) {
     const float *x = traj + (size_t)t * HW;
-    hipLaunchKernelGGL((k_grad_so<N>), dim3((g.R + bs - 1) / bs), dim3(bs), 0,
-                       st, g, domain, iso, x, gnext, grad_s, grad_o,
-                       t == iters - 1 ? 1 : 0);
+    const long long nso = (long long)g.R * N * N;
+    hipLaunchKernelGGL((k_grad_so<N>), dim3((unsigned)((nso + bs - 1) / bs)),
+                       dim3(bs), 0, st, g, domain, iso, x, gnext, grad_s,
+                       grad_o, t == iters - 1 ? 1 : 0);
     if (t > 0) {
       float *gout = bufs[t & 1];
+      const long long np = (long long)a.max_seg * N * N;
+      hipLaunchKernelGGL((k_seg_partial<N>), dim3((unsigned)((np + bs - 1) / bs)),
+                         dim3(bs), 0, st, g, a.segoff + g.ND, a.seg, a.list, iso, s,
+                         gnext, a.partial);
       hipLaunchKernelGGL((k_grad_x<N>), dim3((HW + bs - 1) / bs), dim3(bs), 0,
-                         st, g, iso, s, off, list, gnext, gout);
+                         st, g, a.segoff, a.partial, gout);
       gnext = gout;
     }
   }
-  return hipGetLastError();
+}
+
+void zero_grads(const Geo &g, float *grad_s, float *grad_o, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
+                     grad_s, (long long)g.R, 0.0f);
+  hipLaunchKernelGGL(k_fill_f32, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st,
+                     grad_o, (long long)g.R, 0.0f);
 }
 
 // --- refinement: loss gradient and Adam ------------------------------------
@@ -306,9 +454,7 @@ __global__ void k_adam(int R, float *s, float *o, const float *gs,
 }  // namespace
 
 size_t decode_backward_ws_bytes(const Geo &g) {
-  const size_t HW = (size_t)g.H * g.W;
-  return 3 * a256(sizeof(int32_t) * (g.ND + 1)) + a256(sizeof(int32_t) * g.R) +
-         2 * a256(sizeof(float) * HW);
+  return adj_layout(g, nullptr).total;
 }
 
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
@@ -337,11 +483,19 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                                   const float *grad_xT, float *grad_s,
                                   float *grad_o, void *ws, hipStream_t st) {
   (void)o;
+  if (iters == 0) {
+    zero_grads(g, grad_s, grad_o, st);
+    return hipGetLastError();
+  }
+  AdjWs a = adj_layout(g, ws);
+  build_adjoint_table(g, domain, a, st);
   if (g.n == 8)
-    return backward_impl<8>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
-                            grad_o, ws, st);
-  return backward_impl<4>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
-                          grad_o, ws, st);
+    adjoint_steps<8>(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o,
+                     a, st);
+  else
+    adjoint_steps<4>(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o,
+                     a, st);
+  return hipGetLastError();
 }
 
 }  // namespace fic
@@ -371,7 +525,8 @@ hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso
   float *gso = (float *)w;    w += a256(sizeof(float) * 2 * g.R);
   float *mom = (float *)w;    w += a256(sizeof(float) * 4 * g.R);
   double *part = (double *)w; w += a256(sizeof(double) * nb);
-  void *bws = w;
+  AdjWs adj = adj_layout(g, w);
+  bool table_built = false;
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f, s_lim = 0.999f;
   hipLaunchKernelGGL(k_fill_f32, dim3((4 * g.R + 255) / 256), dim3(256), 0, st,
                      mom, (long long)4 * g.R, 0.0f);
@@ -389,9 +544,19 @@ hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, st, part, nb,
                        (long long)HW, loss, step);
     if (step == steps) break;
-    e = launch_decode_backward(g, domain, iso, s, o, iters, traj, gx, gso,
-                               gso + g.R, bws, st);
-    if (e != hipSuccess) return e;
+    // the codes' domains do not change: the table is built once
+    if (iters == 0) {
+      zero_grads(g, gso, gso + g.R, st);
+    } else {
+      if (!table_built) build_adjoint_table(g, domain, adj, st);
+      table_built = true;
+      if (g.n == 8)
+        adjoint_steps<8>(g, domain, iso, s, iters, traj, gx, gso, gso + g.R,
+                         adj, st);
+      else
+        adjoint_steps<4>(g, domain, iso, s, iters, traj, gx, gso, gso + g.R,
+                         adj, st);
+    }
     p1 *= b1;
     p2 *= b2;
     hipLaunchKernelGGL(k_adam, dim3((g.R + 255) / 256), dim3(256), 0, st, g.R,

@@ -65,6 +65,45 @@ def test_backward_matches_fp64_gradient_and_fd():
     assert rel(gs[idx], np.array(fs)) <= 1e-3 and rel(go[idx], np.array(fo)) <= 1e-3
 
 
+@pytest.mark.parametrize("case", ["one_domain", "few_domains", "ragged_rect"])
+def test_backward_shared_domains(case):
+    """Many ranges on one domain (long lists, many segments) and domain
+    counts that need one, two and three radix passes."""
+    rng = np.random.default_rng(41)
+    H, W, n, step = {"one_domain": (64, 48, 4, 4),      # 165 domains: one pass
+                     "few_domains": (128, 96, 4, 2),    # 2,745 domains: two passes
+                     "ragged_rect": (264, 272, 4, 1),   # 68,105 domains: three passes
+                     }[case]
+    p = F.Params(H, W, 8, n, step)
+    R, ND = F.query(p)[:2]
+    if case == "one_domain":
+        d = np.zeros(R, dtype=np.int32)
+    elif case == "few_domains":
+        d = rng.choice(np.array([0, 5, ND - 1], dtype=np.int32), R)
+    else:
+        d = rng.integers(0, ND, R).astype(np.int32)
+        d[: R // 3] = 7                           # one long list among many short
+    k = rng.integers(0, 8, R).astype(np.uint8)
+    s = rng.uniform(-0.8, 0.8, R)
+    o = rng.uniform(-40, 200, R)
+    T = 6
+    target = rng.integers(0, 256, (H, W)).astype(np.float64)
+    sd, od = dev(s, torch.float32), dev(o, torch.float32)
+    traj = F.decode(dev(d, torch.int32), dev(k, torch.uint8), sd, od, p, T, 128.0)
+    g = 2.0 * (traj[-1] - torch.from_numpy(target).float().cuda()) / (H * W)
+    gs, go = F.decode_backward(dev(d, torch.int32), dev(k, torch.uint8), sd, od, traj, g, p)
+    gs2, go2 = F.decode_backward(dev(d, torch.int32), dev(k, torch.uint8), sd, od, traj, g, p)
+    assert torch.equal(gs, gs2) and torch.equal(go, go2)
+    s32 = s.astype(np.float32).astype(np.float64)
+    o32 = o.astype(np.float32).astype(np.float64)
+    rtraj = O.decode(H, W, n, step, d, k, s32, o32, T, 128.0)
+    rg = 2.0 * (rtraj[-1] - target) / (H * W)
+    rs, ro = O.decode_backward(H, W, n, step, d, k, s32, o32, T, rtraj, rg)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(gs.cpu().numpy().astype(np.float64), rs) <= 1e-4
+    assert rel(go.cpu().numpy().astype(np.float64), ro) <= 1e-4
+
+
 def test_backward_bitwise_reproducible_and_autograd():
     H = W = 64
     n, step, T = 4, 2, 12
