@@ -126,6 +126,7 @@ EncLayout enc_layout(const Geo &g) {
   L.off_col_dom = o;  o = align256(o + (size_t)g.NC_pad * 4);
   L.off_col_sadp = o; o = align256(o + (size_t)g.NC_pad * 8);
   L.off_col_saa = o;  o = align256(o + (size_t)g.NC_pad * 8);
+  L.off_col_rec = o;  o = align256(o + (size_t)g.NC_pad * 16);
   L.off_rng_sb = o;   o = align256(o + (size_t)g.R_pad * 8);
   L.off_rng_sbb = o;  o = align256(o + (size_t)g.R_pad * 8);
   L.off_best = o;     o = align256(o + (size_t)g.R_pad * 8);
@@ -142,6 +143,7 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   b.col_dom = (int32_t *)(w + L.off_col_dom);
   b.col_sadp = (float2 *)(w + L.off_col_sadp);
   b.col_saa = (double *)(w + L.off_col_saa);
+  b.col_rec = (ColRec *)(w + L.off_col_rec);
   b.rng_sb = (double *)(w + L.off_rng_sb);
   b.rng_sbb = (double *)(w + L.off_rng_sbb);
   b.best = (unsigned long long *)(w + L.off_best);

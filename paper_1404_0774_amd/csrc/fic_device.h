@@ -101,4 +101,19 @@ __device__ __forceinline__ float round_down_f(double v) {
   return f;
 }
 
+// Load a workgroup-uniform struct (a slice descriptor, a work item) into
+// scalar registers: each 32-bit word is read and broadcast from the first
+// active lane.  The caller guarantees that every lane reads the same address.
+template <typename T>
+__device__ __forceinline__ T load_uniform(const T *p) {
+  static_assert(sizeof(T) % 4 == 0, "whole 32-bit words");
+  T v;
+  const int *src = (const int *)p;
+  int *dst = (int *)&v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i)
+    dst[i] = __builtin_amdgcn_readfirstlane(src[i]);
+  return v;
+}
+
 }  // namespace fic

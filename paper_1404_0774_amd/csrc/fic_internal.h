@@ -31,6 +31,15 @@ struct Geo {
 };
 
 // Device buffers carved out of the caller's workspace.
+// One column's statistics in a single 16-byte record (8-bit search): SA,
+// the prune denominator D' (as in col_sadp), the domain index and the sum of
+// squared cell sums, exact in 32 bits for 8-bit images (<= 64 * 1020^2).
+struct __attribute__((aligned(16))) ColRec {
+  float sa, dp;
+  int dom;
+  unsigned saa;
+};
+
 struct EncBufs {
   _Float16 *bop;     // [NC_pad][K] contracted domain cell sums, sweep order
                      //   (12-bit: two planes, hi then lo, each [NC_pad][K])
@@ -41,6 +50,8 @@ struct EncBufs {
                      //   prune denominator D' rounded down; +inf for flat
                      //   domains and padding)
   double *col_saa;   // [NC_pad] sum of squared cell sums
+  ColRec *col_rec;   // [NC_pad] the three above in one record (saa = 0
+                     //   for 12-bit images)
   double *rng_sb;    // [R_pad] sum of range pixels
   double *rng_sbb;   // [R_pad] sum of squared range pixels
   unsigned long long *best; // [R_pad] packed (residual, candidate) keys
@@ -50,7 +61,7 @@ struct EncBufs {
 
 // Byte layout of the encode workspace.
 struct EncLayout {
-  size_t off_bop, off_aop, off_col_dom, off_col_sadp, off_col_saa;
+  size_t off_bop, off_aop, off_col_dom, off_col_sadp, off_col_saa, off_col_rec;
   size_t off_rng_sb, off_rng_sbb, off_best, off_flat;
   size_t total;
 };

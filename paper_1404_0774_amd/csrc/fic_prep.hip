@@ -86,6 +86,12 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
         dp = round_down_f(Dp);
     }
     b.col_sadp[col] = float2{(float)SA, dp};
+    ColRec rec;
+    rec.sa = (float)SA;
+    rec.dp = dp;
+    rec.dom = d;
+    rec.saa = g.bits == 8 ? (unsigned)SAA : 0u;
+    b.col_rec[col] = rec;
   }
   __syncthreads();
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
@@ -267,8 +273,9 @@ __global__ void k_batch_init(BatchDev bd) {
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_prep_domains_batch(BatchDev bd) {
   const int s = slice_of(bd.phase_off, bd.n, blockIdx.x);
-  const SliceDesc &d = bd.tab[s];
-  prep_domains_body<Pix, N>(d.g, (const Pix *)d.image, d.b,
+  const Geo g = load_uniform(&bd.tab[s].g);
+  const EncBufs b = load_uniform(&bd.tab[s].b);
+  prep_domains_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b,
                             blockIdx.x - bd.phase_off[s]);
 }
 
@@ -276,16 +283,20 @@ template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_prep_ranges_batch(BatchDev bd) {
   const int *off = bd.phase_off + (bd.n + 1);
   const int s = slice_of(off, bd.n, blockIdx.x);
-  const SliceDesc &d = bd.tab[s];
-  prep_ranges_body<Pix, N>(d.g, (const Pix *)d.image, d.b, blockIdx.x - off[s]);
+  const Geo g = load_uniform(&bd.tab[s].g);
+  const EncBufs b = load_uniform(&bd.tab[s].b);
+  prep_ranges_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b,
+                           blockIdx.x - off[s]);
 }
 
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
   const int *off = bd.phase_off + 3 * (bd.n + 1);
   const int s = slice_of(off, bd.n, blockIdx.x);
-  const SliceDesc &d = bd.tab[s];
-  finalize_body<Pix, N>(d.g, (const Pix *)d.image, d.b, d.out,
+  const Geo g = load_uniform(&bd.tab[s].g);
+  const EncBufs b = load_uniform(&bd.tab[s].b);
+  const fic_codes out = load_uniform(&bd.tab[s].out);
+  finalize_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b, out,
                         blockIdx.x - off[s]);
 }
 

@@ -43,12 +43,12 @@ constexpr int kSync = 4;            // column blocks between global syncs
 constexpr int kQueue = 128;         // pairs; >= 63 + 64 lanes
 
 // A queued (range, domain) pair: the 8 transforms' G, the column's
-// statistics and the wave-local range index.
+// statistics and dl = domain << 4 | wave-local range index.
 struct __attribute__((aligned(16))) QEntry {
   float4 g0, g1;
-  double saa;
   float sa, dp;
-  int dom, lr;
+  unsigned saa;
+  int dl;
 };
 
 // A surviving transform of a queued pair: G, and pair index << 3 | k.
@@ -101,7 +101,7 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
         gv[0] = g0.x; gv[1] = g0.y; gv[2] = g0.z; gv[3] = g0.w;
         gv[4] = g1.x; gv[5] = g1.y; gv[6] = g1.z; gv[7] = g1.w;
         const float sa = q.sa, dp = q.dp;
-        const int lr = q.lr;
+        const int lr = q.dl & 15;
         const double2 rs = rstat[lr];
         const float bbar = (float)(rs.x / K);
         const float t = weight_from_key(best[lr], K * rs.y - rs.x * rs.x, g) * dp;
@@ -127,22 +127,22 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
     for (int c = lane; c < nc; c += 64) {
       const Cand cd = cands[c];
       const QEntry &q = queue[cd.pk >> 3];
-      const int lr = q.lr;
+      const int lr = q.dl & 15;
       const double2 rs = rstat[lr];
-      const Fit f = fit_exact((double)cd.g, (double)q.sa, q.saa, rs.x, rs.y, g);
-      atomicMin(&best[lr], make_key(f.err, 8ll * q.dom + (cd.pk & 7), g));
+      const Fit f =
+          fit_exact((double)cd.g, (double)q.sa, (double)q.saa, rs.x, rs.y, g);
+      atomicMin(&best[lr], make_key(f.err, 8ll * (q.dl >> 4) + (cd.pk & 7), g));
     }
     __builtin_amdgcn_wave_barrier();
   }
   const int rem = qn - n;
-  static_assert(sizeof(QEntry) == 64, "entry is four 16-byte words");
-  uint4 t0 = uint4{0, 0, 0, 0}, t1 = t0, t2 = t0, t3 = t0;
+  static_assert(sizeof(QEntry) == 48, "entry is three 16-byte words");
+  uint4 t0 = uint4{0, 0, 0, 0}, t1 = t0, t2 = t0;
   if (lane < rem) {
     const uint4 *src = (const uint4 *)&queue[n + lane];
     t0 = src[0];
     t1 = src[1];
     t2 = src[2];
-    t3 = src[3];
   }
   __builtin_amdgcn_wave_barrier();
   if (lane < rem) {
@@ -150,7 +150,6 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
     dst[0] = t0;
     dst[1] = t1;
     dst[2] = t2;
-    dst[3] = t3;
   }
   qn = rem;
 }
@@ -166,13 +165,15 @@ struct WaveState {
   int wr0, h, cl, lane;
 };
 
-// One 32-column block: prefetch the next block into (bn, nsd), run the MFMA
+// One 32-column block: prefetch the next block's operand and column records
+// into (bn, nsd), run the MFMA
 // contraction with (bf, sd), prune, queue survivors, sync every few blocks.
 template <int K>
 __device__ __forceinline__ void sweep_block(
     const Geo &g, const EncBufs &b, WaveState &w, const half8 (&af)[kRB][K / 16],
     float (&wp)[kSlots], const float (&bbar)[kSlots], const half8 (&bf)[K / 16],
-    float2 sd, half8 (&bn)[K / 16], float2 &nsd, int cb, int c0, int c1) {
+    const ColRec &sd, half8 (&bn)[K / 16], ColRec &nsd, int cb, int c0,
+    int c1) {
   constexpr int KS = K / 16;
   const int slot = (cb - c0) % kSync;
   const int col = cb * 32 + w.cl;
@@ -181,7 +182,7 @@ __device__ __forceinline__ void sweep_block(
     const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * w.h;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
-    nsd = b.col_sadp[ncol];
+    nsd = b.col_rec[ncol];
   }
   // keep the prefetch ahead of the matrix-core work
   __builtin_amdgcn_sched_barrier(0);
@@ -195,7 +196,7 @@ __device__ __forceinline__ void sweep_block(
       acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
                                                        acc[rb], 0, 0, 0);
   }
-  const float csa = sd.x, cdp = sd.y;
+  const float csa = sd.sa, cdp = sd.dp;
 
   // Per (range, domain) pair: the 8 transforms' G are non-negative integers
   // in FP32, so their bit patterns order like unsigned integers and max/min
@@ -223,8 +224,7 @@ __device__ __forceinline__ void sweep_block(
   if (__any(any_pass)) {
     // append every passing pair, with its 8 G values, to the wave's queue
     // (ballot + mbcnt give each lane its position)
-    const int cdom = b.col_dom[col];
-    const double csaa = b.col_saa[col];
+    const int cdl = sd.dom << 4;
     bool drained = false;
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb)
@@ -242,11 +242,9 @@ __device__ __forceinline__ void sweep_block(
                          acc[rb][8 * e + 3]};
           q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
                          acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
-          q->saa = csaa;
-          q->sa = csa;
-          q->dp = cdp;
-          q->dom = cdom;
-          q->lr = 4 * rb + 2 * w.h + e;
+          *(uint4 *)&q->sa =
+              uint4{__float_as_uint(csa), __float_as_uint(cdp), sd.saa,
+                    (unsigned)(cdl | (4 * rb + 2 * w.h + e))};
         }
         w.qn += __popcll(m);
         if (w.qn >= 64) {
@@ -345,13 +343,13 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
 
   // two register buffers for the streamed domain operand, used alternately
   half8 bA[KS], bB[KS];
-  float2 sdA, sdB;
+  ColRec sdA, sdB;
   {
     const int col = c0 * 32 + w.cl;
     const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * w.h;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) bA[kk] = *(const half8 *)(bsrc + 16 * kk);
-    sdA = b.col_sadp[col];
+    sdA = b.col_rec[col];
   }
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
@@ -387,11 +385,13 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     __syncthreads();
     if (threadIdx.x == 0) s_item = atomicAdd(bd.counter, 1);
     __syncthreads();
-    const int it = s_item;
+    // uniform across the workgroup: keep the item and its slice in scalars
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     if (it >= bd.n_items) break;
-    const int4 w = bd.items[it];
-    const SliceDesc &d = bd.tab[w.x];
-    search_rows<K>(d.g, d.b, lds, w.y, w.z, w.w);
+    const int4 w = load_uniform(&bd.items[it]);
+    const Geo g = load_uniform(&bd.tab[w.x].g);
+    const EncBufs b = load_uniform(&bd.tab[w.x].b);
+    search_rows<K>(g, b, lds, w.y, w.z, w.w);
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();

@@ -147,9 +147,11 @@ __global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
     else
       hi = mid - 1;
   }
-  const SliceDesc &d = bd.tab[lo];
-  const int nb = min(nblocks, d.seed_blocks);
-  if (nb > 0) seed_dense_body<K, B12>(d.g, d.b, nb, blockIdx.x - off[lo]);
+  const int nb = min(nblocks, bd.tab[lo].seed_blocks);
+  if (nb <= 0) return;
+  const Geo g = load_uniform(&bd.tab[lo].g);
+  const EncBufs b = load_uniform(&bd.tab[lo].b);
+  seed_dense_body<K, B12>(g, b, nb, blockIdx.x - off[lo]);
 }
 
 }  // namespace
