@@ -10,9 +10,12 @@ stride 2, and the 256x256 decode workload (decoder, adjoint, refinement).
 Prints one JSON line.
 """
 import argparse
+import csv
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -21,6 +24,78 @@ sys.path.insert(0, ROOT)
 
 MFMA_FP16_PEAK = 2.5e15  # dense FP16 MFMA FLOP/s of MI355X (AMD published)
 HBM_PEAK = 8.0e12        # bytes/s
+# hardware byte counters of the headline search kernel, from rocprofv3 --pmc
+# (written by --pmc-summary); used only while the kernel sources are unchanged
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "search_u8_512_traffic.md")
+SEARCH_SOURCES = ["fic_search_mfma.hip", "fic_search_common.h", "fic_device.h", "fic_internal.h"]
+SEARCH_KERNEL = "k_search_mfma_u8<64>"
+
+
+def search_source_hash():
+    h = hashlib.sha256()
+    for f in SEARCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_1404_0774_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic():
+    """Scaled HBM bytes per launch of the search kernel, or None when no
+    summary exists or the kernel changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    with open(TRAFFIC_PROFILE) as f:
+        m = re.search(r"traffic: kernel=(\S+) fetch_bytes=(\d+) write_bytes=(\d+) src=(\w+)", f.read())
+    if not m or m.group(4) != search_source_hash():
+        return None
+    return {"fetch": int(m.group(2)), "write": int(m.group(3))}
+
+
+def pmc_summary(fetch_dir, write_dir):
+    """Markdown summary of two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of
+    `bench.py --no-extras --copy-probe MIB`: KiB per dispatch, scaled by what
+    the same counters read for the device-to-device copy of known size."""
+    def per_kernel(d, counter):
+        vals = {}
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] != counter:
+                    continue
+                name = r["Kernel_Name"]
+                vals.setdefault(name, []).append(float(r["Counter_Value"]))
+        return vals
+    fetch, write = per_kernel(fetch_dir, "FETCH_SIZE"), per_kernel(write_dir, "WRITE_SIZE")
+    copy_f = sum(sum(v) for k, v in fetch.items() if "copyBuffer" in k)
+    copy_w = sum(sum(v) for k, v in write.items() if "copyBuffer" in k)
+    copy_kib = 3 * 256 * 1024          # three copies of 256 MiB read and written
+    sf = copy_kib / copy_f if copy_f else float("nan")
+    sw = copy_kib / copy_w if copy_w else float("nan")
+    lines = ["# HBM traffic per dispatch (rocprofv3 --pmc), 512x512 u8 encode", "",
+             "Commands (from /tmp, TMPDIR=/tmp):", "",
+             "    rocprofv3 --pmc FETCH_SIZE --output-format csv -d <fetch_dir> -o run -- "
+             "/usr/bin/python3 /root/repo/bench.py --steps 3 --warmup 1 --no-extras --no-cpu-baseline --copy-probe 256",
+             "    rocprofv3 --pmc WRITE_SIZE --output-format csv -d <write_dir> -o run -- (same program)",
+             "    python bench.py --pmc-summary <fetch_dir> <write_dir>", "",
+             f"Copy probe: 3 x 256 MiB device-to-device; FETCH_SIZE read {copy_f:.0f} KiB "
+             f"(scale {sf:.3f}), WRITE_SIZE read {copy_w:.0f} KiB (scale {sw:.3f}).", "",
+             "| kernel | dispatches | FETCH KiB | WRITE KiB | scaled read MB | scaled write MB |",
+             "|---|---|---|---|---|---|"]
+    search = None
+    for name in sorted(set(fetch) | set(write)):
+        if "fic::" not in name:
+            continue
+        f = sum(fetch.get(name, [0])) / max(1, len(fetch.get(name, [])))
+        w = sum(write.get(name, [0])) / max(1, len(write.get(name, [])))
+        short = name.split("(anonymous namespace)::")[-1].split("(")[0]
+        lines.append(f"| {short} | {len(fetch.get(name, []))} | {f:.1f} | {w:.1f} | "
+                     f"{f * sf * 1024 / 1e6:.2f} | {w * sw * 1024 / 1e6:.2f} |")
+        if short == SEARCH_KERNEL:
+            search = (f * sf * 1024, w * sw * 1024)
+    lines.append("")
+    if search:
+        lines.append(f"traffic: kernel={SEARCH_KERNEL} fetch_bytes={search[0]:.0f} "
+                     f"write_bytes={search[1]:.0f} src={search_source_hash()}")
+    return "\n".join(lines) + "\n"
 
 
 def psnr(x, ref, peak):
@@ -28,8 +103,27 @@ def psnr(x, ref, peak):
     return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
 
 
+def trace_summary(stats_dir, command):
+    """Markdown table of a rocprofv3 --kernel-trace --stats run
+    (run_kernel_stats.csv): calls and average duration per kernel."""
+    rows = []
+    with open(os.path.join(stats_dir, "run_kernel_stats.csv")) as f:
+        for r in csv.DictReader(f):
+            rows.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["TotalDurationNs"]) / 1e3))
+    rows.sort(key=lambda x: -x[3])
+    lines = ["# Kernel durations (rocprofv3 --kernel-trace --stats)", "",
+             "Command (from /tmp, TMPDIR=/tmp):", "", "    " + command, "",
+             "| kernel | calls | average us | total us |", "|---|---|---|---|"]
+    for name, calls, avg, tot in rows:
+        short = name.split("(anonymous namespace)::")[-1].split("(")[0]
+        lines.append(f"| {short} | {calls} | {avg:.2f} | {tot:.1f} |")
+    return "\n".join(lines) + "\n"
+
+
 def time_encode(F, torch, timg, p, ws, steps, warmup):
-    """Mean ms per fic_encode and per phase (library HIP events on the stream)."""
+    """Mean ms per fic_encode and per phase (library HIP events on the call's
+    stream: prep, seed, search, finalize)."""
     dev = timg.device
     for _ in range(warmup):
         out = F.encode(timg, p, workspace=ws)
@@ -41,8 +135,9 @@ def time_encode(F, torch, timg, p, ws, steps, warmup):
         out = F.encode(timg, p, workspace=ws)
     e1.record()
     torch.cuda.synchronize(dev)
-    ncalls, ms_prep, ms_search, ms_fin = F.timing_end()
-    return out, e0.elapsed_time(e1) / steps, ms_prep / ncalls, ms_search / ncalls, ms_fin / ncalls
+    n, ms_prep, ms_seed, ms_search, ms_fin = F.timing_end()
+    return out, e0.elapsed_time(e1) / steps, {"prep": ms_prep / n, "seed": ms_seed / n,
+                                              "search": ms_search / n, "finalize": ms_fin / n}
 
 
 def codes_np(out):
@@ -57,7 +152,20 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="ranges timed on the CPU oracle")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
+                    help="print the kernel-duration summary of a rocprofv3 --stats run and exit")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="after the run, copy MIB MiB device-to-device three times (a kernel of "
+                         "known traffic, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.pmc_summary:
+        sys.stdout.write(pmc_summary(*args.pmc_summary))
+        return
+    if args.trace_summary:
+        sys.stdout.write(trace_summary(*args.trace_summary))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the search shards by ranges, see the design notes", file=sys.stderr)
@@ -80,14 +188,17 @@ def main():
     p = F.Params(H, W, bits, n, step, method=F.METHOD_MFMA)
     R, ND, ws_bytes, _ = F.query(p)
     cand = 8 * R * ND
-    flops = 2.0 * n * n * cand            # MFMA FLOPs of the search contraction
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    # the search kernel covers every column block after the densely seeded ones
+    seed_blocks = F.get_tuning(p)["seed_blocks"]
+    cand_search = 8 * R * (ND - 32 * seed_blocks)
+    flops = 2.0 * n * n * cand_search     # MFMA FLOPs of one search launch
 
-    out_m, ms_m, prep_m, search_m, fin_m = time_encode(F, torch, timg, p, ws, args.steps, args.warmup)
+    out_m, ms_m, ph_m = time_encode(F, torch, timg, p, ws, args.steps, args.warmup)
     codes_m = codes_np(out_m)
     p.method = F.METHOD_DIRECT
     dsteps = max(2, args.steps // 4)
-    out_d, ms_d, _, search_d, _ = time_encode(F, torch, timg, p, ws, dsteps, 1)
+    out_d, ms_d, ph_d = time_encode(F, torch, timg, p, ws, dsteps, 1)
     codes_d = codes_np(out_d)
     same = all(np.array_equal(codes_m[k], codes_d[k]) for k in codes_m)
 
@@ -98,7 +209,8 @@ def main():
     ref = img.astype(np.float64)
 
     value = cand / (ms_m / 1e3)
-    achieved = flops / (search_m / 1e3)
+    achieved = flops / (ph_m["search"] / 1e3)
+    traffic = read_traffic()
     result = {
         "metric": "range-domain comparisons/s (MFMA GEMM vs direct) at bit-exact codes; decode PSNR",
         "value": value,
@@ -114,12 +226,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "u8_512: 512x512 uint8 slice, 8x8 ranges, 16x16 domains stride 4",
                    "ranges": R, "domains": ND, "candidates": cand, "seed": 2},
-        "phases_ms": {"prep": prep_m, "search": search_m, "finalize": fin_m},
+        "phases_ms": ph_m,
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP16_PEAK / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK, "traffic": None,
-                     "kernel": "search phase: dense seed block + matrix-core search",
-                     "flop_per_launch": flops},
-        "direct": {"value": cand / (ms_d / 1e3), "ms_per_step": ms_d, "search_ms": search_d,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK,
+                     "traffic": None if traffic is None else traffic["fetch"] + traffic["write"],
+                     "kernel": SEARCH_KERNEL, "flop_per_launch": flops,
+                     "candidates_per_launch": cand_search, "seed_blocks": seed_blocks},
+        "direct": {"value": cand / (ms_d / 1e3), "ms_per_step": ms_d, "phases_ms": ph_d,
                    "steps": dsteps},
         "mfma_over_direct": ms_d / ms_m,
         "codes_identical_mfma_direct": bool(same),
@@ -135,15 +248,18 @@ def main():
         R12, ND12, ws12b, _ = F.query(p12)
         ws12 = torch.empty(ws12b + 256, dtype=torch.uint8, device=dev)
         c12 = 8 * R12 * ND12
-        o12, ms12, pr12, se12, fi12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
+        sb12 = F.get_tuning(p12)["seed_blocks"]
+        o12, ms12, ph12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
         p12.method = F.METHOD_DIRECT
-        o12d, ms12d, _, se12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
+        o12d, ms12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
         same12 = all(np.array_equal(a, b) for a, b in zip(codes_np(o12).values(), codes_np(o12d).values()))
         result["ct12_512"] = {
             "workload": "512x512 12-bit slice, 8x8 ranges, 16x16 domains stride 2",
             "candidates": c12, "value": c12 / (ms12 / 1e3), "unit": "comparisons/s",
-            "ms_per_step": ms12, "phases_ms": {"prep": pr12, "search": se12, "finalize": fi12},
-            "mfma_frac": 2.0 * 4 * 64 * c12 / (se12 / 1e3) / MFMA_FP16_PEAK,
+            "ms_per_step": ms12, "phases_ms": ph12,
+            # four FP16 partial products per searched candidate (hi/lo planes)
+            "mfma_frac": 4 * 2.0 * 64 * 8 * R12 * (ND12 - 32 * sb12) / (ph12["search"] / 1e3)
+                         / MFMA_FP16_PEAK,
             "direct_value": c12 / (ms12d / 1e3), "mfma_over_direct": ms12d / ms12,
             "codes_identical_mfma_direct": bool(same12)}
 
@@ -153,7 +269,7 @@ def main():
         p5 = F.Params(256, 256, 8, 4, 4, method=F.METHOD_MFMA)
         R5, ND5, ws5b, bw5 = F.query(p5)
         ws5 = torch.empty(ws5b + 256, dtype=torch.uint8, device=dev)
-        o5, ms5, _, _, _ = time_encode(F, torch, t5, p5, ws5, args.steps, 2)
+        o5, ms5, _ = time_encode(F, torch, t5, p5, ws5, args.steps, 2)
         s5, o5v = F.dequantize(o5["s_idx"], o5["o_idx"], p5)
         s5, o5v = s5.contiguous(), o5v.contiguous()
         T = 12
@@ -257,6 +373,13 @@ def main():
                                   "cores": O.max_threads(), "kind": "oracle",
                                   "sample": f"{len(rs)} of {R} ranges of the same slice, full domain search each; {dt:.1f} s",
                                   "codes_match_gpu": bool(match)}
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(dev)
+        result["copy_probe_bytes"] = {"read": src.numel() * 4, "write": dst.numel() * 4}
     result["wall_s"] = time.time() - t_wall0
     print(json.dumps(result), flush=True)
 

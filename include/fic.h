@@ -233,16 +233,17 @@ int fic_get_tuning(const fic_params *p, fic_tuning *out);
 /*
  * Benchmark support (not needed to encode).  fic_timing_begin enables and
  * resets phase timing: while enabled, every fic_encode records HIP events on
- * its own stream before operand preparation, before the search, before code
- * extraction and at its end (the most recent 256 calls are kept).
- * fic_timing_end waits for those events, returns the number of timed calls
- * and the summed milliseconds of each phase, and disables timing.  Not
+ * its own stream before operand preparation, before the seeding pass, before
+ * the search, before code extraction and at its end (the most recent 256
+ * calls are kept).  fic_timing_end waits for those events, returns the number
+ * of timed calls and the summed milliseconds of each phase (the search phase
+ * is the one search kernel launch), and disables timing.  Not
  * thread-safe: meant for a single benchmarking thread.  Errors: FIC_E_HIP
  * (event creation or query failed), FIC_E_INVALID (end without begin).
  */
 int fic_timing_begin(void);
-int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_search,
-                   double *ms_finalize);
+int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_seed,
+                   double *ms_search, double *ms_finalize);
 
 /* Message for a status code; never NULL. */
 const char *fic_status_string(int status);

@@ -104,7 +104,7 @@ def lib():
         L.fic_timing_begin.restype = ctypes.c_int
         L.fic_timing_begin.argtypes = []
         L.fic_timing_end.restype = ctypes.c_int
-        L.fic_timing_end.argtypes = [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_double)] * 3
+        L.fic_timing_end.argtypes = [ctypes.POINTER(ctypes.c_int32)] + [ctypes.POINTER(ctypes.c_double)] * 4
         TP = ctypes.POINTER(Tuning)
         L.fic_set_tuning.restype = ctypes.c_int
         L.fic_set_tuning.argtypes = [TP, i32]
@@ -335,11 +335,12 @@ def timing_begin():
 
 
 def timing_end():
-    """Stop timing; returns (n_calls, ms_prep, ms_search, ms_finalize) summed."""
+    """Stop timing; returns (n_calls, ms_prep, ms_seed, ms_search, ms_finalize)
+    summed over the timed calls."""
     n = ctypes.c_int32()
-    a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
-    _check(lib().fic_timing_end(ctypes.byref(n), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
-    return n.value, a.value, b.value, c.value
+    v = [ctypes.c_double() for _ in range(4)]
+    _check(lib().fic_timing_end(ctypes.byref(n), *[ctypes.byref(x) for x in v]))
+    return (n.value,) + tuple(x.value for x in v)
 
 
 class FicDecode(torch.autograd.Function):

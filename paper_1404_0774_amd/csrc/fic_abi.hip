@@ -114,6 +114,12 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   if (st < 1) st = 1;
   while (gcd_ll(st, g.ND) != 1) ++st;
   g.dom_stride = (int)st;
+  // range slots: the same stride through the ranges, so that every search
+  // row group samples the whole image and the work per workgroup evens out
+  long long rs = llround(0.6180339887498949 * g.R_pad);
+  if (rs < 1) rs = 1;
+  while (gcd_ll(rs, g.R_pad) != 1) ++rs;
+  g.rng_stride = (int)rs;
   return FIC_OK;
 }
 
@@ -155,19 +161,21 @@ int hip_fail(hipError_t e, const char *what) {
   return fail(FIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Phase timing for benchmarks: a pool of events, four per timed call.
+// Phase timing for benchmarks: a pool of events, kMarks per timed call
+// (before prep, seed, search and finalize, and at the end).
 constexpr int kTimedCalls = 256;
+constexpr int kMarks = 5;
 struct Timing {
   bool on = false;
   bool created = false;
   int calls = 0;
-  hipEvent_t ev[4 * kTimedCalls];
+  hipEvent_t ev[kMarks * kTimedCalls];
 } g_timing;
 
 void timing_mark(int phase, hipStream_t s) {
   if (!g_timing.on) return;
   const int slot = g_timing.calls % kTimedCalls;
-  hipEventRecord(g_timing.ev[4 * slot + phase], s);
+  hipEventRecord(g_timing.ev[kMarks * slot + phase], s);
 }
 
 }  // namespace
@@ -225,6 +233,7 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   const Tune t = resolve_tune(g, p->method);
   e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
+  timing_mark(2, s);
   if (p->method == FIC_METHOD_DIRECT)
     e = launch_search_direct(g, b, t.chunks, t.seed_blocks, s);
   else if (g.bits == 12)
@@ -232,10 +241,10 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   else
     e = launch_search_mfma(g, b, t.chunks, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "search");
-  timing_mark(2, s);
+  timing_mark(3, s);
   e = launch_finalize(g, image, b, out, s);
   if (e != hipSuccess) return hip_fail(e, "finalize");
-  timing_mark(3, s);
+  timing_mark(4, s);
   if (g_timing.on) ++g_timing.calls;
   return ok();
 }
@@ -317,7 +326,7 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
 
 int fic_timing_begin(void) {
   if (!g_timing.created) {
-    for (int i = 0; i < 4 * kTimedCalls; ++i) {
+    for (int i = 0; i < kMarks * kTimedCalls; ++i) {
       hipError_t e = hipEventCreate(&g_timing.ev[i]);
       if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
     }
@@ -328,27 +337,28 @@ int fic_timing_begin(void) {
   return ok();
 }
 
-int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_search,
-                   double *ms_finalize) {
+int fic_timing_end(int32_t *n_calls, double *ms_prep, double *ms_seed,
+                   double *ms_search, double *ms_finalize) {
   if (!g_timing.on) return fail(FIC_E_INVALID, "timing was not begun");
   g_timing.on = false;
   const int n = g_timing.calls < kTimedCalls ? g_timing.calls : kTimedCalls;
-  double acc[3] = {0, 0, 0};
+  double acc[kMarks - 1] = {0, 0, 0, 0};
   for (int c = 0; c < n; ++c) {
-    hipError_t e = hipEventSynchronize(g_timing.ev[4 * c + 3]);
+    hipError_t e = hipEventSynchronize(g_timing.ev[kMarks * c + kMarks - 1]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
-    for (int ph = 0; ph < 3; ++ph) {
+    for (int ph = 0; ph < kMarks - 1; ++ph) {
       float ms = 0.0f;
-      e = hipEventElapsedTime(&ms, g_timing.ev[4 * c + ph],
-                              g_timing.ev[4 * c + ph + 1]);
+      e = hipEventElapsedTime(&ms, g_timing.ev[kMarks * c + ph],
+                              g_timing.ev[kMarks * c + ph + 1]);
       if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
       acc[ph] += ms;
     }
   }
   if (n_calls) *n_calls = n;
   if (ms_prep) *ms_prep = acc[0];
-  if (ms_search) *ms_search = acc[1];
-  if (ms_finalize) *ms_finalize = acc[2];
+  if (ms_seed) *ms_seed = acc[1];
+  if (ms_search) *ms_search = acc[2];
+  if (ms_finalize) *ms_finalize = acc[3];
   return ok();
 }
 

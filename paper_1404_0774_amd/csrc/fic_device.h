@@ -94,6 +94,13 @@ __device__ __forceinline__ float prune_weight(double best_err, double Sb,
   return w * (1.0f - 0x1p-20f);
 }
 
+// Image range held by range slot i (a permutation of [0, R_pad); values
+// >= R mark padding slots).
+__device__ __forceinline__ int range_of_slot(const Geo &g, int i) {
+  return (int)(((unsigned long long)i * (unsigned)g.rng_stride) %
+               (unsigned)g.R_pad);
+}
+
 // Round a positive double down to float (D' can exceed 2^24).
 __device__ __forceinline__ float round_down_f(double v) {
   float f = (float)v;

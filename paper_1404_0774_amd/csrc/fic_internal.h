@@ -24,6 +24,8 @@ struct Geo {
   int NC_pad;        // NCB * 32
   int cbits;         // low bits of the search key that hold the candidate
   int dom_stride;    // sweep order: column c holds domain (c * dom_stride) % ND
+  int rng_stride;    // range slots: slot i holds range (i * rng_stride) % R_pad
+                     //   (slots of ranges >= R are padding)
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step
@@ -43,8 +45,9 @@ struct __attribute__((aligned(16))) ColRec {
 struct EncBufs {
   _Float16 *bop;     // [NC_pad][K] contracted domain cell sums, sweep order
                      //   (12-bit: two planes, hi then lo, each [NC_pad][K])
-  _Float16 *aop;     // [R_pad * 8][K] range pixels permuted per transform
-                     //   (12-bit: two planes)
+  _Float16 *aop;     // [R_pad * 8][K] range pixels permuted per transform,
+                     //   row 8 i + k for range slot i (12-bit: two planes);
+                     //   every per-range array below is indexed by slot
   int32_t *col_dom;  // [NC_pad] domain index of a column, -1 for padding
   float2 *col_sadp;  // [NC_pad] (sum of the column's cell sums SA,
                      //   prune denominator D' rounded down; +inf for flat

@@ -3,6 +3,8 @@
 #include <limits.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "fic_device.h"
 
 namespace fic {
@@ -97,45 +99,29 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
 }
 
-template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_prep_domains(Geo g, const Pix *img,
-                                                      EncBufs b) {
-  prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
-}
-
-// One thread per range pixel (K threads per range, one wave for n = 8).
+// One thread per range pixel (K threads per range slot r, one wave for
+// n = 8); the slot holds image range range_of_slot(r).
 // Every thread writes its pixel into the 8 rows of its range, row 8 r + k at
 // position sigma_k(q), so that sum_p T[p] row[p] = sum_q T[sigma_k(q)] b[q].
 // 12-bit: b = 64 b_hi + b_lo, two planes.  The range statistics are reduced
-// over the K lanes, and the range's best key is seeded with the better of
-// candidate c = 0 (domain 0, identity) and the first flat domain, both
-// fitted exactly.
+// over the K lanes (32-bit sums for 8-bit images, where every sum is below
+// 2^31), and the range's best key is seeded with candidate c = 0 (domain 0,
+// identity), fitted exactly.
 template <typename Pix, int N>
 __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
                                                  const EncBufs &b, int bid) {
   constexpr int K = N * N;
-  // smallest flat domain over the domain-preparation workgroups
-  __shared__ int s_ff;
-  if (threadIdx.x == 0) s_ff = INT_MAX;
-  __syncthreads();
-  {
-    int m = INT_MAX;
-    for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
-      m = min(m, b.flat_min[i]);
-    atomicMin(&s_ff, m);
-  }
-  __syncthreads();
-  const int ff = s_ff;
+  typedef typename std::conditional<sizeof(Pix) == 1, int, long long>::type Acc;
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
   const int r = (int)(t / K), q = (int)(t % K);
   if (r >= g.R_pad) return;  // whole groups of K lanes leave together
   const int i = q / N, j = q % N, m = N - 1;
   _Float16 *row_hi = b.aop + (size_t)r * 8 * K;
   _Float16 *row_lo = b.aop + (size_t)g.R_pad * 8 * K + (size_t)r * 8 * K;
-  int v = 0;
-  long long A0 = 0;
-  if (r < g.R) {
-    const int ry = r / g.RW, rx = r % g.RW;
+  int v = 0, A0 = 0;
+  const int ri = range_of_slot(g, r);  // image range of slot r
+  if (ri < g.R) {
+    const int ry = ri / g.RW, rx = ri % g.RW;
     v = (int)img[(size_t)(ry * N + i) * g.W + rx * N + j];
     A0 = cell_sum(img, g.W, 2 * i, 2 * j);  // domain 0 sits at (0, 0)
   }
@@ -144,42 +130,39 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
     int si, sj;
     sigma(k, i, j, m, si, sj);
     const int p = si * N + sj;
-    if (g.bits == 12) {
+    if (sizeof(Pix) == 2) {
       row_hi[k * K + p] = (_Float16)(float)(v >> 6);
       row_lo[k * K + p] = (_Float16)(float)(v & 63);
     } else {
       row_hi[k * K + p] = (_Float16)(float)v;
     }
   }
-  const long long Sb = group_sum((long long)v, K);
-  const long long Sbb = group_sum((long long)v * v, K);
-  const long long G0 = group_sum(A0 * v, K);
-  const long long SA0 = group_sum(A0, K);
-  const long long SAA0 = group_sum(A0 * A0, K);
+  const Acc Sb = group_sum((Acc)v, K);
+  const Acc Sbb = group_sum((Acc)v * v, K);
+  const Acc G0 = group_sum((Acc)A0 * v, K);
+  const Acc SA0 = group_sum((Acc)A0, K);
+  const Acc SAA0 = group_sum((Acc)A0 * A0, K);
   if (q != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
-  if (r >= g.R) {
+  if (ri >= g.R) {
     b.best[r] = ~0ull;
     return;
   }
   const Fit f0 = fit_exact((double)G0, (double)SA0, (double)SAA0, (double)Sb,
                            (double)Sbb, g);
-  unsigned long long key = make_key(f0.err, 0, g);
-  if (ff < g.ND) {
-    // a flat domain has A = const, so G = SA * Sb / K, N' = 0, s = 0
-    const double SAf = 0.0;  // any constant domain gives the same fit
-    const Fit f1 = fit_exact(0.0, SAf, 0.0, (double)Sb, (double)Sbb, g);
-    const unsigned long long k1 = make_key(f1.err, 8ll * ff, g);
-    if (k1 < key) key = k1;
-  }
-  b.best[r] = key;
+  b.best[r] = make_key(f0.err, 0, g);
 }
 
+// One launch for both operands: workgroups [0, n_dwg) prepare domains, the
+// rest prepare ranges (the two parts are independent).
 template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_prep_ranges(Geo g, const Pix *img,
-                                                     EncBufs b) {
-  prep_ranges_body<Pix, N>(g, img, b, blockIdx.x);
+__global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
+                                              EncBufs b) {
+  if ((int)blockIdx.x < g.n_dwg)
+    prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
+  else
+    prep_ranges_body<Pix, N>(g, img, b, blockIdx.x - g.n_dwg);
 }
 
 // One group of K lanes per range: unpack the winning key and recompute its
@@ -191,9 +174,11 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
                                               const fic_codes &out, int bid) {
   constexpr int K = N * N;
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const int r = (int)(t / K), q = (int)(t % K);
-  if (r >= g.R) return;  // whole groups leave together (R_pad >= R)
-  const unsigned long long key = b.best[r];
+  const int slot = (int)(t / K), q = (int)(t % K);
+  if (slot >= g.R_pad) return;
+  const int r = range_of_slot(g, slot);  // image range of the slot
+  if (r >= g.R) return;  // padding: whole groups of K lanes leave together
+  const unsigned long long key = b.best[slot];
   const long long c = (long long)(key & ((1ull << g.cbits) - 1));
   const int d = (int)(c >> 3), k = (int)(c & 7);
   const int i = q / N, j = q % N, m = N - 1;
@@ -227,20 +212,12 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
 template <typename Pix>
 hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
                      hipStream_t st) {
-  const int bs = 256;
+  const long long rwg = ((long long)g.R_pad * g.K + 255) / 256;
+  const dim3 grid((unsigned)(g.n_dwg + rwg));
   if (g.n == 8)
-    hipLaunchKernelGGL((k_prep_domains<Pix, 8>), dim3(g.n_dwg), dim3(bs), 0, st,
-                       g, img, b);
+    hipLaunchKernelGGL((k_prep<Pix, 8>), grid, dim3(256), 0, st, g, img, b);
   else
-    hipLaunchKernelGGL((k_prep_domains<Pix, 4>), dim3(g.n_dwg), dim3(bs), 0, st,
-                       g, img, b);
-  const dim3 rgrid((unsigned)(((long long)g.R_pad * g.K + bs - 1) / bs));
-  if (g.n == 8)
-    hipLaunchKernelGGL((k_prep_ranges<Pix, 8>), rgrid, dim3(bs), 0, st, g, img,
-                       b);
-  else
-    hipLaunchKernelGGL((k_prep_ranges<Pix, 4>), rgrid, dim3(bs), 0, st, g, img,
-                       b);
+    hipLaunchKernelGGL((k_prep<Pix, 4>), grid, dim3(256), 0, st, g, img, b);
   return hipGetLastError();
 }
 
@@ -270,23 +247,22 @@ __global__ void k_batch_init(BatchDev bd) {
   }
 }
 
+// Workgroups [0, phase_total[0]) prepare domains, the rest ranges, each
+// phase laid out slice after slice.
 template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_prep_domains_batch(BatchDev bd) {
-  const int s = slice_of(bd.phase_off, bd.n, blockIdx.x);
+__global__ __launch_bounds__(256) void k_prep_batch(BatchDev bd) {
+  const int bid = blockIdx.x;
+  const bool dom = bid < bd.phase_total[0];
+  const int *off = bd.phase_off + (dom ? 0 : bd.n + 1);
+  const int pb = dom ? bid : bid - bd.phase_total[0];
+  const int s = slice_of(off, bd.n, pb);
   const Geo g = load_uniform(&bd.tab[s].g);
   const EncBufs b = load_uniform(&bd.tab[s].b);
-  prep_domains_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b,
-                            blockIdx.x - bd.phase_off[s]);
-}
-
-template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_prep_ranges_batch(BatchDev bd) {
-  const int *off = bd.phase_off + (bd.n + 1);
-  const int s = slice_of(off, bd.n, blockIdx.x);
-  const Geo g = load_uniform(&bd.tab[s].g);
-  const EncBufs b = load_uniform(&bd.tab[s].b);
-  prep_ranges_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b,
-                           blockIdx.x - off[s]);
+  const Pix *img = (const Pix *)load_uniform(&bd.tab[s].image);
+  if (dom)
+    prep_domains_body<Pix, N>(g, img, b, pb - off[s]);
+  else
+    prep_ranges_body<Pix, N>(g, img, b, pb - off[s]);
 }
 
 template <typename Pix, int N>
@@ -305,22 +281,17 @@ __global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
 hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_init, dim3((bd.n + 255) / 256), dim3(256), 0, st,
                      bd);
+  const dim3 grid(bd.phase_total[0] + bd.phase_total[1]);
   if (bd.bits == 12) {
-    if (bd.rsize == 8) {
-      hipLaunchKernelGGL((k_prep_domains_batch<uint16_t, 8>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
-      hipLaunchKernelGGL((k_prep_ranges_batch<uint16_t, 8>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
-    } else {
-      hipLaunchKernelGGL((k_prep_domains_batch<uint16_t, 4>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
-      hipLaunchKernelGGL((k_prep_ranges_batch<uint16_t, 4>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
-    }
+    if (bd.rsize == 8)
+      hipLaunchKernelGGL((k_prep_batch<uint16_t, 8>), grid, dim3(256), 0, st, bd);
+    else
+      hipLaunchKernelGGL((k_prep_batch<uint16_t, 4>), grid, dim3(256), 0, st, bd);
   } else {
-    if (bd.rsize == 8) {
-      hipLaunchKernelGGL((k_prep_domains_batch<uint8_t, 8>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
-      hipLaunchKernelGGL((k_prep_ranges_batch<uint8_t, 8>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
-    } else {
-      hipLaunchKernelGGL((k_prep_domains_batch<uint8_t, 4>), dim3(bd.phase_total[0]), dim3(256), 0, st, bd);
-      hipLaunchKernelGGL((k_prep_ranges_batch<uint8_t, 4>), dim3(bd.phase_total[1]), dim3(256), 0, st, bd);
-    }
+    if (bd.rsize == 8)
+      hipLaunchKernelGGL((k_prep_batch<uint8_t, 8>), grid, dim3(256), 0, st, bd);
+    else
+      hipLaunchKernelGGL((k_prep_batch<uint8_t, 4>), grid, dim3(256), 0, st, bd);
   }
   return hipGetLastError();
 }
@@ -350,7 +321,7 @@ hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
                            fic_codes out, hipStream_t st) {
   const int bs = 256;
-  const dim3 grid((unsigned)(((long long)g.R * g.K + bs - 1) / bs));
+  const dim3 grid((unsigned)(((long long)g.R_pad * g.K + bs - 1) / bs));
   if (g.bits == 12) {
     if (g.n == 8)
       hipLaunchKernelGGL((k_finalize<uint16_t, 8>), grid, dim3(bs), 0, st, g,

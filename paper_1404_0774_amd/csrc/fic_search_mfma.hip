@@ -67,16 +67,25 @@ __device__ __forceinline__ bool pair_passes(float gmx, float gmn, float csa,
   return mm * mm >= wp * cdp;
 }
 
+// Reload the lane's 8 prune weights.  Lane l < 16 computes the weight of
+// wave range l once and stores it at wtab[h][s] (range 4 (s / 2) + 2 h +
+// s mod 2); every lane then reads the 8 weights of its half-wave h.
 __device__ __forceinline__ void refresh_weights(float *wp,
                                                 const unsigned long long *best,
-                                                const double2 *rstat, int h,
+                                                const double2 *rstat,
+                                                float *wtab, int h, int lane,
                                                 const Geo &g) {
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const int lr = 4 * (s >> 1) + 2 * h + (s & 1);
-    const double2 rs = rstat[lr];
-    wp[s] = weight_from_key(best[lr], (double)g.K * rs.y - rs.x * rs.x, g);
+  if (lane < kWaveRanges) {
+    const double2 rs = rstat[lane];
+    const float wv =
+        weight_from_key(best[lane], (double)g.K * rs.y - rs.x * rs.x, g);
+    wtab[((lane >> 1) & 1) * kSlots + 2 * (lane >> 2) + (lane & 1)] = wv;
   }
+  __builtin_amdgcn_wave_barrier();
+  const float4 *wt = (const float4 *)(wtab + h * kSlots);
+  const float4 w0 = wt[0], w1 = wt[1];
+  wp[0] = w0.x; wp[1] = w0.y; wp[2] = w0.z; wp[3] = w0.w;
+  wp[4] = w1.x; wp[5] = w1.y; wp[6] = w1.z; wp[7] = w1.w;
 }
 
 // Process the first n queued pairs (64 per round, one per lane): re-test
@@ -160,6 +169,7 @@ struct WaveState {
   double2 *rstat;            // LDS: (Sb, Sbb) per range
   QEntry *queue;             // LDS: queued pairs
   Cand *cands;               // LDS: drain candidates
+  float *wtab;               // LDS: prune weights [2][kSlots]
   int qn;                    // queued pairs (wave-uniform)
   unsigned long long gsnap;  // global keys as last seen (lanes < 16)
   int wr0, h, cl, lane;
@@ -216,12 +226,16 @@ __device__ __forceinline__ void sweep_block(
       gmx[2 * rb + e] = __uint_as_float(ux);
       gmn[2 * rb + e] = __uint_as_float(un);
     }
-  bool any_pass = false;
+  // wave masks of the passing pairs, one per slot (scalar registers)
+  unsigned long long pm[kSlots], anym = 0;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s)
-    any_pass |= pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
+  for (int s = 0; s < kSlots; ++s) {
+    pm[s] = __builtin_amdgcn_ballot_w64(
+        pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp));
+    anym |= pm[s];
+  }
 
-  if (__any(any_pass)) {
+  if (anym != 0) {
     // append every passing pair, with its 8 G values, to the wave's queue
     // (ballot + mbcnt give each lane its position)
     const int cdl = sd.dom << 4;
@@ -231,9 +245,9 @@ __device__ __forceinline__ void sweep_block(
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int s = 2 * rb + e;
-        const bool ps = pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp);
-        const unsigned long long m = __builtin_amdgcn_ballot_w64(ps);
+        const unsigned long long m = pm[s];
         if (m == 0) continue;
+        const bool ps = (m >> w.lane) & 1;
         if (ps) {
           const int off = __builtin_amdgcn_mbcnt_hi(
               (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
@@ -252,7 +266,7 @@ __device__ __forceinline__ void sweep_block(
           drained = true;
         }
       }
-    if (drained) refresh_weights(wp, w.best, w.rstat, w.h, g);
+    if (drained) refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   }
 
   const int jn = cb - c0 + 1;  // blocks done in this chunk
@@ -268,7 +282,7 @@ __device__ __forceinline__ void sweep_block(
       if (m < w.gsnap) atomicMin(&b.best[w.wr0 + w.lane], m);
       w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
     }
-    refresh_weights(wp, w.best, w.rstat, w.h, g);
+    refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   }
 }
 
@@ -289,6 +303,7 @@ struct SearchLds {
   double2 rstat[4][kWaveRanges];  // (Sb, Sbb) of each range
   QEntry queue[4][kQueue];
   Cand cands[4][8 * 64];
+  float wtab[4][2 * kSlots];
 };
 
 // The workgroup's 64 ranges (row group rg) against column blocks [c0, c1).
@@ -307,6 +322,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.rstat = lds.rstat[wave];
   w.queue = lds.queue[wave];
   w.cands = lds.cands[wave];
+  w.wtab = lds.wtab[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
   if (w.lane < kWaveRanges) {
@@ -337,7 +353,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   for (int s = 0; s < kSlots; ++s)
     bbar[s] = (float)(b.rng_sb[w.wr0 + 4 * (s >> 1) + 2 * w.h + (s & 1)] / K);
   __builtin_amdgcn_wave_barrier();
-  refresh_weights(wp, w.best, w.rstat, w.h, g);
+  refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
 
   if (c0 >= c1) return;
 

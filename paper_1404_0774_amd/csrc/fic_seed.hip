@@ -1,13 +1,18 @@
-// fic_seed.hip -- dense exact evaluation of the first column blocks.
+// fic_seed.hip -- seeding of every range's best key before the search.
 //
-// Before the pruned search starts, every range needs a good best residual:
-// the least-squares prune is only as tight as that bound, and a cold start
-// lets a large share of the first block's candidates through.  This kernel
-// fits every candidate of the first `nblocks` column blocks exactly (no
-// prune), spread over the whole GPU, and lowers each range's seeded key.
+// Flat domains (no variance) all fit a range with s = 0 and the range mean
+// (eqs. 11-12), so they tie and only the first of them can be kept; the
+// search skips them and this kernel offers that one candidate to every
+// range.  Before the pruned search starts, every range also needs a good
+// best residual: the least-squares prune is only as tight as that bound, and
+// a cold start lets a large share of the first block's candidates through.
+// So the kernel also fits every candidate of the first `nblocks` column
+// blocks exactly (no prune; nblocks may be 0), spread over the whole GPU,
+// and lowers each range's seeded key.
 // The sweep order puts a quasi-uniform sample of the image's domains in any
 // prefix of columns, so one or two blocks already give a bound close to the
 // final one.
+#include <limits.h>
 #include <math.h>
 
 #include "fic_device.h"
@@ -36,13 +41,30 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   __shared__ float s_sa[32], s_dp[32];
   __shared__ double s_saa[32];
   __shared__ int s_dom[32];
+  __shared__ int s_ff;
   const int t = threadIdx.x;
   const int row = t >> 2, cgp = t & 3;
   const int rl = row >> 3, k = row & 7;
   const int r = bid * 8 + rl;
 
+  // the first flat domain: minimum over the domain-preparation workgroups
+  if (t == 0) s_ff = INT_MAX;
+  __syncthreads();
+  {
+    int mf = INT_MAX;
+    for (int i = t; i < g.n_dwg; i += 256) mf = min(mf, b.flat_min[i]);
+    if (mf != INT_MAX) atomicMin(&s_ff, mf);
+  }
+  const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
+  unsigned long long best = ~0ull;
+  __syncthreads();
+  if ((t & 31) == 0 && s_ff < g.ND) {
+    const Fit ff = fit_exact(0.0, 0.0, 0.0, Sb, Sbb, g);
+    best = make_key(ff.err, 8ll * s_ff, g);
+  }
+
   // the workgroup's 64 rows (8 ranges x 8 transforms) of the range operand
-  for (int i = t; i < NP * 64 * PER; i += 256) {
+  for (int i = t; nblocks > 0 && i < NP * 64 * PER; i += 256) {
     const int pl = i / (64 * PER), ii = i % (64 * PER);
     const int rw = ii / PER, p0 = (ii % PER) * 8;
     const half8_t v = *(const half8_t *)(b.aop + (size_t)pl * g.R_pad * 8 * K +
@@ -51,9 +73,6 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     for (int e = 0; e < 4; ++e)
       sA[pl][p0 / 2 + e][rw] = half2_t{v[2 * e], v[2 * e + 1]};
   }
-  const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
-  unsigned long long best = ~0ull;
-
   for (int cb = 0; cb < nblocks; ++cb) {
     __syncthreads();
     for (int i = t; i < NP * 32 * PER; i += 256) {
@@ -127,7 +146,8 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     const unsigned long long v = __shfl_xor(best, o, 32);
     best = v < best ? v : best;
   }
-  if ((t & 31) == 0 && r < g.R && best < b.best[r]) b.best[r] = best;
+  if ((t & 31) == 0 && range_of_slot(g, r) < g.R && best < b.best[r])
+    b.best[r] = best;
 }
 
 template <int K, bool B12>
@@ -148,7 +168,6 @@ __global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
       hi = mid - 1;
   }
   const int nb = min(nblocks, bd.tab[lo].seed_blocks);
-  if (nb <= 0) return;
   const Geo g = load_uniform(&bd.tab[lo].g);
   const EncBufs b = load_uniform(&bd.tab[lo].b);
   seed_dense_body<K, B12>(g, b, nb, blockIdx.x - off[lo]);
@@ -157,7 +176,6 @@ __global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
 }  // namespace
 
 hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
   auto kern = bd.bits == 12 ? (bd.rsize == 8 ? k_seed_batch<64, true>
                                              : k_seed_batch<16, true>)
                             : (bd.rsize == 8 ? k_seed_batch<64, false>
@@ -169,7 +187,6 @@ hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
 
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
   const dim3 grid(g.R_pad / 8);
   auto kern = g.bits == 12 ? (g.K == 64 ? k_seed_dense<64, true>
                                         : k_seed_dense<16, true>)
