@@ -122,22 +122,27 @@ def trace_summary(stats_dir, command):
 
 
 def time_encode(F, torch, timg, p, ws, steps, warmup):
-    """Mean ms per fic_encode and per phase (library HIP events on the call's
-    stream: prep, seed, search, finalize)."""
+    """Mean ms per fic_encode over `steps` back-to-back calls (two events
+    around the whole run), then the per-phase split from a second run with
+    the library's phase events (prep, seed, search, finalize) switched on."""
     dev = timg.device
     for _ in range(warmup):
         out = F.encode(timg, p, workspace=ws)
     torch.cuda.synchronize(dev)
-    F.timing_begin()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
         out = F.encode(timg, p, workspace=ws)
     e1.record()
     torch.cuda.synchronize(dev)
+    ms = e0.elapsed_time(e1) / steps
+    F.timing_begin()
+    for _ in range(steps):
+        F.encode(timg, p, workspace=ws)
+    torch.cuda.synchronize(dev)
     n, ms_prep, ms_seed, ms_search, ms_fin = F.timing_end()
-    return out, e0.elapsed_time(e1) / steps, {"prep": ms_prep / n, "seed": ms_seed / n,
-                                              "search": ms_search / n, "finalize": ms_fin / n}
+    return out, ms, {"prep": ms_prep / n, "seed": ms_seed / n,
+                     "search": ms_search / n, "finalize": ms_fin / n}
 
 
 def codes_np(out):
@@ -189,9 +194,10 @@ def main():
     R, ND, ws_bytes, _ = F.query(p)
     cand = 8 * R * ND
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
-    # the search kernel covers every column block after the densely seeded ones
+    # one search launch covers every candidate (the seed pass only ranks a
+    # few leading column blocks for a starting bound)
     seed_blocks = F.get_tuning(p)["seed_blocks"]
-    cand_search = 8 * R * (ND - 32 * seed_blocks)
+    cand_search = cand
     flops = 2.0 * n * n * cand_search     # MFMA FLOPs of one search launch
 
     out_m, ms_m, ph_m = time_encode(F, torch, timg, p, ws, args.steps, args.warmup)
@@ -248,7 +254,6 @@ def main():
         R12, ND12, ws12b, _ = F.query(p12)
         ws12 = torch.empty(ws12b + 256, dtype=torch.uint8, device=dev)
         c12 = 8 * R12 * ND12
-        sb12 = F.get_tuning(p12)["seed_blocks"]
         o12, ms12, ph12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
         p12.method = F.METHOD_DIRECT
         o12d, ms12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
@@ -258,8 +263,7 @@ def main():
             "candidates": c12, "value": c12 / (ms12 / 1e3), "unit": "comparisons/s",
             "ms_per_step": ms12, "phases_ms": ph12,
             # four FP16 partial products per searched candidate (hi/lo planes)
-            "mfma_frac": 4 * 2.0 * 64 * 8 * R12 * (ND12 - 32 * sb12) / (ph12["search"] / 1e3)
-                         / MFMA_FP16_PEAK,
+            "mfma_frac": 4 * 2.0 * 64 * c12 / (ph12["search"] / 1e3) / MFMA_FP16_PEAK,
             "direct_value": c12 / (ms12d / 1e3), "mfma_over_direct": ms12d / ms12,
             "codes_identical_mfma_direct": bool(same12)}
 

@@ -123,7 +123,7 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
  *   code arrays, as in fic_encode.  Call it whenever the slice shapes or
  *   pointers change, outside any stream capture.
  * fic_encode_batch -- enqueues the batch on `stream`: one launch per phase
- *   for all slices (operand preparation, dense seed block, search, code
+ *   for all slices (operand preparation, seed pass, search, code
  *   extraction); the search runs as a persistent grid that takes work items
  *   from a device counter.  It performs no allocation and no host-device
  *   copy, so a stream capture of it can be replayed as a graph.  `ticks`
@@ -195,13 +195,14 @@ int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
  * Launch-shape tuning (host only; no GPU work).  The search grid splits the
  * candidate table of eq. (8) into row groups of ranges and column chunks of
  * domains; these entries choose how many chunks, how many leading 32-column
- * blocks a dense pass fits first to seed each range's bound, and how many
+ * blocks a seed pass ranks first to give each range a starting bound (the
+ * search still covers every block), and how many
  * column blocks one work item of the batched search covers.  Any choice
  * yields the same codes; only speed changes.  An entry applies to encodes
  * with equal bit_depth, range_size and method and at least `min_domains`
  * domains; among those the largest min_domains wins.  A field of 0 (-1 for
  * seed_blocks) keeps the built-in default.  Values are clamped to the
- * problem (at least one chunk; seed_blocks below the column block count).
+ * problem (at least one chunk; at most every column block).
  *
  * fic_set_tuning -- replaces the table with n_entries entries (0 clears it).
  *   Errors: FIC_E_INVALID (NULL entries with n > 0, a field out of range:
@@ -222,7 +223,7 @@ typedef struct {
   int32_t bit_depth, range_size, method; /* key */
   int32_t min_domains;                   /* applies from this domain count */
   int32_t col_chunks;  /* column chunks per row group of the search grid */
-  int32_t seed_blocks; /* 32-column blocks fitted densely first; -1 default */
+  int32_t seed_blocks; /* 32-column blocks ranked by the seed; -1 default */
   int32_t item_blocks; /* batched search: column blocks per work item */
 } fic_tuning;
 

@@ -132,7 +132,7 @@ def main(argv=None):
     entries, records = [], []
     chunks = [2, 3, 4, 6, 8, 12, 16, 24, 32]
     img = torch.from_numpy(gen_image(512, 512, 8, 2)).to(dev)
-    e, r = tune_single("u8_512 mfma", img, F.Params(512, 512, 8, 8, 4), chunks, [0, 1, 2, 3],
+    e, r = tune_single("u8_512 mfma", img, F.Params(512, 512, 8, 8, 4), chunks, [0, 1, 2, 4, 8],
                        args.reps, dev, log)
     entries.append(e); records.append(r)
     if not args.skip_direct:
@@ -141,16 +141,16 @@ def main(argv=None):
         entries.append(e); records.append(r)
     img12 = torch.from_numpy(gen_image(512, 512, 12, 3).astype(np.int16)).to(dev)
     e, r = tune_single("ct12_512 mfma", img12, F.Params(512, 512, 12, 8, 2), [1, 2, 4, 8, 16, 32],
-                       [1, 2], max(3, args.reps // 3), dev, log)
+                       [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
     entries.append(e); records.append(r)
     img5 = torch.from_numpy(gen_image(256, 256, 8, 5)).to(dev)
-    e, r = tune_single("u8_256 n4 mfma", img5, F.Params(256, 256, 8, 4, 4), chunks, [1, 2],
+    e, r = tune_single("u8_256 n4 mfma", img5, F.Params(256, 256, 8, 4, 4), chunks, [0, 1, 2, 4],
                        args.reps, dev, log)
     entries.append(e); records.append(r)
     sides = batch_sides(64)
     bimgs = [torch.from_numpy(gen_image(s, s, 8, 4000 + i)).to(dev) for i, s in enumerate(sides)]
     bparams = [F.Params(s, s, 8, 8, 8) for s in sides]
-    batch_entry, r = tune_batch(bimgs, bparams, [8, 16, 32, 64, 128, 256], [0, 1, 2],
+    batch_entry, r = tune_batch(bimgs, bparams, [8, 16, 32, 64, 128, 256], [0, 1, 2, 4],
                                 max(3, args.reps // 3), dev, log)
     entries.append(batch_entry); records.append(r)
 

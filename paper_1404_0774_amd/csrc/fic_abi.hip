@@ -229,17 +229,18 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   hipError_t e = launch_prep(g, image, b, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
   timing_mark(1, s);
-  // leading column blocks are fitted densely to seed every range's bound
+  // the seed pass ranks the leading column blocks to give every range a
+  // starting bound; the search still covers every column block
   const Tune t = resolve_tune(g, p->method);
   e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
   timing_mark(2, s);
   if (p->method == FIC_METHOD_DIRECT)
-    e = launch_search_direct(g, b, t.chunks, t.seed_blocks, s);
+    e = launch_search_direct(g, b, t.chunks, 0, s);
   else if (g.bits == 12)
-    e = launch_search_mfma12(g, b, t.chunks, t.seed_blocks, s);
+    e = launch_search_mfma12(g, b, t.chunks, 0, s);
   else
-    e = launch_search_mfma(g, b, t.chunks, t.seed_blocks, s);
+    e = launch_search_mfma(g, b, t.chunks, 0, s);
   if (e != hipSuccess) return hip_fail(e, "search");
   timing_mark(3, s);
   e = launch_finalize(g, image, b, out, s);

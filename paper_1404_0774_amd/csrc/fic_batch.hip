@@ -50,8 +50,7 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
   // and row groups inner so that workgroups running together share domains
   std::vector<long long> cost(n);
   for (int s = 0; s < n; ++s)
-    cost[s] = (long long)(pl.geo[s].R_pad / kMfmaRangesPerWG) *
-              (pl.geo[s].NCB - pl.tune[s].seed_blocks);
+    cost[s] = (long long)(pl.geo[s].R_pad / kMfmaRangesPerWG) * pl.geo[s].NCB;
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
@@ -62,7 +61,7 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
     const Geo &g = pl.geo[s];
     const Tune &t = pl.tune[s];
     const int rg = g.R_pad / kMfmaRangesPerWG;
-    for (int c0 = t.seed_blocks; c0 < g.NCB; c0 += t.item_blocks)
+    for (int c0 = 0; c0 < g.NCB; c0 += t.item_blocks)
       for (int r = 0; r < rg; ++r) {
         pl.items.push_back(int4{s, r, c0, std::min(c0 + t.item_blocks, g.NCB)});
         ++pl.items_per_slice[s];

@@ -99,11 +99,11 @@ hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st);
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
-                              int seeded_blocks, hipStream_t st);
+                              int first_block, hipStream_t st);
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
-                                int seeded_blocks, hipStream_t st);
+                                int first_block, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                int seeded_blocks, hipStream_t st);
+                                int first_block, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
                            fic_codes out, hipStream_t st);
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
@@ -132,10 +132,10 @@ constexpr int kDirectRangesPerWG = 32;
 
 // Launch shape of one encode, resolved from the tuning table (fic_tuning.hip)
 // with the library defaults for anything the table leaves open.  Always
-// 1 <= chunks <= NCB - seed_blocks and 0 <= seed_blocks < NCB.
+// 1 <= chunks <= NCB and 0 <= seed_blocks <= NCB.
 struct Tune {
   int chunks;       // column chunks per row group of the search grid
-  int seed_blocks;  // leading column blocks fitted densely before the search
+  int seed_blocks;  // leading column blocks ranked by the seed pass
   int item_blocks;  // batched search: column blocks per work item
 };
 Tune resolve_tune(const Geo &g, int method);

@@ -209,8 +209,8 @@ __global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b,
 }  // namespace
 
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                int seeded_blocks, hipStream_t st) {
-  const int rest = g.NCB - seeded_blocks;
+                                int first_block, hipStream_t st) {
+  const int rest = g.NCB - first_block;
   if (rest <= 0) return hipSuccess;
   if (chunks > rest) chunks = rest;
   if (chunks < 1) chunks = 1;
@@ -220,19 +220,19 @@ hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
     const dim3 grid12(nchunks, g.R_pad / 16);
     if (g.K == 64)
       hipLaunchKernelGGL(k_search_direct_12<64>, grid12, dim3(256), 0, st, g,
-                         b, seeded_blocks, cbpc);
+                         b, first_block, cbpc);
     else
       hipLaunchKernelGGL(k_search_direct_12<16>, grid12, dim3(256), 0, st, g,
-                         b, seeded_blocks, cbpc);
+                         b, first_block, cbpc);
     return hipGetLastError();
   }
   dim3 grid(nchunks, g.R_pad / kDirectRangesPerWG);
   if (g.K == 64)
     hipLaunchKernelGGL(k_search_direct_u8<64>, grid, dim3(256), 0, st, g, b,
-                       seeded_blocks, cbpc);
+                       first_block, cbpc);
   else
     hipLaunchKernelGGL(k_search_direct_u8<16>, grid, dim3(256), 0, st, g, b,
-                       seeded_blocks, cbpc);
+                       first_block, cbpc);
   return hipGetLastError();
 }
 

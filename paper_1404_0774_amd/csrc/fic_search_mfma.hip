@@ -430,11 +430,11 @@ hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st) {
 }
 
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
-                              int seeded_blocks, hipStream_t st) {
+                              int first_block, hipStream_t st) {
   static_assert(4 * kWaveRanges == kMfmaRangesPerWG, "tile");
   if (g.bits != 8) return hipErrorInvalidValue;
   const int rg = g.R_pad / kMfmaRangesPerWG;
-  const int rest = g.NCB - seeded_blocks;
+  const int rest = g.NCB - first_block;
   if (rest <= 0) return hipSuccess;
   if (chunks > rest) chunks = rest;
   if (chunks < 1) chunks = 1;
@@ -442,7 +442,7 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
   const int nchunks = (rest + cbpc - 1) / cbpc;
   auto kern = g.K == 64 ? k_search_mfma_u8<64> : k_search_mfma_u8<16>;
   hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b,
-                     seeded_blocks, g.NCB, cbpc);
+                     first_block, g.NCB, cbpc);
   return hipGetLastError();
 }
 

@@ -314,11 +314,11 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
 }  // namespace
 
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
-                                int seeded_blocks, hipStream_t st) {
+                                int first_block, hipStream_t st) {
   if (g.bits != 12) return hipErrorInvalidValue;
   static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
   const int rg = g.R_pad / (4 * kWR);
-  const int rest = g.NCB - seeded_blocks;
+  const int rest = g.NCB - first_block;
   if (rest <= 0) return hipSuccess;
   if (chunks > rest) chunks = rest;
   if (chunks < 1) chunks = 1;
@@ -326,7 +326,7 @@ hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
   const int nchunks = (rest + cbpc - 1) / cbpc;
   auto kern = g.K == 64 ? k_search_mfma_12<64> : k_search_mfma_12<16>;
   hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b,
-                     seeded_blocks, g.NCB, cbpc);
+                     first_block, g.NCB, cbpc);
   return hipGetLastError();
 }
 

@@ -30,6 +30,11 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 // planes (b = 64 b_hi + b_lo, A = 128 A_hi + A_lo); the four partial sums
 // are exact in FP32 and G is rebuilt exactly in FP64.  Both operands are
 // staged in LDS as FP16 pairs.
+//
+// The seed only has to be some candidate's exact residual (any one is a
+// valid bound), so candidates are ranked by their least-squares score
+// N'^2 / D' in FP32 (the unquantised residual is (V - N'^2/D') / K), and
+// only each range's top-ranked candidate is fitted exactly in FP64.
 template <int K, bool B12>
 __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
                                                 int nblocks, int bid) {
@@ -38,9 +43,7 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   constexpr int PER = K / 8;                      // 16-byte words per row
   __shared__ __attribute__((aligned(16))) half2_t sA[NP][KP][64];
   __shared__ __attribute__((aligned(16))) half2_t sB[NP][KP][32];
-  __shared__ float s_sa[32], s_dp[32];
-  __shared__ double s_saa[32];
-  __shared__ int s_dom[32];
+  __shared__ float s_sa[32], s_idp[32];
   __shared__ int s_ff;
   const int t = threadIdx.x;
   const int row = t >> 2, cgp = t & 3;
@@ -49,20 +52,10 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
 
   // the first flat domain: minimum over the domain-preparation workgroups
   if (t == 0) s_ff = INT_MAX;
-  __syncthreads();
-  {
-    int mf = INT_MAX;
-    for (int i = t; i < g.n_dwg; i += 256) mf = min(mf, b.flat_min[i]);
-    if (mf != INT_MAX) atomicMin(&s_ff, mf);
-  }
+  int mf = INT_MAX;
+  for (int i = t; i < g.n_dwg; i += 256) mf = min(mf, b.flat_min[i]);
   const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
-  unsigned long long best = ~0ull;
-  __syncthreads();
-  if ((t & 31) == 0 && s_ff < g.ND) {
-    const Fit ff = fit_exact(0.0, 0.0, 0.0, Sb, Sbb, g);
-    best = make_key(ff.err, 8ll * s_ff, g);
-  }
-
+  const float sbf = (float)Sb;
   // the workgroup's 64 rows (8 ranges x 8 transforms) of the range operand
   for (int i = t; nblocks > 0 && i < NP * 64 * PER; i += 256) {
     const int pl = i / (64 * PER), ii = i % (64 * PER);
@@ -73,8 +66,17 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     for (int e = 0; e < 4; ++e)
       sA[pl][p0 / 2 + e][rw] = half2_t{v[2 * e], v[2 * e + 1]};
   }
+  __syncthreads();
+  if (mf != INT_MAX) atomicMin(&s_ff, mf);
+
+  float bscore = -1.0f;  // best N'^2 / D' seen by this thread
+  float bg[NP * NP];     // its partial sums
+  int bcol = -1;         // and its column
+#pragma unroll
+  for (int x = 0; x < NP * NP; ++x) bg[x] = 0.0f;
+
   for (int cb = 0; cb < nblocks; ++cb) {
-    __syncthreads();
+    if (cb > 0) __syncthreads();
     for (int i = t; i < NP * 32 * PER; i += 256) {
       const int pl = i / (32 * PER), ii = i % (32 * PER);
       const int col = ii / PER, p0 = (ii % PER) * 8;
@@ -85,12 +87,10 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
         sB[pl][p0 / 2 + e][col] = half2_t{v[2 * e], v[2 * e + 1]};
     }
     if (t < 32) {
-      const int col = cb * 32 + t;
-      const float2 sadp = b.col_sadp[col];
+      const float2 sadp = b.col_sadp[cb * 32 + t];
       s_sa[t] = sadp.x;
-      s_dp[t] = sadp.y;
-      s_saa[t] = b.col_saa[col];
-      s_dom[t] = b.col_dom[col];
+      // flat domains are seeded separately; padding columns are not domains
+      s_idp[t] = sadp.y == __builtin_inff() ? -1.0f : 1.0f / sadp.y;
     }
     __syncthreads();
 
@@ -126,28 +126,51 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int cc = 8 * cgp + c;
-      // flat domains are seeded separately; padding columns are not domains
-      if (s_dp[cc] == __builtin_inff()) continue;
+      const float idp = s_idp[cc];
       // 12-bit: G = 8192 G_hh + 128 G_(A_hi b_lo) + 64 G_(A_lo b_hi) + G_ll
-      const double G =
-          B12 ? 8192.0 * acc[0][0][c] + 128.0 * acc[1][0][c] +
-                    64.0 * acc[0][NP - 1][c] + (double)acc[NP - 1][NP - 1][c]
-              : (double)acc[0][0][c];
-      const Fit f = fit_exact(G, (double)s_sa[cc], s_saa[cc], Sb, Sbb, g);
-      const unsigned long long key =
-          make_key(f.err, 8ll * s_dom[cc] + k, g);
-      best = key < best ? key : best;
+      const float gf = B12 ? fmaf(8192.0f, acc[0][0][c],
+                                  fmaf(128.0f, acc[1][0][c],
+                                       fmaf(64.0f, acc[0][NP - 1][c],
+                                            acc[NP - 1][NP - 1][c])))
+                           : acc[0][0][c];
+      const float np = fmaf((float)g.K, gf, -s_sa[cc] * sbf);
+      const float score = idp < 0.0f ? -1.0f : np * np * idp;
+      if (score > bscore) {
+        bscore = score;
+        bcol = cb * 32 + cc;
+#pragma unroll
+        for (int x = 0; x < NP; ++x)
+#pragma unroll
+          for (int y = 0; y < NP; ++y) bg[x * NP + y] = acc[x][y][c];
+      }
     }
   }
 
-  // minimum over the 32 threads (8 transforms x 4 column groups) of a range
+  __syncthreads();  // s_ff is final
+  // the top-ranked candidate of each range (8 transforms x 4 column groups =
+  // 32 threads): the lowest thread holding the maximum fits it exactly
+  float m = bscore;
 #pragma unroll
-  for (int o = 1; o < 32; o <<= 1) {
-    const unsigned long long v = __shfl_xor(best, o, 32);
-    best = v < best ? v : best;
+  for (int o = 1; o < 32; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 32));
+  const unsigned long long bal = __builtin_amdgcn_ballot_w64(bscore == m);
+  const unsigned grp = (unsigned)(bal >> (t & 32));
+  if ((t & 31) != __builtin_ctz(grp)) return;
+  unsigned long long key = ~0ull;
+  if (s_ff < g.ND) {
+    // a flat domain fits with s = 0 and the range mean (eqs. 11-12)
+    const Fit ff = fit_exact(0.0, 0.0, 0.0, Sb, Sbb, g);
+    key = make_key(ff.err, 8ll * s_ff, g);
   }
-  if ((t & 31) == 0 && range_of_slot(g, r) < g.R && best < b.best[r])
-    b.best[r] = best;
+  if (bcol >= 0) {
+    const double G = B12 ? 8192.0 * bg[0] + 128.0 * bg[2] + 64.0 * bg[1] +
+                               (double)bg[3]
+                         : (double)bg[0];
+    const Fit f = fit_exact(G, (double)b.col_sadp[bcol].x, b.col_saa[bcol],
+                            Sb, Sbb, g);
+    const unsigned long long k2 = make_key(f.err, 8ll * b.col_dom[bcol] + k, g);
+    key = k2 < key ? k2 : key;
+  }
+  if (range_of_slot(g, r) < g.R && key < b.best[r]) b.best[r] = key;
 }
 
 template <int K, bool B12>

@@ -30,8 +30,8 @@ constexpr int kMaxSeedBlocks = 64;
 constexpr int kMaxItemBlocks = 4096;
 
 // Built-in defaults: about two workgroups per compute unit (256 CUs) in the
-// search launch, one seed block once there are 16 or more column blocks,
-// 16 column blocks per batched work item.
+// search launch, one seed block (ranked for a starting bound) once there are
+// 16 or more column blocks, 16 column blocks per batched work item.
 Tune default_tune(const Geo &g, int method) {
   const int per_wg = (g.bits == 12 && method == FIC_METHOD_MFMA)
                          ? kMfma12RangesPerWG
@@ -245,9 +245,8 @@ Tune resolve_tune(const Geo &g, int method) {
       if (pick->item_blocks > 0) t.item_blocks = pick->item_blocks;
     }
   }
-  // every slice keeps at least one column block for the search proper
-  t.seed_blocks = std::max(0, std::min(t.seed_blocks, g.NCB - 1));
-  t.chunks = std::max(1, std::min(t.chunks, g.NCB - t.seed_blocks));
+  t.seed_blocks = std::max(0, std::min(t.seed_blocks, g.NCB));
+  t.chunks = std::max(1, std::min(t.chunks, g.NCB));
   t.item_blocks = std::max(1, t.item_blocks);
   return t;
 }

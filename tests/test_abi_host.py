@@ -177,10 +177,10 @@ def test_tuning_table_selection(clean_tuning):
     assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (5, 1, 16)
     small = F.Params(128, 128, 8, 8, 4)              # 841 domains: first entry
     assert F.get_tuning(small)["col_chunks"] == 4
-    # clamping: seed below the block count, chunks within what is left
+    # clamping: seed and chunks at most the block count
     F.set_tuning([dict(bit_depth=8, range_size=4, method=0, col_chunks=4096, seed_blocks=64)])
     t = F.get_tuning(F.Params(64, 64, 8, 4, 4))      # 8 column blocks
-    assert t["seed_blocks"] == 7 and t["col_chunks"] == 1
+    assert t["seed_blocks"] == 8 and t["col_chunks"] == 8
     F.set_tuning([])
     assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 8
 
