@@ -167,18 +167,36 @@ __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
 
 // One group of K lanes per range: unpack the winning key and recompute its
 // fit from the image to produce the code (domain, transform, s index,
-// o index, residual).
+// o index, residual).  Flat domains (no variance) all fit a range with s = 0
+// and the range mean (eqs. 11-12), so they tie and only the first of them
+// can win; the search skips them and the first one is compared here.
 template <typename Pix, int N>
 __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
                                               const EncBufs &b,
                                               const fic_codes &out, int bid) {
   constexpr int K = N * N;
+  __shared__ int s_ff;
+  if (threadIdx.x == 0) s_ff = INT_MAX;
+  __syncthreads();
+  {
+    int mf = INT_MAX;
+    for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
+      mf = min(mf, b.flat_min[i]);
+    if (mf != INT_MAX) atomicMin(&s_ff, mf);
+  }
+  __syncthreads();
+  const int ff = s_ff;
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
   const int slot = (int)(t / K), q = (int)(t % K);
   if (slot >= g.R_pad) return;
   const int r = range_of_slot(g, slot);  // image range of the slot
   if (r >= g.R) return;  // padding: whole groups of K lanes leave together
-  const unsigned long long key = b.best[slot];
+  unsigned long long key = b.best[slot];
+  if (ff < g.ND) {
+    const Fit f0 = fit_exact(0.0, 0.0, 0.0, b.rng_sb[slot], b.rng_sbb[slot], g);
+    const unsigned long long kf = make_key(f0.err, 8ll * ff, g);
+    key = kf < key ? kf : key;
+  }
   const long long c = (long long)(key & ((1ull << g.cbits) - 1));
   const int d = (int)(c >> 3), k = (int)(c & 7);
   const int i = q / N, j = q % N, m = N - 1;

@@ -286,6 +286,69 @@ __device__ __forceinline__ void sweep_block(
   }
 }
 
+// Starting bound from the workgroup's first column block: per range, the
+// (range, domain) pair whose best transform has the largest least-squares
+// score (G - SA Sb/K)^2 / D' over the block's 32 domains is queued and its
+// transforms are fitted exactly.  (The sweep then covers the block as usual.)
+template <int K>
+__device__ __forceinline__ void seed_first_block(
+    const Geo &g, WaveState &w, const half8 (&af)[kRB][K / 16],
+    const float (&bbar)[kSlots], const half8 (&bf)[K / 16], const ColRec &sd) {
+  constexpr int KS = K / 16;
+  f32x16 acc[kRB];
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb) {
+    acc[rb] = f32x16{};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk)
+      acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
+                                                       acc[rb], 0, 0, 0);
+  }
+  // flat domains and padding columns (D' = +inf) take no part
+  const bool live = sd.dp != __builtin_inff();
+  const float idp = live ? 1.0f / sd.dp : 0.0f;
+  const int cdl = sd.dom << 4;
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int s = 2 * rb + e;
+      const float c = sd.sa * bbar[s];
+      float sc = -1.0f;
+      if (live) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float d = acc[rb][8 * e + k] - c;
+          sc = fmaxf(sc, d * d * idp);
+        }
+      }
+      // the best column of each half-wave (its 32 lanes share the ranges)
+      float m = sc;
+#pragma unroll
+      for (int o = 1; o < 32; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 32));
+      const bool top = sc == m && m >= 0.0f;
+      const unsigned half =
+          (unsigned)(__builtin_amdgcn_ballot_w64(top) >> (32 * w.h));
+      const bool win = top && w.cl == __builtin_ctz(half);
+      const unsigned long long mw = __builtin_amdgcn_ballot_w64(win);
+      if (win) {
+        const int off = __builtin_amdgcn_mbcnt_hi(
+            (unsigned)(mw >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mw, 0));
+        QEntry *q = &w.queue[w.qn + off];
+        q->g0 = float4{acc[rb][8 * e], acc[rb][8 * e + 1], acc[rb][8 * e + 2],
+                       acc[rb][8 * e + 3]};
+        q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
+                       acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
+        *(uint4 *)&q->sa =
+            uint4{__float_as_uint(sd.sa), __float_as_uint(sd.dp), sd.saa,
+                  (unsigned)(cdl | (4 * rb + 2 * w.h + e))};
+      }
+      w.qn += __popcll(mw);  // at most 16 entries in all
+    }
+  __builtin_amdgcn_wave_barrier();
+  if (w.qn > 0) drain(w.queue, w.cands, w.qn, w.qn, w.best, w.rstat, g);
+}
+
 // grid: (chunks, R_pad / 64); block: 4 waves, each owning 16 ranges
 // (4 row blocks of 32 rows = 4 ranges x 8 transforms).  The workgroup sweeps
 // column blocks [cb_begin + x * cb_per_chunk, ...) of 32 domains each.
@@ -325,13 +388,19 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.wtab = lds.wtab[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
-  if (w.lane < kWaveRanges) {
-    w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
-    w.best[w.lane] = w.gsnap;
-    w.rstat[w.lane] =
-        double2{b.rng_sb[w.wr0 + w.lane], b.rng_sbb[w.wr0 + w.lane]};
-  }
+  if (c0 >= c1) return;
 
+  // every independent global load first: the first domain block, the range
+  // operand fragments, the range sums and the current keys
+  half8 bA[KS], bB[KS];  // two buffers for the streamed domain operand
+  ColRec sdA, sdB;
+  {
+    const int col = c0 * 32 + w.cl;
+    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * w.h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) bA[kk] = *(const half8 *)(bsrc + 16 * kk);
+    sdA = b.col_rec[col];
+  }
   half8 af[kRB][KS];
   {
     const int rho = w.lane & 31;
@@ -346,27 +415,23 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
         af[rb][kk] = *(const half8 *)(src + 16 * kk);
     }
   }
-
   // per lane: ranges wr0 + 4 rb + 2 h + e for slot s = 2 rb + e
   float wp[kSlots], bbar[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
-    bbar[s] = (float)(b.rng_sb[w.wr0 + 4 * (s >> 1) + 2 * w.h + (s & 1)] / K);
+    bbar[s] = (float)(b.rng_sb[w.wr0 + 4 * (s >> 1) + 2 * w.h + (s & 1)] *
+                      (1.0 / K));
+  if (w.lane < kWaveRanges) {
+    w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
+    w.best[w.lane] = w.gsnap;
+    w.rstat[w.lane] =
+        double2{b.rng_sb[w.wr0 + w.lane], b.rng_sbb[w.wr0 + w.lane]};
+  }
   __builtin_amdgcn_wave_barrier();
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
 
-  if (c0 >= c1) return;
-
-  // two register buffers for the streamed domain operand, used alternately
-  half8 bA[KS], bB[KS];
-  ColRec sdA, sdB;
-  {
-    const int col = c0 * 32 + w.cl;
-    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * w.h;
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bA[kk] = *(const half8 *)(bsrc + 16 * kk);
-    sdA = b.col_rec[col];
-  }
+  seed_first_block<K>(g, w, af, bbar, bA, sdA);
+  refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
     if (cb + 1 < c1)
@@ -382,9 +447,20 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
                                                            int cb_end,
                                                            int cb_per_chunk) {
   __shared__ SearchLds lds;
-  const int c0 = cb_begin + blockIdx.x * cb_per_chunk;
+  // Workgroups are dispatched to the 8 XCDs round-robin by linear id.  When
+  // the row groups split evenly over the XCDs, place all chunks of a row
+  // group on one XCD, so that its range operand is fetched into one L2
+  // (the streamed domain columns are the cheaper operand to replicate).
+  int chunk = blockIdx.x, rg = blockIdx.y;
+  if ((gridDim.y & 7) == 0) {
+    const int i = blockIdx.y * gridDim.x + blockIdx.x;
+    const int xcd = i & 7, j = i >> 3;
+    chunk = j % gridDim.x;
+    rg = xcd + 8 * (j / gridDim.x);
+  }
+  const int c0 = cb_begin + chunk * cb_per_chunk;
   const int c1 = min(c0 + cb_per_chunk, cb_end);
-  search_rows<K>(g, b, lds, blockIdx.y, c0, c1);
+  search_rows<K>(g, b, lds, rg, c0, c1);
 }
 
 // Many slices: a persistent grid whose workgroups take search items

@@ -1,17 +1,11 @@
-// fic_seed.hip -- seeding of every range's best key before the search.
+// fic_seed.hip -- a starting bound for every range before the search.
 //
-// Flat domains (no variance) all fit a range with s = 0 and the range mean
-// (eqs. 11-12), so they tie and only the first of them can be kept; the
-// search skips them and this kernel offers that one candidate to every
-// range.  Before the pruned search starts, every range also needs a good
-// best residual: the least-squares prune is only as tight as that bound, and
-// a cold start lets a large share of the first block's candidates through.
-// So the kernel also fits every candidate of the first `nblocks` column
-// blocks exactly (no prune; nblocks may be 0), spread over the whole GPU,
-// and lowers each range's seeded key.
-// The sweep order puts a quasi-uniform sample of the image's domains in any
-// prefix of columns, so one or two blocks already give a bound close to the
-// final one.
+// The least-squares prune is only as tight as each range's best residual so
+// far, and a cold start lets a large share of the first blocks' candidates
+// through.  This kernel ranks every candidate of the first `nblocks` column
+// blocks, spread over the whole GPU, and lowers each range's key with the
+// exact residual of its top-ranked candidate.  (The search itself still
+// covers these blocks.)
 #include <limits.h>
 #include <math.h>
 
@@ -44,16 +38,11 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   __shared__ __attribute__((aligned(16))) half2_t sA[NP][KP][64];
   __shared__ __attribute__((aligned(16))) half2_t sB[NP][KP][32];
   __shared__ float s_sa[32], s_idp[32];
-  __shared__ int s_ff;
   const int t = threadIdx.x;
   const int row = t >> 2, cgp = t & 3;
   const int rl = row >> 3, k = row & 7;
   const int r = bid * 8 + rl;
 
-  // the first flat domain: minimum over the domain-preparation workgroups
-  if (t == 0) s_ff = INT_MAX;
-  int mf = INT_MAX;
-  for (int i = t; i < g.n_dwg; i += 256) mf = min(mf, b.flat_min[i]);
   const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
   const float sbf = (float)Sb;
   // the workgroup's 64 rows (8 ranges x 8 transforms) of the range operand
@@ -67,7 +56,6 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
       sA[pl][p0 / 2 + e][rw] = half2_t{v[2 * e], v[2 * e + 1]};
   }
   __syncthreads();
-  if (mf != INT_MAX) atomicMin(&s_ff, mf);
 
   float bscore = -1.0f;  // best N'^2 / D' seen by this thread
   float bg[NP * NP];     // its partial sums
@@ -146,7 +134,6 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     }
   }
 
-  __syncthreads();  // s_ff is final
   // the top-ranked candidate of each range (8 transforms x 4 column groups =
   // 32 threads): the lowest thread holding the maximum fits it exactly
   float m = bscore;
@@ -156,11 +143,6 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   const unsigned grp = (unsigned)(bal >> (t & 32));
   if ((t & 31) != __builtin_ctz(grp)) return;
   unsigned long long key = ~0ull;
-  if (s_ff < g.ND) {
-    // a flat domain fits with s = 0 and the range mean (eqs. 11-12)
-    const Fit ff = fit_exact(0.0, 0.0, 0.0, Sb, Sbb, g);
-    key = make_key(ff.err, 8ll * s_ff, g);
-  }
   if (bcol >= 0) {
     const double G = B12 ? 8192.0 * bg[0] + 128.0 * bg[2] + 64.0 * bg[1] +
                                (double)bg[3]
@@ -199,6 +181,7 @@ __global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
 }  // namespace
 
 hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
   auto kern = bd.bits == 12 ? (bd.rsize == 8 ? k_seed_batch<64, true>
                                              : k_seed_batch<16, true>)
                             : (bd.rsize == 8 ? k_seed_batch<64, false>
@@ -210,6 +193,7 @@ hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
 
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
   const dim3 grid(g.R_pad / 8);
   auto kern = g.bits == 12 ? (g.K == 64 ? k_seed_dense<64, true>
                                         : k_seed_dense<16, true>)
