@@ -191,21 +191,6 @@ __global__ __launch_bounds__(256) void k_grad_so(Geo g, const int32_t *domain,
   }
 }
 
-// Inverse of sigma_k: the output pixel (i, j) that reads cell (ci, cj).
-__device__ __forceinline__ void sigma_inv(int k, int ci, int cj, int m, int &i,
-                                          int &j) {
-  switch (k & 7) {
-    case 0: i = ci;     j = cj;     break;
-    case 1: i = m - cj; j = ci;     break;
-    case 2: i = m - ci; j = m - cj; break;
-    case 3: i = cj;     j = m - ci; break;
-    case 4: i = ci;     j = m - cj; break;
-    case 5: i = cj;     j = ci;     break;
-    case 6: i = m - ci; j = cj;     break;
-    default: i = m - cj; j = m - ci; break;
-  }
-}
-
 // One thread per (segment, cell): the segment's share of s_r g_{t+1}[p] / 4
 // over the range pixels p that read that cell of the domain.
 // `nseg` points at the segment count the table build wrote (the grid is

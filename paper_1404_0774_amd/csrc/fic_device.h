@@ -24,6 +24,21 @@ __host__ __device__ inline void sigma(int k, int i, int j, int m, int &si,
   }
 }
 
+// Inverse of sigma_k: the output pixel (i, j) that reads cell (ci, cj).
+__host__ __device__ inline void sigma_inv(int k, int ci, int cj, int m, int &i,
+                                          int &j) {
+  switch (k & 7) {
+    case 0: i = ci;     j = cj;     break;
+    case 1: i = m - cj; j = ci;     break;
+    case 2: i = m - ci; j = m - cj; break;
+    case 3: i = cj;     j = m - ci; break;
+    case 4: i = ci;     j = m - cj; break;
+    case 5: i = cj;     j = ci;     break;
+    case 6: i = m - ci; j = cj;     break;
+    default: i = m - cj; j = m - ci; break;
+  }
+}
+
 // Result of the exact fit of one candidate.
 struct Fit {
   double err;  // eq. (8) with quantised s, o

@@ -175,36 +175,41 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
                                               const EncBufs &b,
                                               const fic_codes &out, int bid) {
   constexpr int K = N * N;
-  __shared__ int s_ff;
-  if (threadIdx.x == 0) s_ff = INT_MAX;
-  __syncthreads();
-  {
-    int mf = INT_MAX;
-    for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
-      mf = min(mf, b.flat_min[i]);
-    if (mf != INT_MAX) atomicMin(&s_ff, mf);
-  }
-  __syncthreads();
-  const int ff = s_ff;
+  __shared__ int s_wmin[8];  // per-wave minima of the flat-domain table
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
   const int slot = (int)(t / K), q = (int)(t % K);
-  if (slot >= g.R_pad) return;
-  const int r = range_of_slot(g, slot);  // image range of the slot
-  if (r >= g.R) return;  // padding: whole groups of K lanes leave together
-  unsigned long long key = b.best[slot];
+  const bool live = slot < g.R_pad;
+  const int r = live ? range_of_slot(g, slot) : g.R;  // image range
+  // independent loads first: the key, the range sums, the flat-domain table
+  const int i = q / N, j = q % N, m = N - 1;
+  unsigned long long key = ~0ull;
+  double Sb0 = 0.0, Sbb0 = 0.0, v = 0.0;
+  if (live && r < g.R) {
+    key = b.best[slot];
+    Sb0 = b.rng_sb[slot];
+    Sbb0 = b.rng_sbb[slot];
+    v = (double)img[(size_t)((r / g.RW) * N + i) * g.W + (r % g.RW) * N + j];
+  }
+  int mf = INT_MAX;
+  for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
+    mf = min(mf, b.flat_min[i]);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) mf = min(mf, __shfl_xor(mf, o));
+  if ((threadIdx.x & 63) == 0) s_wmin[threadIdx.x >> 6] = mf;
+  __syncthreads();
+  int ff = s_wmin[0];
+  for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) ff = min(ff, s_wmin[wv]);
+  if (!live || r >= g.R) return;  // padding: whole groups of K lanes leave
   if (ff < g.ND) {
-    const Fit f0 = fit_exact(0.0, 0.0, 0.0, b.rng_sb[slot], b.rng_sbb[slot], g);
+    const Fit f0 = fit_exact(0.0, 0.0, 0.0, Sb0, Sbb0, g);
     const unsigned long long kf = make_key(f0.err, 8ll * ff, g);
     key = kf < key ? kf : key;
   }
   const long long c = (long long)(key & ((1ull << g.cbits) - 1));
   const int d = (int)(c >> 3), k = (int)(c & 7);
-  const int i = q / N, j = q % N, m = N - 1;
-  const int ry = r / g.RW, rx = r % g.RW;
   const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
   int si, sj;
   sigma(k, i, j, m, si, sj);
-  const double v = (double)img[(size_t)(ry * N + i) * g.W + rx * N + j];
   const double A = (double)cell_sum(img, g.W, Y + 2 * si, X + 2 * sj);
   // integer sums below 2^53: exact in double in any order
   const double G = group_sum(A * v, K);

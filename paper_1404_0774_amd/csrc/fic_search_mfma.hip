@@ -286,10 +286,12 @@ __device__ __forceinline__ void sweep_block(
   }
 }
 
-// Starting bound from the workgroup's first column block: per range, the
-// (range, domain) pair whose best transform has the largest least-squares
-// score (G - SA Sb/K)^2 / D' over the block's 32 domains is queued and its
-// transforms are fitted exactly.  (The sweep then covers the block as usual.)
+// Starting bound from the workgroup's first column block.  Each lane ranks
+// the 8 transforms of each of its ranges against its column by the
+// least-squares score (G - SA Sb/K)^2 / D' and posts the best through LDS
+// (the empty candidate buffer); lane l < 16 then picks range l's best column
+// and fits that one candidate exactly.  Any candidate's exact residual is a
+// valid bound; the sweep then covers the block as usual.
 template <int K>
 __device__ __forceinline__ void seed_first_block(
     const Geo &g, WaveState &w, const half8 (&af)[kRB][K / 16],
@@ -307,46 +309,58 @@ __device__ __forceinline__ void seed_first_block(
   // flat domains and padding columns (D' = +inf) take no part
   const bool live = sd.dp != __builtin_inff();
   const float idp = live ? 1.0f / sd.dp : 0.0f;
-  const int cdl = sd.dom << 4;
+  // per (half, slot, column): score, and G << 3 | transform
+  float *sc_tab = (float *)w.cands;
+  unsigned *gk_tab = (unsigned *)w.cands + 2 * kSlots * 32;
+  ColRec *col_tab = (ColRec *)w.queue;
 #pragma unroll
   for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int s = 2 * rb + e;
       const float c = sd.sa * bbar[s];
-      float sc = -1.0f;
-      if (live) {
+      float best = -1.0f;
+      unsigned gk = 0;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
-          const float d = acc[rb][8 * e + k] - c;
-          sc = fmaxf(sc, d * d * idp);
+      for (int k = 0; k < 8; ++k) {
+        const float gv = acc[rb][8 * e + k];
+        const float d = gv - c;
+        const float v = live ? d * d * idp : -1.0f;
+        if (v > best) {
+          best = v;
+          gk = ((unsigned)gv << 3) | (unsigned)k;
         }
       }
-      // the best column of each half-wave (its 32 lanes share the ranges)
-      float m = sc;
-#pragma unroll
-      for (int o = 1; o < 32; o <<= 1) m = fmaxf(m, __shfl_xor(m, o, 32));
-      const bool top = sc == m && m >= 0.0f;
-      const unsigned half =
-          (unsigned)(__builtin_amdgcn_ballot_w64(top) >> (32 * w.h));
-      const bool win = top && w.cl == __builtin_ctz(half);
-      const unsigned long long mw = __builtin_amdgcn_ballot_w64(win);
-      if (win) {
-        const int off = __builtin_amdgcn_mbcnt_hi(
-            (unsigned)(mw >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)mw, 0));
-        QEntry *q = &w.queue[w.qn + off];
-        q->g0 = float4{acc[rb][8 * e], acc[rb][8 * e + 1], acc[rb][8 * e + 2],
-                       acc[rb][8 * e + 3]};
-        q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
-                       acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
-        *(uint4 *)&q->sa =
-            uint4{__float_as_uint(sd.sa), __float_as_uint(sd.dp), sd.saa,
-                  (unsigned)(cdl | (4 * rb + 2 * w.h + e))};
-      }
-      w.qn += __popcll(mw);  // at most 16 entries in all
+      sc_tab[(w.h * kSlots + s) * 32 + w.cl] = best;
+      gk_tab[(w.h * kSlots + s) * 32 + w.cl] = gk;
     }
+  if (w.h == 0) col_tab[w.cl] = sd;
   __builtin_amdgcn_wave_barrier();
-  if (w.qn > 0) drain(w.queue, w.cands, w.qn, w.qn, w.best, w.rstat, g);
+  if (w.lane < kWaveRanges) {
+    const int lr = w.lane, h = (lr >> 1) & 1, s = 2 * (lr >> 2) + (lr & 1);
+    const float4 *row = (const float4 *)(sc_tab + (h * kSlots + s) * 32);
+    float best = -1.0f;
+    int bc = -1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float4 v = row[q];
+      if (v.x > best) { best = v.x; bc = 4 * q; }
+      if (v.y > best) { best = v.y; bc = 4 * q + 1; }
+      if (v.z > best) { best = v.z; bc = 4 * q + 2; }
+      if (v.w > best) { best = v.w; bc = 4 * q + 3; }
+    }
+    if (bc >= 0) {
+      const unsigned gk = gk_tab[(h * kSlots + s) * 32 + bc];
+      const ColRec cr = col_tab[bc];
+      const double2 rs = w.rstat[lr];
+      const Fit f = fit_exact((double)(gk >> 3), (double)cr.sa, (double)cr.saa,
+                              rs.x, rs.y, g);
+      const unsigned long long key =
+          make_key(f.err, 8ll * cr.dom + (gk & 7), g);
+      if (key < w.best[lr]) w.best[lr] = key;
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
 }
 
 // grid: (chunks, R_pad / 64); block: 4 waves, each owning 16 ranges
