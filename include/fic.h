@@ -196,7 +196,8 @@ int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
  * candidate table of eq. (8) into row groups of ranges and column chunks of
  * domains; these entries choose how many chunks, how many leading 32-column
  * blocks a seed pass ranks first to give each range a starting bound (the
- * search still covers every block), and how many
+ * search still covers every block; the 8-bit, n = 8 matrix-core search seeds
+ * itself and always resolves this to 0), and how many
  * column blocks one work item of the batched search covers.  Any choice
  * yields the same codes; only speed changes.  An entry applies to encodes
  * with equal bit_depth, range_size and method and at least `min_domains`

@@ -120,6 +120,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   if (rs < 1) rs = 1;
   while (gcd_ll(rs, g.R_pad) != 1) ++rs;
   g.rng_stride = (int)rs;
+  g.pix_a = 0;
   return FIC_OK;
 }
 
@@ -225,6 +226,10 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
                 L.total);
   const EncBufs b = enc_bufs(L, workspace);
   hipStream_t s = (hipStream_t)stream;
+  // 8x8 ranges on the matrix cores take their range fragments straight from
+  // the (8-byte aligned) image
+  g.pix_a = p->method == FIC_METHOD_MFMA && g.bits == 8 && g.n == 8 &&
+            ((uintptr_t)image & 7) == 0;
   timing_mark(0, s);
   hipError_t e = launch_prep(g, image, b, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
@@ -240,7 +245,7 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   else if (g.bits == 12)
     e = launch_search_mfma12(g, b, t.chunks, 0, s);
   else
-    e = launch_search_mfma(g, b, t.chunks, 0, s);
+    e = launch_search_mfma(g, b, image, t.chunks, 0, s);
   if (e != hipSuccess) return hip_fail(e, "search");
   timing_mark(3, s);
   e = launch_finalize(g, image, b, out, s);

@@ -35,6 +35,9 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
   for (int s = 0; s < n; ++s) {
     const int st = make_geo_for_batch(&slices[s], pl.geo[s]);
     if (st) return st;
+    // 8x8 ranges build their range fragments from the image (confirmed per
+    // image, for alignment, in fic_batch_prepare)
+    pl.geo[s].pix_a = pl.geo[s].n == 8 ? 1 : 0;
     pl.tune[s] = resolve_tune(pl.geo[s], FIC_METHOD_MFMA);
     if (slices[s].bit_depth != slices[0].bit_depth ||
         slices[s].range_size != slices[0].range_size ||
@@ -154,6 +157,7 @@ int fic_batch_prepare(const fic_params *slices, int32_t n_slices,
         !out[s].o_idx || !out[s].err)
       return abi_fail(FIC_E_INVALID, "null image or code pointer in slice");
     tab[s].g = pl.geo[s];
+    tab[s].g.pix_a = pl.geo[s].pix_a && ((uintptr_t)images[s] & 7) == 0;
     tab[s].b = enc_workspace_bufs(pl.geo[s],
                                   (char *)workspace + pl.slice_off[s]);
     tab[s].image = images[s];

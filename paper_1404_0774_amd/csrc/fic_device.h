@@ -112,6 +112,9 @@ __device__ __forceinline__ float prune_weight(double best_err, double Sb,
 // Image range held by range slot i (a permutation of [0, R_pad); values
 // >= R mark padding slots).
 __device__ __forceinline__ int range_of_slot(const Geo &g, int i) {
+  // 32-bit arithmetic whenever i * stride < R_pad^2 fits in 32 bits
+  if (g.R_pad <= 65535)
+    return (int)(((unsigned)i * (unsigned)g.rng_stride) % (unsigned)g.R_pad);
   return (int)(((unsigned long long)i * (unsigned)g.rng_stride) %
                (unsigned)g.R_pad);
 }

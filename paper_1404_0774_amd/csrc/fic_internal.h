@@ -26,6 +26,8 @@ struct Geo {
   int dom_stride;    // sweep order: column c holds domain (c * dom_stride) % ND
   int rng_stride;    // range slots: slot i holds range (i * rng_stride) % R_pad
                      //   (slots of ranges >= R are padding)
+  int pix_a;         // 1: the 8-bit n = 8 matrix-core search builds its range
+                     //   fragments from the image; no range operand is written
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step
@@ -98,7 +100,8 @@ hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
                        hipStream_t st);
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st);
-hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
+hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
+                              const void *image, int chunks,
                               int first_block, hipStream_t st);
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
                                 int first_block, hipStream_t st);

@@ -17,10 +17,40 @@ __device__ __forceinline__ int cell_sum(const Pix *img, int W, int y, int x) {
   return (int)p[0] + (int)p[1] + (int)p[W] + (int)p[W + 1];
 }
 
-// Sum over aligned groups of `width` lanes (width a power of two <= 64).
-template <typename T>
-__device__ __forceinline__ T group_sum(T v, int width) {
-  for (int o = 1; o < width; o <<= 1) v += __shfl_xor(v, o, width);
+// The value of a partner lane inside the lane's row of 16 (DPP, no LDS
+// traffic): CTRL 0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x141 = mirror within 8,
+// 0x140 = mirror within 16.  Every lane of the row must be active.
+template <int CTRL, typename T>
+__device__ __forceinline__ T dpp_partner(T v) {
+  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(T) == 4) {
+    const int x = __builtin_bit_cast(int, v);
+    return __builtin_bit_cast(
+        T, __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF,
+                                               0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32),
+                                               CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(
+        T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+  }
+}
+
+// Sum over aligned groups of W lanes (W a power of two <= 64), the result in
+// every lane of the group.  Butterfly: after each step every lane holds the
+// sum of its aligned group of twice the size.  Every lane of a group must be
+// active (integer or exactly representable sums, so the order is free).
+template <int W, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  static_assert(W >= 1 && W <= 64 && (W & (W - 1)) == 0, "power of two");
+  if constexpr (W >= 2) v += dpp_partner<0xB1>(v);
+  if constexpr (W >= 4) v += dpp_partner<0x4E>(v);
+  if constexpr (W >= 8) v += dpp_partner<0x141>(v);
+  if constexpr (W >= 16) v += dpp_partner<0x140>(v);
+  if constexpr (W >= 32) v += __shfl_xor(v, 16);
+  if constexpr (W >= 64) v += __shfl_xor(v, 32);
   return v;
 }
 
@@ -50,7 +80,10 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
 #pragma unroll
   for (int j = 0; j < N; ++j) vh[j] = vl[j] = (_Float16)0.0f;
   if (live && col < g.ND) {
-    d = (int)((col * (long long)g.dom_stride) % g.ND);
+    // 32-bit arithmetic whenever col * stride < (ND + 32) * ND fits
+    d = g.ND <= 65000
+            ? (int)(((unsigned)col * (unsigned)g.dom_stride) % (unsigned)g.ND)
+            : (int)((col * (long long)g.dom_stride) % g.ND);
     const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
     const Pix *r0 = img + (size_t)(Y + 2 * i) * g.W + X;
     const Pix *r1 = r0 + g.W;
@@ -74,8 +107,8 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
       *(halfN *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + i * N) = vl;
   }
   // the column's statistics over its N adjacent threads
-  SA = group_sum(SA, N);
-  SAA = group_sum(SAA, N);
+  SA = group_sum<N>(SA);
+  SAA = group_sum<N>(SAA);
   if (live && i == 0) {
     b.col_dom[col] = d;
     b.col_saa[col] = (double)SAA;
@@ -126,7 +159,7 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
     A0 = cell_sum(img, g.W, 2 * i, 2 * j);  // domain 0 sits at (0, 0)
   }
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < 8 && !g.pix_a; ++k) {
     int si, sj;
     sigma(k, i, j, m, si, sj);
     const int p = si * N + sj;
@@ -137,11 +170,11 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
       row_hi[k * K + p] = (_Float16)(float)v;
     }
   }
-  const Acc Sb = group_sum((Acc)v, K);
-  const Acc Sbb = group_sum((Acc)v * v, K);
-  const Acc G0 = group_sum((Acc)A0 * v, K);
-  const Acc SA0 = group_sum((Acc)A0, K);
-  const Acc SAA0 = group_sum((Acc)A0 * A0, K);
+  const Acc Sb = group_sum<K>((Acc)v);
+  const Acc Sbb = group_sum<K>((Acc)v * v);
+  const Acc G0 = group_sum<K>((Acc)A0 * v);
+  const Acc SA0 = group_sum<K>((Acc)A0);
+  const Acc SAA0 = group_sum<K>((Acc)A0 * A0);
   if (q != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
@@ -212,11 +245,11 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
   sigma(k, i, j, m, si, sj);
   const double A = (double)cell_sum(img, g.W, Y + 2 * si, X + 2 * sj);
   // integer sums below 2^53: exact in double in any order
-  const double G = group_sum(A * v, K);
-  const double SA = group_sum(A, K);
-  const double SAA = group_sum(A * A, K);
-  const double Sb = group_sum(v, K);
-  const double Sbb = group_sum(v * v, K);
+  const double G = group_sum<K>(A * v);
+  const double SA = group_sum<K>(A);
+  const double SAA = group_sum<K>(A * A);
+  const double Sb = group_sum<K>(v);
+  const double Sbb = group_sum<K>(v * v);
   if (q != 0) return;
   const Fit f = fit_exact(G, SA, SAA, Sb, Sbb, g);
   out.domain[r] = d;

@@ -383,9 +383,74 @@ struct SearchLds {
   float wtab[4][2 * kSlots];
 };
 
+// Range operand fragments of 8x8 ranges built from the image (8-bit pixels)
+// instead of read from the range operand.  The wave stages its 16 ranges'
+// pixels in LDS (the empty queue), once row by row and once transposed, so
+// that every transform of a fragment row is one 8-byte read of a range row or
+// column, forward or reversed (sigma_k^-1 of the row, Section V).  Bytes
+// become FP16 exactly: 0x64xx is 1024 + xx, and 1024 is then subtracted.
+__device__ __forceinline__ void range_fragments_from_pixels(
+    const Geo &g, const uint8_t *img, WaveState &w, half8 (&af)[kRB][4]) {
+  uint2 *rows = (uint2 *)w.queue;  // [16 ranges][8 rows], 8 pixels each
+  uint2 *cols = rows + 16 * 8;     // [16 ranges][8 columns]
+  {
+    const int lr = w.lane >> 2, i0 = 2 * (w.lane & 3);
+    const int ri = range_of_slot(g, w.wr0 + lr);
+    uint2 r0 = uint2{0, 0}, r1 = uint2{0, 0};
+    if (ri < g.R) {
+      const uint8_t *p =
+          img + (size_t)((ri / g.RW) * 8 + i0) * g.W + (size_t)(ri % g.RW) * 8;
+      r0 = *(const uint2 *)p;
+      r1 = *(const uint2 *)(p + g.W);
+    }
+    rows[lr * 8 + i0] = r0;
+    rows[lr * 8 + i0 + 1] = r1;
+    // column j holds pixel (i, j) at byte i: this lane's bytes i0, i0 + 1
+    unsigned short *ct = (unsigned short *)(cols + lr * 8);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const unsigned b0 = ((j < 4 ? r0.x : r0.y) >> (8 * (j & 3))) & 255u;
+      const unsigned b1 = ((j < 4 ? r1.x : r1.y) >> (8 * (j & 3))) & 255u;
+      ct[j * 4 + (i0 >> 1)] = (unsigned short)(b0 | (b1 << 8));
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  // this lane's fragment row: range rl of each row block, transform k
+  const int rho = w.lane & 31;
+  const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
+  const int rl = 2 * hh + (gg >> 1), k = 4 * (gg & 1) + q;
+  // row pi of sigma_k^-1: transforms 1, 3, 5, 7 read range columns; 2, 3, 6,
+  // 7 read index 7 - pi; 1, 2, 4, 7 read the 8 pixels in reverse
+  const bool colw = k & 1;
+  const bool flip = k == 2 || k == 3 || k == 6 || k == 7;
+  const bool rev = k == 1 || k == 2 || k == 4 || k == 7;
+  const uint2 *tab = colw ? cols : rows;
+  const unsigned c64 = 0x64646464u;
+  const unsigned s0 = rev ? 0x04020403u : 0x04010400u;
+  const unsigned s1 = rev ? 0x04000401u : 0x04030402u;
+  const half8 k1024 = half8{1024, 1024, 1024, 1024, 1024, 1024, 1024, 1024};
+#pragma unroll
+  for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int pi = 2 * kk + w.h;
+      const uint2 v = tab[(4 * rb + rl) * 8 + (flip ? 7 - pi : pi)];
+      const unsigned lo = rev ? v.y : v.x, hi = rev ? v.x : v.y;
+      const uint4 u = uint4{__builtin_amdgcn_perm(c64, lo, s0),
+                            __builtin_amdgcn_perm(c64, lo, s1),
+                            __builtin_amdgcn_perm(c64, hi, s0),
+                            __builtin_amdgcn_perm(c64, hi, s1)};
+      af[rb][kk] = __builtin_bit_cast(half8, u) - k1024;
+    }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // The workgroup's 64 ranges (row group rg) against column blocks [c0, c1).
+// img: the 8-bit image when the range fragments come from pixels (K = 64),
+// else null (read the range operand).
 template <int K>
 __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
+                                            const uint8_t *img,
                                             SearchLds &lds, int rg, int c0,
                                             int c1) {
   constexpr int KS = K / 16;
@@ -416,7 +481,10 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     sdA = b.col_rec[col];
   }
   half8 af[kRB][KS];
-  {
+  if constexpr (K == 64) {
+    if (img) range_fragments_from_pixels(g, img, w, af);
+  }
+  if (K != 64 || !img) {
     const int rho = w.lane & 31;
     const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
     const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
@@ -457,6 +525,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
 // against column blocks [cb_begin + x * cb_per_chunk, ...).
 template <int K>
 __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
+                                                           const uint8_t *img,
                                                            int cb_begin,
                                                            int cb_end,
                                                            int cb_per_chunk) {
@@ -474,7 +543,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   }
   const int c0 = cb_begin + chunk * cb_per_chunk;
   const int c1 = min(c0 + cb_per_chunk, cb_end);
-  search_rows<K>(g, b, lds, rg, c0, c1);
+  search_rows<K>(g, b, img, lds, rg, c0, c1);
 }
 
 // Many slices: a persistent grid whose workgroups take search items
@@ -497,7 +566,9 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const int4 w = load_uniform(&bd.items[it]);
     const Geo g = load_uniform(&bd.tab[w.x].g);
     const EncBufs b = load_uniform(&bd.tab[w.x].b);
-    search_rows<K>(g, b, lds, w.y, w.z, w.w);
+    const uint8_t *img =
+        g.pix_a ? (const uint8_t *)load_uniform(&bd.tab[w.x].image) : nullptr;
+    search_rows<K>(g, b, img, lds, w.y, w.z, w.w);
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
@@ -519,8 +590,9 @@ hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
-                              int first_block, hipStream_t st) {
+hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
+                              const void *image, int chunks, int first_block,
+                              hipStream_t st) {
   static_assert(4 * kWaveRanges == kMfmaRangesPerWG, "tile");
   if (g.bits != 8) return hipErrorInvalidValue;
   const int rg = g.R_pad / kMfmaRangesPerWG;
@@ -531,7 +603,8 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b, int chunks,
   const int cbpc = (rest + chunks - 1) / chunks;
   const int nchunks = (rest + cbpc - 1) / cbpc;
   auto kern = g.K == 64 ? k_search_mfma_u8<64> : k_search_mfma_u8<16>;
-  hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b,
+  const uint8_t *img = g.pix_a ? (const uint8_t *)image : nullptr;
+  hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b, img,
                      first_block, g.NCB, cbpc);
   return hipGetLastError();
 }

@@ -246,6 +246,9 @@ Tune resolve_tune(const Geo &g, int method) {
     }
   }
   t.seed_blocks = std::max(0, std::min(t.seed_blocks, g.NCB));
+  // the 8-bit, n = 8 matrix-core search seeds itself and has no range
+  // operand for the seed pass to read
+  if (method == FIC_METHOD_MFMA && g.bits == 8 && g.n == 8) t.seed_blocks = 0;
   t.chunks = std::max(1, std::min(t.chunks, g.NCB));
   t.item_blocks = std::max(1, t.item_blocks);
   return t;

@@ -152,9 +152,12 @@ def clean_tuning():
 def test_tuning_defaults(clean_tuning):
     # 512x512, n = 8, STEP 4: 4096 ranges = 64 row groups, 15,625 domains in
     # 489 column blocks -> about two workgroups per CU (512 / 64 = 8 chunks)
+    # (the 8-bit, n = 8 matrix-core search seeds itself: no seed pass)
     t = F.get_tuning(F.Params(512, 512, 8, 8, 4))
     assert t == dict(bit_depth=8, range_size=8, method=0, min_domains=15625,
-                     col_chunks=8, seed_blocks=1, item_blocks=16)
+                     col_chunks=8, seed_blocks=0, item_blocks=16)
+    td = F.get_tuning(F.Params(512, 512, 8, 8, 4, method=F.METHOD_DIRECT))
+    assert td["seed_blocks"] == 1
     # 12-bit matrix-core search uses 16-range row groups: 256 groups -> 2 chunks
     t12 = F.get_tuning(F.Params(512, 512, 12, 8, 2))
     assert t12["col_chunks"] == 2 and t12["seed_blocks"] == 1
@@ -171,7 +174,16 @@ def test_tuning_table_selection(clean_tuning):
                   dict(bit_depth=8, range_size=8, method=0, min_domains=20000, col_chunks=3),
                   dict(bit_depth=8, range_size=8, method=1, min_domains=0, col_chunks=5)])
     t = F.get_tuning(p)
-    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (12, 2, 8)
+    # the self-seeding 8-bit, n = 8 matrix-core search ignores seed_blocks
+    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (12, 0, 8)
+    p12 = F.Params(512, 512, 12, 8, 4)
+    F.set_tuning([dict(bit_depth=12, range_size=8, method=0, min_domains=0, seed_blocks=3)])
+    assert F.get_tuning(p12)["seed_blocks"] == 3
+    F.set_tuning([dict(bit_depth=8, range_size=8, method=0, min_domains=0, col_chunks=4),
+                  dict(bit_depth=8, range_size=8, method=0, min_domains=10000, col_chunks=12,
+                       seed_blocks=2, item_blocks=8),
+                  dict(bit_depth=8, range_size=8, method=0, min_domains=20000, col_chunks=3),
+                  dict(bit_depth=8, range_size=8, method=1, min_domains=0, col_chunks=5)])
     p.method = F.METHOD_DIRECT
     t = F.get_tuning(p)
     assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (5, 1, 16)
@@ -207,8 +219,10 @@ def test_tuning_json(clean_tuning, tmp_path):
                     '  "col_chunks": 6, "seed_blocks": 2, "item_blocks": 32, "ms": 0.16,\n'
                     '  "sweep": [1, 2, {"x": null}], "ok": true}\n], "note": "a \\"quoted\\" word"}')
     F.load_tuning(str(good))
-    t = F.get_tuning(F.Params(512, 512, 8, 8, 4))
-    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (6, 2, 32)
+    t = F.get_tuning(F.Params(512, 512, 8, 8, 4, method=F.METHOD_MFMA))
+    assert (t["col_chunks"], t["seed_blocks"], t["item_blocks"]) == (6, 0, 32)
+    t4 = F.get_tuning(F.Params(512, 512, 8, 4, 4))   # n = 4: no entry, defaults
+    assert t4["seed_blocks"] == 1 and t4["item_blocks"] == 16
     for bad in ['{"entries": [{"bit_depth": 8, "range_size": 8, "method": 0,}]}',
                 '{"entries": [{"bit_depth": 8, "range_size": 8, "method": 0, "col_chunks": 1.5}]}',
                 '{"entries": [{"bit_depth": 9, "range_size": 8, "method": 0}]}',

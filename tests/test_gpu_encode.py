@@ -56,6 +56,27 @@ def test_parity_small_images(method, H, W, n, step, seed):
     assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), f"{H}x{W}")
 
 
+def test_unaligned_image_takes_range_operand_path():
+    """8x8 ranges normally build the range fragments from the image; an image
+    that is not 8-byte aligned goes through the range operand instead.  Both
+    give the oracle's codes."""
+    H, W, n, step = 96, 128, 8, 4
+    img = gen_image(H, W, 8, 17)
+    p = F.Params(H, W, 8, n, step)
+    buf = torch.zeros(H * W + 8, dtype=torch.uint8, device="cuda")
+    res = []
+    for off in (0, 3):
+        view = buf[off:off + H * W].view(H, W)
+        view.copy_(torch.from_numpy(img))
+        assert (view.data_ptr() % 8 == 0) == (off == 0)
+        out = F.encode(view, p)
+        torch.cuda.synchronize()
+        res.append({k: out[k].cpu().numpy() for k in KEYS})
+    ora = O.encode(img, n, step)
+    assert_same(res[0], ora, "aligned")
+    assert_same(res[1], ora, "unaligned")
+
+
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("kind", ["zeros", "const", "max", "checker", "noise", "levels"])
 def test_parity_degenerate_images(method, kind):
