@@ -102,6 +102,10 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.dlt = 2.0 * g.P / ldexp(1.0, g.ob);
   g.S = ldexp(1.0, g.sb - 1);
   g.escale = ldexp(1.0, 2 * g.sb + 2);
+  g.invK = 1.0 / g.K;
+  g.invS = 1.0 / g.S;
+  g.invDlt = 1.0 / g.dlt;
+  g.invEscale = 1.0 / g.escale;
   const int ebits = residual_bits(g);
   g.cbits = 64 - ebits;
   const long long ncand = 8ll * g.ND;

@@ -61,9 +61,10 @@ __device__ __forceinline__ Fit fit_exact(double G, double SA, double SAA,
   const double s = (Dp == 0.0) ? 0.0 : (4.0 * Np) / Dp;  // eq. (11) / (9)
   double j = floor((s + 1.0) * g.S + 0.5);
   j = fmin(fmax(j, 0.0), 2.0 * g.S - 1.0);
-  const double sq = j / g.S - 1.0;
-  const double o = (Sb - sq * SA * 0.25) / K;             // eq. (10) / (12)
-  double m = floor((o + g.P) / g.dlt + 0.5);
+  // K, S and dlt are powers of two: scaling by the reciprocal is exact
+  const double sq = j * g.invS - 1.0;
+  const double o = (Sb - sq * SA * 0.25) * g.invK;        // eq. (10) / (12)
+  double m = floor((o + g.P) * g.invDlt + 0.5);
   m = fmin(fmax(m, 0.0), ldexp(1.0, g.ob) - 1.0);
   const double oq = m * g.dlt - g.P;
   // eq. (8) expanded over the sums: sum (sq a + oq - b)^2 with a = A/4
@@ -88,7 +89,7 @@ __device__ __forceinline__ unsigned long long make_key(double err, long long c,
 
 __device__ __forceinline__ double key_err(unsigned long long key,
                                           const Geo &g) {
-  return (double)(key >> g.cbits) / g.escale;
+  return (double)(key >> g.cbits) * g.invEscale;
 }
 
 // Prune weight of a range from its best residual so far.  A candidate can

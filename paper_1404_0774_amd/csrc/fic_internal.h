@@ -32,6 +32,9 @@ struct Geo {
   double P;          // 2^bits
   double dlt;        // offset step
   double S;          // 2^(sb - 1)
+  // exact reciprocals of the powers of two above (K, S, dlt, escale): a
+  // product by them equals the quotient bit for bit, at a fraction of the cost
+  double invK, invS, invDlt, invEscale;
 };
 
 // Device buffers carved out of the caller's workspace.

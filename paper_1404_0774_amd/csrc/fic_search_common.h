@@ -18,8 +18,8 @@ __device__ __forceinline__ unsigned long long load_best(
 __device__ __forceinline__ float weight_from_key(unsigned long long key,
                                                  double V, const Geo &g) {
   const double K = (double)g.K;
-  const double Wd = fma(-K / g.escale, (double)(key >> g.cbits), V);
-  const float w = (float)(fmax(Wd, 0.0) * (1.0 / (K * K))) * (1.0f - 0x1p-20f);
+  const double Wd = fma(-K * g.invEscale, (double)(key >> g.cbits), V);
+  const float w = (float)(fmax(Wd, 0.0) * (g.invK * g.invK)) * (1.0f - 0x1p-20f);
   return V == 0.0 ? __builtin_inff() : w;
 }
 

@@ -112,7 +112,7 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
         const float sa = q.sa, dp = q.dp;
         const int lr = q.dl & 15;
         const double2 rs = rstat[lr];
-        const float bbar = (float)(rs.x / K);
+        const float bbar = (float)(rs.x * g.invK);
         const float t = weight_from_key(best[lr], K * rs.y - rs.x * rs.x, g) * dp;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {

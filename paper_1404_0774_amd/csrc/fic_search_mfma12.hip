@@ -41,8 +41,8 @@ struct __attribute__((aligned(16))) QEntry12 {
 // Exact-safe test of one candidate in FP64: G - SA Sb/K is exact in double,
 // t = W' D' is rounded down.
 __device__ __forceinline__ bool passes_exact(double G, double sa, double Sb,
-                                             double K, float t) {
-  const double a = G - sa * Sb / K;
+                                             double invK, float t) {
+  const double a = G - sa * Sb * invK;  // K is a power of two
   return a * a >= (double)t;
 }
 
@@ -68,7 +68,7 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
             weight_from_key(best[q.lr], K * rs.y - rs.x * rs.x, g) * q.dp;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
-          pass |= passes_exact(gv[k], (double)q.sa, rs.x, K, t) ? (1u << k) : 0u;
+          pass |= passes_exact(gv[k], (double)q.sa, rs.x, g.invK, t) ? (1u << k) : 0u;
       }
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
 #pragma unroll
   for (int e = 0; e < 2; ++e) {
     const double2 rs = rstat[2 * h + e];
-    bbar[e] = (float)(rs.x / Kd);
+    bbar[e] = (float)(rs.x * g.invK);
     wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
   }
 
