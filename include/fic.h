@@ -110,6 +110,19 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * fic_search_counts -- host, synchronous.  After an fic_encode of `p` with
+ * the matrix-core method on an 8-bit image has completed on `workspace`,
+ * reports how many ranges and how many domains the search visited: those
+ * with variance.  A flat range (all pixels equal) ties on every candidate
+ * and keeps candidate 0; a flat domain ties with the first flat domain,
+ * which code extraction compares (Section V: shadow blocks need no search).
+ * Errors: FIC_E_INVALID (null pointers, workspace smaller than fic_query
+ * reports), FIC_E_UNSUPPORTED (another method or bit depth), FIC_E_HIP.
+ */
+int fic_search_counts(const fic_params *p, const void *workspace,
+                      size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains);
+
+/*
  * Batched encode of many slices of uneven size (each slice an independent
  * fic_encode problem; the paper encodes one image per kernel launch).
  * All slices must share bit_depth (8), range_size, s_bits and o_bits; size

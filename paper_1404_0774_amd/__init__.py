@@ -7,9 +7,9 @@ ABI.  PyTorch provides device memory and streams.
 from ._lib import (FicError, Params, encode, decode, decode_backward, query,
                    dequantize, FicDecode, lib, METHOD_MFMA, METHOD_DIRECT,
                    timing_begin, timing_end, refine, Batch, Tuning, set_tuning,
-                   load_tuning, get_tuning)
+                   load_tuning, get_tuning, search_counts)
 
 __all__ = ["FicError", "Params", "encode", "decode", "decode_backward", "query",
            "dequantize", "FicDecode", "lib", "METHOD_MFMA", "METHOD_DIRECT",
            "timing_begin", "timing_end", "refine", "Batch", "Tuning", "set_tuning",
-           "load_tuning", "get_tuning"]
+           "load_tuning", "get_tuning", "search_counts"]

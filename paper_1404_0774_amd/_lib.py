@@ -83,6 +83,9 @@ def lib():
         L.fic_query.restype = ctypes.c_int
         L.fic_query.argtypes = [P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                 ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.fic_search_counts.restype = ctypes.c_int
+        L.fic_search_counts.argtypes = [P, vp, sz, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64)]
         L.fic_encode.restype = ctypes.c_int
         L.fic_encode.argtypes = [P, vp, _Codes, vp, sz, vp]
         L.fic_decode.restype = ctypes.c_int
@@ -210,7 +213,19 @@ def encode(image: torch.Tensor, p: Params, workspace=None):
     _check(lib().fic_encode(ctypes.byref(cp), ctypes.c_void_p(img_ptr), codes,
                             ctypes.c_void_p(ws), ctypes.c_size_t(ew), _stream(dev)))
     out["_ws"] = keep
+    out["_ws_ptr"] = (ws, ew)
     return out
+
+
+def search_counts(out, p: Params):
+    """(ranges, domains) the search visited in the encode that produced
+    `out` (8-bit, matrix-core method); synchronises the device."""
+    ws, ew = out["_ws_ptr"]
+    nr, nd = ctypes.c_int64(), ctypes.c_int64()
+    cp = p.c()
+    _check(lib().fic_search_counts(ctypes.byref(cp), ctypes.c_void_p(ws), ctypes.c_size_t(ew),
+                                   ctypes.byref(nr), ctypes.byref(nd)))
+    return nr.value, nd.value
 
 
 class Batch:

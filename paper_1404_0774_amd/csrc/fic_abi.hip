@@ -142,6 +142,11 @@ EncLayout enc_layout(const Geo &g) {
   L.off_rng_sbb = o;  o = align256(o + (size_t)g.R_pad * 8);
   L.off_best = o;     o = align256(o + (size_t)g.R_pad * 8);
   L.off_flat = o;     o = align256(o + (size_t)g.n_dwg * 4);
+  L.off_act_slot = o; o = align256(o + (size_t)g.R_pad * 4);
+  L.off_act_col = o;  o = align256(o + (size_t)g.NC_pad * 4);
+  L.off_n_act = o;    o = align256(o + 2 * 4);
+  L.off_rng_flag = o; o = align256(o + (size_t)g.R_pad);
+  L.off_col_flag = o; o = align256(o + (size_t)g.NC_pad);
   L.total = o;
   return L;
 }
@@ -159,6 +164,11 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   b.rng_sbb = (double *)(w + L.off_rng_sbb);
   b.best = (unsigned long long *)(w + L.off_best);
   b.flat_min = (int32_t *)(w + L.off_flat);
+  b.act_slot = (int32_t *)(w + L.off_act_slot);
+  b.act_col = (int32_t *)(w + L.off_act_col);
+  b.n_act = (int32_t *)(w + L.off_n_act);
+  b.rng_flag = (uint8_t *)(w + L.off_rng_flag);
+  b.col_flag = (uint8_t *)(w + L.off_col_flag);
   return b;
 }
 
@@ -241,6 +251,12 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   // the seed pass ranks the leading column blocks to give every range a
   // starting bound; the search still covers every column block
   const Tune t = resolve_tune(g, p->method);
+  if (p->method == FIC_METHOD_MFMA && g.bits == 8) {
+    // the 8-bit matrix-core search visits only ranges and domains with
+    // variance (lists built here, in order)
+    e = launch_compact(g, b, s);
+    if (e != hipSuccess) return hip_fail(e, "compact");
+  }
   e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
   timing_mark(2, s);
@@ -249,13 +265,36 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   else if (g.bits == 12)
     e = launch_search_mfma12(g, b, t.chunks, 0, s);
   else
-    e = launch_search_mfma(g, b, image, t.chunks, 0, s);
+    e = launch_search_mfma(g, b, image, t.chunks * (g.R_pad / kMfmaRangesPerWG),
+                           s);
   if (e != hipSuccess) return hip_fail(e, "search");
   timing_mark(3, s);
   e = launch_finalize(g, image, b, out, s);
   if (e != hipSuccess) return hip_fail(e, "finalize");
   timing_mark(4, s);
   if (g_timing.on) ++g_timing.calls;
+  return ok();
+}
+
+int fic_search_counts(const fic_params *p, const void *workspace,
+                      size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/true);
+  if (st) return st;
+  if (!workspace || !n_ranges || !n_domains)
+    return fail(FIC_E_INVALID, "null workspace or output pointer");
+  if (p->method != FIC_METHOD_MFMA || g.bits != 8)
+    return fail(FIC_E_UNSUPPORTED,
+                "search counts exist for the 8-bit matrix-core method only");
+  const EncLayout L = enc_layout(g);
+  if (ws_bytes < L.total)
+    return fail(FIC_E_INVALID, "workspace %zu bytes < %zu", ws_bytes, L.total);
+  int32_t n[2];
+  const hipError_t e = hipMemcpy(n, (const char *)workspace + L.off_n_act,
+                                 sizeof n, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+  *n_ranges = n[0];
+  *n_domains = n[1];
   return ok();
 }
 

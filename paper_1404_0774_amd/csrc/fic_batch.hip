@@ -199,6 +199,7 @@ int fic_encode_batch(const fic_params *slices, int32_t n_slices,
   if (ticks) bd.ticks = (unsigned long long *)ticks;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = launch_prep_batch(bd, s);
+  if (e == hipSuccess) e = launch_compact_batch(bd, s);
   int max_seed = 0;
   for (const Tune &t : pl.tune) max_seed = std::max(max_seed, t.seed_blocks);
   if (e == hipSuccess) e = launch_seed_batch(bd, max_seed, s);

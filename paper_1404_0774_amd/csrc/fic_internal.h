@@ -65,12 +65,22 @@ struct EncBufs {
   unsigned long long *best; // [R_pad] packed (residual, candidate) keys
   int32_t *flat_min;  // [domain-prep workgroups] smallest flat domain index
                       //   seen by each workgroup (INT_MAX if none)
+  // The candidates the search has to visit: range slots holding a range with
+  // variance and domain columns holding a domain with variance, each in
+  // order (flat ranges keep candidate 0, flat domains tie with the first
+  // one; code extraction handles both).
+  int32_t *act_slot;  // [R_pad] searched range slots, first n_act[0] valid
+  int32_t *act_col;   // [NC_pad] searched domain columns, first n_act[1]
+  int32_t *n_act;     // [2] counts of the two lists
+  uint8_t *rng_flag;  // [R_pad] 1: slot holds a range with variance
+  uint8_t *col_flag;  // [NC_pad] 1: column holds a domain with variance
 };
 
 // Byte layout of the encode workspace.
 struct EncLayout {
   size_t off_bop, off_aop, off_col_dom, off_col_sadp, off_col_saa, off_col_rec;
-  size_t off_rng_sb, off_rng_sbb, off_best, off_flat;
+  size_t off_rng_sb, off_rng_sbb, off_best, off_flat, off_act_slot,
+      off_act_col, off_n_act, off_rng_flag, off_col_flag;
   size_t total;
 };
 
@@ -104,8 +114,8 @@ hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st);
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
-                              const void *image, int chunks,
-                              int first_block, hipStream_t st);
+                              const void *image, int workgroups,
+                              hipStream_t st);
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
                                 int first_block, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
@@ -122,6 +132,8 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                                   float *grad_o, void *ws, hipStream_t st);
 size_t decode_backward_ws_bytes(const Geo &g);
 hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st);
+hipError_t launch_compact(const Geo &g, const EncBufs &b, hipStream_t st);
+hipError_t launch_compact_batch(const BatchDev &bd, hipStream_t st);
 hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st);
 hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st);
 hipError_t launch_finalize_batch(const BatchDev &bd, hipStream_t st);

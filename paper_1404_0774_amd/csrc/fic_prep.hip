@@ -127,6 +127,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     rec.dom = d;
     rec.saa = g.bits == 8 ? (unsigned)SAA : 0u;
     b.col_rec[col] = rec;
+    b.col_flag[col] = dp != __builtin_inff() ? 1 : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
@@ -178,6 +179,8 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
   if (q != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
+  // searched iff a real range with variance (K Sbb - Sb^2 != 0, exact)
+  b.rng_flag[r] = ri < g.R && (Acc)K * Sbb - Sb * Sb != 0 ? 1 : 0;
   if (ri >= g.R) {
     b.best[r] = ~0ull;
     return;
@@ -277,6 +280,59 @@ hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
   return hipGetLastError();
 }
 
+// Ordered compaction of the indices i < n whose flag byte is 1, by one
+// workgroup of 1024 threads (n a multiple of 16).  Thread t owns the
+// contiguous 16-byte words [t P, (t + 1) P) of the flags and counts them
+// with one popcount per word; the counts are scanned in LDS and each thread
+// writes its selected indices in order.
+__device__ __forceinline__ void block_compact(int n, const uint8_t *flag,
+                                              int32_t *out, int32_t *count) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int words = n / 16;
+  const int per = (words + 1023) / 1024;
+  const int w0 = min(t * per, words), w1 = min(w0 + per, words);
+  const uint4 *fw = (const uint4 *)flag;
+  int c = 0;
+  for (int i = w0; i < w1; ++i) {
+    const uint4 v = fw[i];  // 16 flags of 0 or 1
+    c += __builtin_popcount(v.x) + __builtin_popcount(v.y) +
+         __builtin_popcount(v.z) + __builtin_popcount(v.w);
+  }
+  part[t] = c;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int pos = part[t] - c;
+  for (int i = w0; i < w1; ++i) {
+    const uint4 v = fw[i];
+    const unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if ((u[q] >> (8 * e)) & 1u) out[pos++] = 16 * i + 4 * q + e;
+  }
+  if (t == 1023) *count = part[1023];
+  __syncthreads();  // part is reused by the next call
+}
+
+// The search's work lists: range slots holding a range with variance and
+// domain columns holding a domain with variance (flags written by the
+// preparation), both in slot / sweep order.
+__device__ __forceinline__ void compact_body(const Geo &g, const EncBufs &b) {
+  block_compact(g.R_pad, b.rng_flag, b.act_slot, &b.n_act[0]);
+  block_compact(g.NC_pad, b.col_flag, b.act_col, &b.n_act[1]);
+}
+
+__global__ __launch_bounds__(1024) void k_compact(Geo g, EncBufs b) {
+  compact_body(g, b);
+}
+
 // Slice of workgroup `bid` in a phase with offsets off[0..n] (off[n] is the
 // total): the s with off[s] <= bid < off[s + 1].
 __device__ __forceinline__ int slice_of(const int *off, int n, int bid) {
@@ -332,7 +388,24 @@ __global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
                         blockIdx.x - off[s]);
 }
 
+// One workgroup per slice.
+__global__ __launch_bounds__(1024) void k_compact_batch(BatchDev bd) {
+  const Geo g = load_uniform(&bd.tab[blockIdx.x].g);
+  const EncBufs b = load_uniform(&bd.tab[blockIdx.x].b);
+  compact_body(g, b);
+}
+
 }  // namespace
+
+hipError_t launch_compact(const Geo &g, const EncBufs &b, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, st, g, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_batch(const BatchDev &bd, hipStream_t st) {
+  hipLaunchKernelGGL(k_compact_batch, dim3(bd.n), dim3(1024), 0, st, bd);
+  return hipGetLastError();
+}
 
 hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st) {
   hipLaunchKernelGGL(k_batch_init, dim3((bd.n + 255) / 256), dim3(256), 0, st,

@@ -170,10 +170,33 @@ struct WaveState {
   QEntry *queue;             // LDS: queued pairs
   Cand *cands;               // LDS: drain candidates
   float *wtab;               // LDS: prune weights [2][kSlots]
+  int *slots;                // LDS: range slot of each wave range (-1: none)
+  int ci_next;               // column of the next block (-1: none)
+  int nD;                    // searched domain columns
   int qn;                    // queued pairs (wave-uniform)
   unsigned long long gsnap;  // global keys as last seen (lanes < 16)
   int wr0, h, cl, lane;
 };
+
+// Column ci of the domain operand and its record; ci < 0 (past the searched
+// columns) reads column 0 and marks it flat, so it never passes the prune.
+template <int K>
+__device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
+                                            half8 (&bn)[K / 16], ColRec &nsd) {
+  const int c = ci >= 0 ? ci : 0;
+  const _Float16 *bsrc = b.bop + (size_t)c * K + 8 * h;
+#pragma unroll
+  for (int kk = 0; kk < K / 16; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
+  nsd = b.col_rec[c];
+  if (ci < 0) nsd.dp = __builtin_inff();
+}
+
+// Column of searched block cb for lane column cl (-1 past the list).
+__device__ __forceinline__ int column_of(const EncBufs &b, int nD, int cb,
+                                         int cl) {
+  const int j = cb * 32 + cl;
+  return j < nD ? b.act_col[j] : -1;
+}
 
 // One 32-column block: prefetch the next block's operand and column records
 // into (bn, nsd), run the MFMA
@@ -186,13 +209,11 @@ __device__ __forceinline__ void sweep_block(
     int c1) {
   constexpr int KS = K / 16;
   const int slot = (cb - c0) % kSync;
-  const int col = cb * 32 + w.cl;
   {
-    const int ncol = (cb + 1 < c1 ? cb + 1 : cb) * 32 + w.cl;
-    const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * w.h;
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
-    nsd = b.col_rec[ncol];
+    // the next block (its column index came a block earlier) and the index
+    // of the block after it
+    load_column<K>(b, w.ci_next, w.h, bn, nsd);
+    w.ci_next = cb + 2 < c1 ? column_of(b, w.nD, cb + 2, w.cl) : -1;
   }
   // keep the prefetch ahead of the matrix-core work
   __builtin_amdgcn_sched_barrier(0);
@@ -277,10 +298,13 @@ __device__ __forceinline__ void sweep_block(
     if (cb + 1 == c1 && w.qn > 0)
       drain(w.queue, w.cands, w.qn, w.qn, w.best, w.rstat, g);
     if (w.lane < kWaveRanges) {
+      const int sl = w.slots[w.lane];
       const unsigned long long m = min(w.best[w.lane], w.gsnap);
       w.best[w.lane] = m;
-      if (m < w.gsnap) atomicMin(&b.best[w.wr0 + w.lane], m);
-      w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
+      if (sl >= 0) {
+        if (m < w.gsnap) atomicMin(&b.best[sl], m);
+        w.gsnap = load_best(&b.best[sl]);
+      }
     }
     refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   }
@@ -381,6 +405,7 @@ struct SearchLds {
   QEntry queue[4][kQueue];
   Cand cands[4][8 * 64];
   float wtab[4][2 * kSlots];
+  int slots[4][kWaveRanges];
 };
 
 // Range operand fragments of 8x8 ranges built from the image (8-bit pixels)
@@ -395,7 +420,8 @@ __device__ __forceinline__ void range_fragments_from_pixels(
   uint2 *cols = rows + 16 * 8;     // [16 ranges][8 columns]
   {
     const int lr = w.lane >> 2, i0 = 2 * (w.lane & 3);
-    const int ri = range_of_slot(g, w.wr0 + lr);
+    const int sl = w.slots[lr];
+    const int ri = sl >= 0 ? range_of_slot(g, sl) : g.R;
     uint2 r0 = uint2{0, 0}, r1 = uint2{0, 0};
     if (ri < g.R) {
       const uint8_t *p =
@@ -445,41 +471,54 @@ __device__ __forceinline__ void range_fragments_from_pixels(
   __builtin_amdgcn_wave_barrier();
 }
 
-// The workgroup's 64 ranges (row group rg) against column blocks [c0, c1).
-// img: the 8-bit image when the range fragments come from pixels (K = 64),
-// else null (read the range operand).
+// The workgroup's 64 searched ranges (entries row0 .. row0 + 63 of the range
+// list) against searched column blocks [c0, c1).  nA, nD: lengths of the two
+// lists.  img: the 8-bit image when the range fragments come from pixels
+// (K = 64), else null (read the range operand).
 template <int K>
 __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
                                             const uint8_t *img,
-                                            SearchLds &lds, int rg, int c0,
-                                            int c1) {
+                                            SearchLds &lds, int row0, int nA,
+                                            int nD, int c0, int c1) {
   constexpr int KS = K / 16;
   WaveState w;
   w.lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   w.h = w.lane >> 5;
   w.cl = w.lane & 31;
-  w.wr0 = rg * (4 * kWaveRanges) + wave * kWaveRanges;
+  w.wr0 = row0 + wave * kWaveRanges;
   w.best = lds.best[wave];
   w.rstat = lds.rstat[wave];
   w.queue = lds.queue[wave];
   w.cands = lds.cands[wave];
   w.wtab = lds.wtab[wave];
+  w.slots = lds.slots[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
+  w.nD = nD;
   if (c0 >= c1) return;
 
-  // every independent global load first: the first domain block, the range
-  // operand fragments, the range sums and the current keys
+  // the wave's range slots, their keys and sums; the first two columns
+  if (w.lane < kWaveRanges) {
+    const int j = w.wr0 + w.lane;
+    const int sl = j < nA ? b.act_slot[j] : -1;
+    w.slots[w.lane] = sl;
+    double sb = 0.0, sbb = 0.0;
+    if (sl >= 0) {
+      w.gsnap = load_best(&b.best[sl]);
+      sb = b.rng_sb[sl];
+      sbb = b.rng_sbb[sl];
+    }
+    w.best[w.lane] = w.gsnap;
+    w.rstat[w.lane] = double2{sb, sbb};
+  }
+  const int ci0 = column_of(b, nD, c0, w.cl);
+  w.ci_next = c0 + 1 < c1 ? column_of(b, nD, c0 + 1, w.cl) : -1;
   half8 bA[KS], bB[KS];  // two buffers for the streamed domain operand
   ColRec sdA, sdB;
-  {
-    const int col = c0 * 32 + w.cl;
-    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * w.h;
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bA[kk] = *(const half8 *)(bsrc + 16 * kk);
-    sdA = b.col_rec[col];
-  }
+  load_column<K>(b, ci0, w.h, bA, sdA);
+  __builtin_amdgcn_wave_barrier();
+
   half8 af[kRB][KS];
   if constexpr (K == 64) {
     if (img) range_fragments_from_pixels(g, img, w, af);
@@ -490,26 +529,19 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb) {
+      const int sl = w.slots[4 * rb + rl];
       const _Float16 *src =
-          b.aop + ((size_t)(w.wr0 + 4 * rb + rl) * 8 + iso) * K + 8 * w.h;
+          b.aop + ((size_t)(sl >= 0 ? sl : 0) * 8 + iso) * K + 8 * w.h;
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk)
-        af[rb][kk] = *(const half8 *)(src + 16 * kk);
+        af[rb][kk] = sl >= 0 ? *(const half8 *)(src + 16 * kk) : half8{};
     }
   }
-  // per lane: ranges wr0 + 4 rb + 2 h + e for slot s = 2 rb + e
+  // per lane: wave ranges 4 rb + 2 h + e for slot s = 2 rb + e
   float wp[kSlots], bbar[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s)
-    bbar[s] = (float)(b.rng_sb[w.wr0 + 4 * (s >> 1) + 2 * w.h + (s & 1)] *
-                      (1.0 / K));
-  if (w.lane < kWaveRanges) {
-    w.gsnap = load_best(&b.best[w.wr0 + w.lane]);
-    w.best[w.lane] = w.gsnap;
-    w.rstat[w.lane] =
-        double2{b.rng_sb[w.wr0 + w.lane], b.rng_sbb[w.wr0 + w.lane]};
-  }
-  __builtin_amdgcn_wave_barrier();
+    bbar[s] = (float)(w.rstat[4 * (s >> 1) + 2 * w.h + (s & 1)].x * g.invK);
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
 
   seed_first_block<K>(g, w, af, bbar, bA, sdA);
@@ -521,29 +553,24 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   }
 }
 
-// One image: grid (chunks, R_pad / 64); workgroup (x, y) sweeps row group y
-// against column blocks [cb_begin + x * cb_per_chunk, ...).
+// One image: a grid of G workgroups over the searched ranges and columns.
+// The lists' lengths are read on the device; the rows of 64 ranges are each
+// split into G / rows chunks of column blocks (at least one).
 template <int K>
 __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
-                                                           const uint8_t *img,
-                                                           int cb_begin,
-                                                           int cb_end,
-                                                           int cb_per_chunk) {
+                                                           const uint8_t *img) {
   __shared__ SearchLds lds;
-  // Workgroups are dispatched to the 8 XCDs round-robin by linear id.  When
-  // the row groups split evenly over the XCDs, place all chunks of a row
-  // group on one XCD, so that its range operand is fetched into one L2
-  // (the streamed domain columns are the cheaper operand to replicate).
-  int chunk = blockIdx.x, rg = blockIdx.y;
-  if ((gridDim.y & 7) == 0) {
-    const int i = blockIdx.y * gridDim.x + blockIdx.x;
-    const int xcd = i & 7, j = i >> 3;
-    chunk = j % gridDim.x;
-    rg = xcd + 8 * (j / gridDim.x);
-  }
-  const int c0 = cb_begin + chunk * cb_per_chunk;
-  const int c1 = min(c0 + cb_per_chunk, cb_end);
-  search_rows<K>(g, b, img, lds, rg, c0, c1);
+  const int nA = __builtin_amdgcn_readfirstlane(b.n_act[0]);
+  const int nD = __builtin_amdgcn_readfirstlane(b.n_act[1]);
+  const int rows = (nA + kMfmaRangesPerWG - 1) / kMfmaRangesPerWG;
+  const int ncb = (nD + 31) / 32;
+  if (rows == 0 || ncb == 0) return;
+  const int chunks = max(1, min((int)gridDim.x / rows, ncb));
+  const int rg = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+  if (rg >= rows) return;
+  const int cbpc = (ncb + chunks - 1) / chunks;
+  const int c0 = chunk * cbpc, c1 = min(c0 + cbpc, ncb);
+  search_rows<K>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0, c1);
 }
 
 // Many slices: a persistent grid whose workgroups take search items
@@ -568,7 +595,13 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const EncBufs b = load_uniform(&bd.tab[w.x].b);
     const uint8_t *img =
         g.pix_a ? (const uint8_t *)load_uniform(&bd.tab[w.x].image) : nullptr;
-    search_rows<K>(g, b, img, lds, w.y, w.z, w.w);
+    // the item's row and blocks within the slice's searched lists
+    const int nA = __builtin_amdgcn_readfirstlane(b.n_act[0]);
+    const int nD = __builtin_amdgcn_readfirstlane(b.n_act[1]);
+    const int row0 = w.y * kMfmaRangesPerWG;
+    const int c1 = min(w.w, (nD + 31) / 32);
+    if (row0 < nA && w.z < c1)
+      search_rows<K>(g, b, img, lds, row0, nA, nD, w.z, c1);
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
@@ -591,21 +624,14 @@ hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st) {
 }
 
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
-                              const void *image, int chunks, int first_block,
+                              const void *image, int workgroups,
                               hipStream_t st) {
   static_assert(4 * kWaveRanges == kMfmaRangesPerWG, "tile");
   if (g.bits != 8) return hipErrorInvalidValue;
-  const int rg = g.R_pad / kMfmaRangesPerWG;
-  const int rest = g.NCB - first_block;
-  if (rest <= 0) return hipSuccess;
-  if (chunks > rest) chunks = rest;
-  if (chunks < 1) chunks = 1;
-  const int cbpc = (rest + chunks - 1) / chunks;
-  const int nchunks = (rest + cbpc - 1) / cbpc;
-  auto kern = g.K == 64 ? k_search_mfma_u8<64> : k_search_mfma_u8<16>;
+  if (workgroups < 1) workgroups = 1;
   const uint8_t *img = g.pix_a ? (const uint8_t *)image : nullptr;
-  hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b, img,
-                     first_block, g.NCB, cbpc);
+  auto kern = g.K == 64 ? k_search_mfma_u8<64> : k_search_mfma_u8<16>;
+  hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b, img);
   return hipGetLastError();
 }
 

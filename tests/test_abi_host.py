@@ -234,3 +234,19 @@ def test_tuning_json(clean_tuning, tmp_path):
         assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 6
     with pytest.raises(F.FicError):
         F.load_tuning(str(tmp_path / "missing.json"))
+
+
+def test_search_counts_validation():
+    L = F.lib()
+    p = F.Params(64, 64, 8, 8, 4).c()
+    nr, nd = ctypes.c_int64(), ctypes.c_int64()
+    fake = ctypes.c_void_p(1 << 20)
+    ws = F.query(F.Params(64, 64, 8, 8, 4))[2]
+    assert L.fic_search_counts(ctypes.byref(p), None, ws, ctypes.byref(nr), ctypes.byref(nd)) == 1
+    assert L.fic_search_counts(ctypes.byref(p), fake, ws, None, ctypes.byref(nd)) == 1
+    assert L.fic_search_counts(ctypes.byref(p), fake, 16, ctypes.byref(nr), ctypes.byref(nd)) == 1
+    pd = F.Params(64, 64, 8, 8, 4, method=F.METHOD_DIRECT).c()
+    assert L.fic_search_counts(ctypes.byref(pd), fake, ws, ctypes.byref(nr), ctypes.byref(nd)) == 2
+    p12 = F.Params(64, 64, 12, 8, 4).c()
+    ws12 = F.query(F.Params(64, 64, 12, 8, 4))[2]
+    assert L.fic_search_counts(ctypes.byref(p12), fake, ws12, ctypes.byref(nr), ctypes.byref(nd)) == 2

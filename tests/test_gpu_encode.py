@@ -56,6 +56,26 @@ def test_parity_small_images(method, H, W, n, step, seed):
     assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), f"{H}x{W}")
 
 
+def test_search_visits_exactly_the_ranges_and_domains_with_variance():
+    """The 8-bit matrix-core search skips flat ranges and flat domains (their
+    outcome is fixed); the counts it reports match a direct count."""
+    H, W, n, step = 128, 96, 8, 4
+    img = gen_image(H, W, 8, 19)
+    p = F.Params(H, W, 8, n, step)
+    out = F.encode(torch.from_numpy(img).cuda(), p)
+    nr, nd = F.search_counts(out, p)
+    blocks = img.reshape(H // n, n, W // n, n).transpose(0, 2, 1, 3).reshape(-1, n * n)
+    want_r = int((blocks.max(1) != blocks.min(1)).sum())
+    ny, nx = (H - 2 * n) // step + 1, (W - 2 * n) // step + 1
+    cells = [img[y * step:y * step + 2 * n, x * step:x * step + 2 * n]
+             .reshape(n, 2, n, 2).astype(np.int64).sum(axis=(1, 3))
+             for y in range(ny) for x in range(nx)]
+    want_d = sum(int(c.max() != c.min()) for c in cells)
+    assert (nr, nd) == (want_r, want_d)
+    assert 0 < nr < len(blocks) and 0 < nd < ny * nx   # the image has background
+    assert_same({k: out[k].cpu().numpy() for k in KEYS}, O.encode(img, n, step), "counts image")
+
+
 def test_unaligned_image_takes_range_operand_path():
     """8x8 ranges normally build the range fragments from the image; an image
     that is not 8-byte aligned goes through the range operand instead.  Both
