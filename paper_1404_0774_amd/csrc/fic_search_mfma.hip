@@ -310,79 +310,103 @@ __device__ __forceinline__ void sweep_block(
   }
 }
 
-// Starting bound from the workgroup's first column block.  Each lane ranks
-// the 8 transforms of each of its ranges against its column by the
-// least-squares score (G - SA Sb/K)^2 / D' and posts the best through LDS
-// (the empty candidate buffer); lane l < 16 then picks range l's best column
-// and fits that one candidate exactly.  Any candidate's exact residual is a
-// valid bound; the sweep then covers the block as usual.
+// Starting bound from the workgroup's first nb column blocks (nb <=
+// kSeedBlocks).  Each lane ranks the 8 transforms of each of its ranges
+// against its column of every block by the least-squares score
+// (G - SA Sb/K)^2 / D' and keeps the best; the bests are posted through LDS
+// (the empty candidate and queue buffers) and lane l < 16 picks range l's
+// best and fits that one candidate exactly.  Any candidate's exact residual
+// is a valid bound; the sweep then covers these blocks as usual.
+constexpr int kSeedBlocks = 2;
+
 template <int K>
-__device__ __forceinline__ void seed_first_block(
-    const Geo &g, WaveState &w, const half8 (&af)[kRB][K / 16],
-    const float (&bbar)[kSlots], const half8 (&bf)[K / 16], const ColRec &sd) {
+__device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
+                                            WaveState &w,
+                                            const half8 (&af)[kRB][K / 16],
+                                            const float (&bbar)[kSlots],
+                                            int c0, int nb) {
   constexpr int KS = K / 16;
-  f32x16 acc[kRB];
-#pragma unroll
-  for (int rb = 0; rb < kRB; ++rb) {
-    acc[rb] = f32x16{};
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk)
-      acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
-                                                       acc[rb], 0, 0, 0);
-  }
-  // flat domains and padding columns (D' = +inf) take no part
-  const bool live = sd.dp != __builtin_inff();
-  const float idp = live ? 1.0f / sd.dp : 0.0f;
-  // per (half, slot, column): score, and G << 3 | transform
+  // per (half, slot, column): score, and block << 27 | G << 3 | transform
   float *sc_tab = (float *)w.cands;
   unsigned *gk_tab = (unsigned *)w.cands + 2 * kSlots * 32;
-  ColRec *col_tab = (ColRec *)w.queue;
+  ColRec *col_tab = (ColRec *)w.queue;  // [kSeedBlocks][32]
+  float best[kSlots];
+  unsigned gk[kSlots];
 #pragma unroll
-  for (int rb = 0; rb < kRB; ++rb)
+  for (int s = 0; s < kSlots; ++s) {
+    best[s] = -1.0f;
+    gk[s] = 0;
+  }
+  half8 bf[KS];
+  ColRec sd;
+  load_column<K>(b, column_of(b, w.nD, c0, w.cl), w.h, bf, sd);
+  for (int blk = 0; blk < nb; ++blk) {
+    f32x16 acc[kRB];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int s = 2 * rb + e;
-      const float c = sd.sa * bbar[s];
-      float best = -1.0f;
-      unsigned gk = 0;
+    for (int rb = 0; rb < kRB; ++rb) {
+      acc[rb] = f32x16{};
 #pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const float gv = acc[rb][8 * e + k];
-        const float d = gv - c;
-        const float v = live ? d * d * idp : -1.0f;
-        if (v > best) {
-          best = v;
-          gk = ((unsigned)gv << 3) | (unsigned)k;
+      for (int kk = 0; kk < KS; ++kk)
+        acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
+                                                         acc[rb], 0, 0, 0);
+    }
+    const ColRec cur = sd;
+    if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
+    if (blk + 1 < nb)
+      load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, bf, sd);
+    // flat domains and padding columns (D' = +inf) take no part
+    const bool live = cur.dp != __builtin_inff();
+    const float idp = live ? 1.0f / cur.dp : 0.0f;
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int s = 2 * rb + e;
+        const float c = cur.sa * bbar[s];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const float gv = acc[rb][8 * e + k];
+          const float d = gv - c;
+          const float v = live ? d * d * idp : -1.0f;
+          if (v > best[s]) {
+            best[s] = v;
+            gk[s] = ((unsigned)blk << 27) | ((unsigned)gv << 3) | (unsigned)k;
+          }
         }
       }
-      sc_tab[(w.h * kSlots + s) * 32 + w.cl] = best;
-      gk_tab[(w.h * kSlots + s) * 32 + w.cl] = gk;
-    }
-  if (w.h == 0) col_tab[w.cl] = sd;
+  }
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    sc_tab[(w.h * kSlots + s) * 32 + w.cl] = best[s];
+    gk_tab[(w.h * kSlots + s) * 32 + w.cl] = gk[s];
+  }
   __builtin_amdgcn_wave_barrier();
   if (w.lane < kWaveRanges) {
     const int lr = w.lane, h = (lr >> 1) & 1, s = 2 * (lr >> 2) + (lr & 1);
     const float4 *row = (const float4 *)(sc_tab + (h * kSlots + s) * 32);
-    float best = -1.0f;
+    float bv = -1.0f;
     int bc = -1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const float4 v = row[q];
-      if (v.x > best) { best = v.x; bc = 4 * q; }
-      if (v.y > best) { best = v.y; bc = 4 * q + 1; }
-      if (v.z > best) { best = v.z; bc = 4 * q + 2; }
-      if (v.w > best) { best = v.w; bc = 4 * q + 3; }
+      if (v.x > bv) { bv = v.x; bc = 4 * q; }
+      if (v.y > bv) { bv = v.y; bc = 4 * q + 1; }
+      if (v.z > bv) { bv = v.z; bc = 4 * q + 2; }
+      if (v.w > bv) { bv = v.w; bc = 4 * q + 3; }
     }
     if (bc >= 0) {
-      const unsigned gk = gk_tab[(h * kSlots + s) * 32 + bc];
-      const ColRec cr = col_tab[bc];
+      const unsigned t = gk_tab[(h * kSlots + s) * 32 + bc];
+      const ColRec cr = col_tab[(t >> 27) * 32 + bc];
       const double2 rs = w.rstat[lr];
-      const Fit f = fit_exact((double)(gk >> 3), (double)cr.sa, (double)cr.saa,
-                              rs.x, rs.y, g);
+      const Fit f = fit_exact((double)((t >> 3) & 0xFFFFFFu), (double)cr.sa,
+                              (double)cr.saa, rs.x, rs.y, g);
       const unsigned long long key =
-          make_key(f.err, 8ll * cr.dom + (gk & 7), g);
+          make_key(f.err, 8ll * cr.dom + (t & 7), g);
       if (key < w.best[lr]) w.best[lr] = key;
     }
+    // share it with the other chunks of these ranges right away
+    const int sl = w.slots[lr];
+    if (sl >= 0 && w.best[lr] < w.gsnap) atomicMin(&b.best[sl], w.best[lr]);
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -544,7 +568,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     bbar[s] = (float)(w.rstat[4 * (s >> 1) + 2 * w.h + (s & 1)].x * g.invK);
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
 
-  seed_first_block<K>(g, w, af, bbar, bA, sdA);
+  seed_blocks<K>(g, b, w, af, bbar, c0, min(kSeedBlocks, c1 - c0));
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
