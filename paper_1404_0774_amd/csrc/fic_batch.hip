@@ -79,9 +79,9 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
       const Geo &g = pl.geo[s];
       long long wg = 0;
       if (ph == 0) wg = g.n_dwg;
-      if (ph == 1) wg = ((long long)g.R_pad * g.K + 255) / 256;
+      if (ph == 1) wg = ((long long)g.R_pad * g.n + 255) / 256;
       if (ph == 2) wg = g.R_pad / 8;
-      if (ph == 3) wg = ((long long)g.R_pad * g.K + 255) / 256;
+      if (ph == 3) wg = ((long long)g.R_pad * g.n + 255) / 256;
       acc += (int)wg;
     }
     pl.phase_off[ph * (n + 1) + n] = acc;

@@ -54,14 +54,38 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// One thread per (column, cell row): N threads per column.  Column c of the
-// sweep holds domain d = (c * dom_stride) mod ND; its 2x2 cell sums A (4x the
-// contracted value of Alg. 1) are written as exact FP16 integers.  12-bit
-// images store A = 128 A_hi + A_lo as two planes.  Flat domains (no
-// variance) get +inf as their prune denominator: they all fit any range with
-// s = 0 and the same offset (eqs. 11-12), so only the first of them, seeded
-// per range, can be kept.  Each workgroup records the smallest flat domain
-// index it saw.
+// The 2N pixels p[0 .. 2N) of one domain row.  wide: p is 4-byte aligned,
+// so the row is read as 32-bit words (four 8-bit or two 16-bit pixels each).
+template <typename Pix, int N>
+__device__ __forceinline__ void load_row(const Pix *p, bool wide,
+                                         int (&v)[2 * N]) {
+  constexpr int PW = 4 / sizeof(Pix);  // pixels per word
+  if (wide) {
+    const unsigned *w = (const unsigned *)p;
+#pragma unroll
+    for (int q = 0; q < 2 * N / PW; ++q) {
+      const unsigned u = w[q];
+#pragma unroll
+      for (int e = 0; e < PW; ++e)
+        v[q * PW + e] = (int)((u >> (8 * sizeof(Pix) * e)) &
+                              ((1u << (8 * sizeof(Pix))) - 1u));
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 2 * N; ++k) v[k] = (int)p[k];
+  }
+}
+
+// One thread per (domain, cell row): N threads per domain, domains in
+// natural order so that the threads of a wave read neighbouring pixels.
+// Domain d goes to sweep column (d * dom_stride_inv) mod ND, the column
+// that holds domain (c * dom_stride) mod ND; threads past ND fill the
+// padding columns.  Its 2x2 cell sums A (4x the contracted value of Alg. 1)
+// are written as exact FP16 integers.  12-bit images store A = 128 A_hi +
+// A_lo as two planes.  Flat domains (no variance) get +inf as their prune
+// denominator: they all fit any range with s = 0 and the same offset (eqs.
+// 11-12), so only the first of them, seeded per range, can be kept.  Each
+// workgroup records the smallest flat domain index it saw.
 template <typename Pix, int N>
 __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
                                                   const EncBufs &b, int bid) {
@@ -71,26 +95,34 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   if (threadIdx.x == 0) s_flat = INT_MAX;
   __syncthreads();
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const long long col = t / N;
+  const long long e = t / N;  // domain, or padding column e >= ND
   const int i = (int)(t % N);
-  const bool live = col < g.NC_pad;
+  const bool live = e < g.NC_pad;
+  long long col = e;
   long long SA = 0, SAA = 0;
   int d = -1;
   halfN vh, vl;
 #pragma unroll
   for (int j = 0; j < N; ++j) vh[j] = vl[j] = (_Float16)0.0f;
-  if (live && col < g.ND) {
-    // 32-bit arithmetic whenever col * stride < (ND + 32) * ND fits
-    d = g.ND <= 65000
-            ? (int)(((unsigned)col * (unsigned)g.dom_stride) % (unsigned)g.ND)
-            : (int)((col * (long long)g.dom_stride) % g.ND);
+  if (live && e < g.ND) {
+    d = (int)e;
+    // 32-bit arithmetic whenever d * stride_inv < ND^2 fits
+    col = g.ND <= 65000
+              ? (long long)(((unsigned)d * (unsigned)g.dom_stride_inv) %
+                            (unsigned)g.ND)
+              : ((long long)d * g.dom_stride_inv) % g.ND;
     const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
     const Pix *r0 = img + (size_t)(Y + 2 * i) * g.W + X;
-    const Pix *r1 = r0 + g.W;
+    // rows start on 4-byte boundaries when the image, its width and the
+    // domain step allow it (the same for every thread)
+    const bool wide = ((uintptr_t)img & 3) == 0 &&
+                      ((g.W | g.step) & (sizeof(Pix) == 1 ? 3 : 1)) == 0;
+    int p0[2 * N], p1[2 * N];
+    load_row<Pix, N>(r0, wide, p0);
+    load_row<Pix, N>(r0 + g.W, wide, p1);
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const int A = (int)r0[2 * j] + (int)r0[2 * j + 1] + (int)r1[2 * j] +
-                    (int)r1[2 * j + 1];
+      const int A = p0[2 * j] + p0[2 * j + 1] + p1[2 * j] + p1[2 * j + 1];
       SA += A;
       SAA += (long long)A * A;
       if (g.bits == 12) {
@@ -133,50 +165,69 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
 }
 
-// One thread per range pixel (K threads per range slot r, one wave for
-// n = 8); the slot holds image range range_of_slot(r).
-// Every thread writes its pixel into the 8 rows of its range, row 8 r + k at
-// position sigma_k(q), so that sum_p T[p] row[p] = sum_q T[sigma_k(q)] b[q].
-// 12-bit: b = 64 b_hi + b_lo, two planes.  The range statistics are reduced
-// over the K lanes (32-bit sums for 8-bit images, where every sum is below
-// 2^31), and the range's best key is seeded with candidate c = 0 (domain 0,
-// identity), fitted exactly.
-template <typename Pix, int N>
+// L lanes per range slot r (L = K = N^2: one pixel each, one wave for
+// n = 8; L = N: one row each), the slot holding image range
+// range_of_slot(r).  Every pixel is written into the 8 rows of its range,
+// row 8 r + k at position sigma_k(q), so that sum_p T[p] row[p] =
+// sum_q T[sigma_k(q)] b[q] (unless the search builds those rows from the
+// pixels itself).  12-bit: b = 64 b_hi + b_lo, two planes.  The range
+// statistics are reduced over the L lanes (32-bit sums for 8-bit images,
+// where every sum is below 2^31), and the range's best key is seeded with
+// candidate c = 0 (domain 0, identity), fitted exactly.
+template <typename Pix, int N, int L>
 __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
                                                  const EncBufs &b, int bid) {
-  constexpr int K = N * N;
+  constexpr int K = N * N, P = K / L;  // pixels per lane
+  static_assert(L == N || L == K, "a row or a pixel per lane");
   typedef typename std::conditional<sizeof(Pix) == 1, int, long long>::type Acc;
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const int r = (int)(t / K), q = (int)(t % K);
-  if (r >= g.R_pad) return;  // whole groups of K lanes leave together
-  const int i = q / N, j = q % N, m = N - 1;
+  const int r = (int)(t / L), q0 = (int)(t % L) * P, m = N - 1;
+  if (r >= g.R_pad) return;  // whole groups of L lanes leave together
+  const int i = q0 / N, j0 = q0 % N;  // the lane's pixels: row i, j0 ..
   _Float16 *row_hi = b.aop + (size_t)r * 8 * K;
   _Float16 *row_lo = b.aop + (size_t)g.R_pad * 8 * K + (size_t)r * 8 * K;
-  int v = 0, A0 = 0;
+  int v[P], A0[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = A0[e] = 0;
   const int ri = range_of_slot(g, r);  // image range of slot r
   if (ri < g.R) {
     const int ry = ri / g.RW, rx = ri % g.RW;
-    v = (int)img[(size_t)(ry * N + i) * g.W + rx * N + j];
-    A0 = cell_sum(img, g.W, 2 * i, 2 * j);  // domain 0 sits at (0, 0)
-  }
+    const Pix *p = img + (size_t)(ry * N + i) * g.W + rx * N + j0;
 #pragma unroll
-  for (int k = 0; k < 8 && !g.pix_a; ++k) {
-    int si, sj;
-    sigma(k, i, j, m, si, sj);
-    const int p = si * N + sj;
-    if (sizeof(Pix) == 2) {
-      row_hi[k * K + p] = (_Float16)(float)(v >> 6);
-      row_lo[k * K + p] = (_Float16)(float)(v & 63);
-    } else {
-      row_hi[k * K + p] = (_Float16)(float)v;
+    for (int e = 0; e < P; ++e) {
+      v[e] = (int)p[e];
+      A0[e] = cell_sum(img, g.W, 2 * i, 2 * (j0 + e));  // domain 0: (0, 0)
     }
   }
-  const Acc Sb = group_sum<K>((Acc)v);
-  const Acc Sbb = group_sum<K>((Acc)v * v);
-  const Acc G0 = group_sum<K>((Acc)A0 * v);
-  const Acc SA0 = group_sum<K>((Acc)A0);
-  const Acc SAA0 = group_sum<K>((Acc)A0 * A0);
-  if (q != 0) return;
+  Acc Sb = 0, Sbb = 0, G0 = 0, SA0 = 0, SAA0 = 0;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    if (!g.pix_a) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        int si, sj;
+        sigma(k, i, j0 + e, m, si, sj);
+        const int pp = si * N + sj;
+        if (sizeof(Pix) == 2) {
+          row_hi[k * K + pp] = (_Float16)(float)(v[e] >> 6);
+          row_lo[k * K + pp] = (_Float16)(float)(v[e] & 63);
+        } else {
+          row_hi[k * K + pp] = (_Float16)(float)v[e];
+        }
+      }
+    }
+    Sb += v[e];
+    Sbb += (Acc)v[e] * v[e];
+    G0 += (Acc)A0[e] * v[e];
+    SA0 += A0[e];
+    SAA0 += (Acc)A0[e] * A0[e];
+  }
+  Sb = group_sum<L>(Sb);
+  Sbb = group_sum<L>(Sbb);
+  G0 = group_sum<L>(G0);
+  SA0 = group_sum<L>(SA0);
+  SAA0 = group_sum<L>(SAA0);
+  if (q0 != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
   // searched iff a real range with variance (K Sbb - Sb^2 != 0, exact)
@@ -198,44 +249,55 @@ __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
   if ((int)blockIdx.x < g.n_dwg)
     prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
   else
-    prep_ranges_body<Pix, N>(g, img, b, blockIdx.x - g.n_dwg);
+    prep_ranges_body<Pix, N, N * N>(g, img, b, blockIdx.x - g.n_dwg);
 }
 
-// One group of K lanes per range: unpack the winning key and recompute its
-// fit from the image to produce the code (domain, transform, s index,
-// o index, residual).  Flat domains (no variance) all fit a range with s = 0
-// and the range mean (eqs. 11-12), so they tie and only the first of them
-// can win; the search skips them and the first one is compared here.
-template <typename Pix, int N>
+// One group of L lanes per range (L = N or K = N^2), each lane holding K / L
+// consecutive pixels of the range: unpack the winning key and recompute its
+// fit from the image to produce the code (domain, transform, s index, o
+// index, residual).  K lanes suit one image (many short waves), N lanes a
+// batch (a quarter or an eighth of the waves).  Flat domains (no variance) all fit
+// a range with s = 0 and the range mean (eqs. 11-12), so they tie and only
+// the first of them can win; the search skips them and the first one is
+// compared here.
+template <typename Pix, int N, int L>
 __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
                                               const EncBufs &b,
                                               const fic_codes &out, int bid) {
-  constexpr int K = N * N;
+  constexpr int P = N * N / L;  // pixels per lane
+  static_assert(L == N || L == N * N, "a row or a pixel per lane");
   __shared__ int s_wmin[8];  // per-wave minima of the flat-domain table
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const int slot = (int)(t / K), q = (int)(t % K);
+  const int slot = (int)(t / L), q0 = (int)(t % L) * P, m = N - 1;
   const bool live = slot < g.R_pad;
   const int r = live ? range_of_slot(g, slot) : g.R;  // image range
-  // independent loads first: the key, the range sums, the flat-domain table
-  const int i = q / N, j = q % N, m = N - 1;
+  // independent loads first: the key, the range sums, the range row, the
+  // flat-domain table
   unsigned long long key = ~0ull;
-  double Sb0 = 0.0, Sbb0 = 0.0, v = 0.0;
+  double Sb0 = 0.0, Sbb0 = 0.0;
+  int v[P];
+#pragma unroll
+  for (int e = 0; e < P; ++e) v[e] = 0;
   if (live && r < g.R) {
     key = b.best[slot];
     Sb0 = b.rng_sb[slot];
     Sbb0 = b.rng_sbb[slot];
-    v = (double)img[(size_t)((r / g.RW) * N + i) * g.W + (r % g.RW) * N + j];
+    // the lane's pixels lie in one row of the range
+    const Pix *p = img + (size_t)((r / g.RW) * N + q0 / N) * g.W +
+                   (r % g.RW) * N + q0 % N;
+#pragma unroll
+    for (int e = 0; e < P; ++e) v[e] = (int)p[e];
   }
   int mf = INT_MAX;
-  for (int i = threadIdx.x; i < g.n_dwg; i += blockDim.x)
-    mf = min(mf, b.flat_min[i]);
+  for (int w = threadIdx.x; w < g.n_dwg; w += blockDim.x)
+    mf = min(mf, b.flat_min[w]);
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) mf = min(mf, __shfl_xor(mf, o));
   if ((threadIdx.x & 63) == 0) s_wmin[threadIdx.x >> 6] = mf;
   __syncthreads();
   int ff = s_wmin[0];
   for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) ff = min(ff, s_wmin[wv]);
-  if (!live || r >= g.R) return;  // padding: whole groups of K lanes leave
+  if (!live || r >= g.R) return;  // padding: whole groups of L lanes leave
   if (ff < g.ND) {
     const Fit f0 = fit_exact(0.0, 0.0, 0.0, Sb0, Sbb0, g);
     const unsigned long long kf = make_key(f0.err, 8ll * ff, g);
@@ -244,17 +306,27 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
   const long long c = (long long)(key & ((1ull << g.cbits) - 1));
   const int d = (int)(c >> 3), k = (int)(c & 7);
   const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
-  int si, sj;
-  sigma(k, i, j, m, si, sj);
-  const double A = (double)cell_sum(img, g.W, Y + 2 * si, X + 2 * sj);
-  // integer sums below 2^53: exact in double in any order
-  const double G = group_sum<K>(A * v);
-  const double SA = group_sum<K>(A);
-  const double SAA = group_sum<K>(A * A);
-  const double Sb = group_sum<K>(v);
-  const double Sbb = group_sum<K>(v * v);
-  if (q != 0) return;
-  const Fit f = fit_exact(G, SA, SAA, Sb, Sbb, g);
+  // integer sums (below 2^63 per lane and 2^53 in total): exact
+  long long G = 0, SA = 0, SAA = 0, Sb = 0, Sbb = 0;
+#pragma unroll
+  for (int e = 0; e < P; ++e) {
+    int si, sj;
+    sigma(k, q0 / N, q0 % N + e, m, si, sj);
+    const long long A = cell_sum(img, g.W, Y + 2 * si, X + 2 * sj);
+    G += A * v[e];
+    SA += A;
+    SAA += A * A;
+    Sb += v[e];
+    Sbb += (long long)v[e] * v[e];
+  }
+  G = group_sum<L>(G);
+  SA = group_sum<L>(SA);
+  SAA = group_sum<L>(SAA);
+  Sb = group_sum<L>(Sb);
+  Sbb = group_sum<L>(Sbb);
+  if (q0 != 0) return;
+  const Fit f = fit_exact((double)G, (double)SA, (double)SAA, (double)Sb,
+                          (double)Sbb, g);
   out.domain[r] = d;
   out.iso[r] = (uint8_t)k;
   out.s_idx[r] = (uint8_t)f.j;
@@ -265,7 +337,7 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
                                                   EncBufs b, fic_codes out) {
-  finalize_body<Pix, N>(g, img, b, out, blockIdx.x);
+  finalize_body<Pix, N, N * N>(g, img, b, out, blockIdx.x);
 }
 
 template <typename Pix>
@@ -280,34 +352,26 @@ hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
   return hipGetLastError();
 }
 
-// Ordered compaction of the indices i < n whose flag byte is 1, by one
-// workgroup of 1024 threads (n a multiple of 16).  Thread t owns the
-// contiguous 16-byte words [t P, (t + 1) P) of the flags and counts them
-// with one popcount per word; the counts are scanned in LDS and each thread
-// writes its selected indices in order.
-__device__ __forceinline__ void block_compact(int n, const uint8_t *flag,
-                                              int32_t *out, int32_t *count) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int words = n / 16;
-  const int per = (words + 1023) / 1024;
-  const int w0 = min(t * per, words), w1 = min(w0 + per, words);
+// Ordered compaction of the indices whose flag byte is 1, for two flag
+// arrays at once (lengths multiples of 16), by one workgroup of 1024
+// threads.  Thread t owns a contiguous run of 16-byte words of each array
+// and counts it with one popcount per word; a shuffle scan inside each wave
+// and one pass over the 16 wave totals in LDS give every thread its output
+// position, and it writes its selected indices in order.
+__device__ __forceinline__ void count_words(const uint8_t *flag, int w0,
+                                            int w1, int &c) {
   const uint4 *fw = (const uint4 *)flag;
-  int c = 0;
+  c = 0;
   for (int i = w0; i < w1; ++i) {
     const uint4 v = fw[i];  // 16 flags of 0 or 1
     c += __builtin_popcount(v.x) + __builtin_popcount(v.y) +
          __builtin_popcount(v.z) + __builtin_popcount(v.w);
   }
-  part[t] = c;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = t >= o ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int pos = part[t] - c;
+}
+
+__device__ __forceinline__ void write_selected(const uint8_t *flag, int w0,
+                                               int w1, int pos, int32_t *out) {
+  const uint4 *fw = (const uint4 *)flag;
   for (int i = w0; i < w1; ++i) {
     const uint4 v = fw[i];
     const unsigned u[4] = {v.x, v.y, v.z, v.w};
@@ -317,16 +381,56 @@ __device__ __forceinline__ void block_compact(int n, const uint8_t *flag,
       for (int e = 0; e < 4; ++e)
         if ((u[q] >> (8 * e)) & 1u) out[pos++] = 16 * i + 4 * q + e;
   }
-  if (t == 1023) *count = part[1023];
-  __syncthreads();  // part is reused by the next call
+}
+
+__device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
+                                               int32_t *o0, int n1,
+                                               const uint8_t *f1, int32_t *o1,
+                                               int32_t *count) {
+  __shared__ int2 wtot[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int p0 = (n0 / 16 + 1023) / 1024, p1 = (n1 / 16 + 1023) / 1024;
+  const int a0 = min(t * p0, n0 / 16), a1 = min(a0 + p0, n0 / 16);
+  const int b0 = min(t * p1, n1 / 16), b1 = min(b0 + p1, n1 / 16);
+  int c0, c1;
+  count_words(f0, a0, a1, c0);
+  count_words(f1, b0, b1, c1);
+  // inclusive scan over the wave
+  int s0 = c0, s1 = c1;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u0 = __shfl_up(s0, o), u1 = __shfl_up(s1, o);
+    if (lane >= o) {
+      s0 += u0;
+      s1 += u1;
+    }
+  }
+  if (lane == 63) wtot[wave] = int2{s0, s1};
+  __syncthreads();
+  int q0 = 0, q1 = 0, t0 = 0, t1 = 0;
+  for (int w = 0; w < 16; ++w) {
+    const int2 v = wtot[w];
+    if (w < wave) {
+      q0 += v.x;
+      q1 += v.y;
+    }
+    t0 += v.x;
+    t1 += v.y;
+  }
+  write_selected(f0, a0, a1, q0 + s0 - c0, o0);
+  write_selected(f1, b0, b1, q1 + s1 - c1, o1);
+  if (t == 0) {
+    count[0] = t0;
+    count[1] = t1;
+  }
 }
 
 // The search's work lists: range slots holding a range with variance and
 // domain columns holding a domain with variance (flags written by the
 // preparation), both in slot / sweep order.
 __device__ __forceinline__ void compact_body(const Geo &g, const EncBufs &b) {
-  block_compact(g.R_pad, b.rng_flag, b.act_slot, &b.n_act[0]);
-  block_compact(g.NC_pad, b.col_flag, b.act_col, &b.n_act[1]);
+  block_compact2(g.R_pad, b.rng_flag, b.act_slot, g.NC_pad, b.col_flag,
+                 b.act_col, b.n_act);
 }
 
 __global__ __launch_bounds__(1024) void k_compact(Geo g, EncBufs b) {
@@ -374,7 +478,7 @@ __global__ __launch_bounds__(256) void k_prep_batch(BatchDev bd) {
   if (dom)
     prep_domains_body<Pix, N>(g, img, b, pb - off[s]);
   else
-    prep_ranges_body<Pix, N>(g, img, b, pb - off[s]);
+    prep_ranges_body<Pix, N, N>(g, img, b, pb - off[s]);
 }
 
 template <typename Pix, int N>
@@ -384,7 +488,7 @@ __global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
   const Geo g = load_uniform(&bd.tab[s].g);
   const EncBufs b = load_uniform(&bd.tab[s].b);
   const fic_codes out = load_uniform(&bd.tab[s].out);
-  finalize_body<Pix, N>(g, (const Pix *)bd.tab[s].image, b, out,
+  finalize_body<Pix, N, N>(g, (const Pix *)bd.tab[s].image, b, out,
                         blockIdx.x - off[s]);
 }
 
