@@ -19,12 +19,12 @@ struct BatchPlan {
   std::vector<Geo> geo;
   std::vector<Tune> tune;
   std::vector<int4> items;
-  std::vector<int> phase_off;        // [4][n + 1]
+  std::vector<int2> wg_map;          // [sum of phase_total]
   std::vector<int> items_per_slice;  // [n]
   std::vector<size_t> slice_off;     // workspace offset of each slice
-  size_t off_tab, off_items, off_phase, off_ips, off_rem, off_counter,
+  size_t off_tab, off_items, off_map, off_ips, off_rem, off_counter,
       off_ticks, total;
-  int phase_total[4];
+  int phase_total[4], phase_base[4];
 };
 
 int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
@@ -71,27 +71,27 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
       }
   }
 
-  pl.phase_off.assign(4 * (n + 1), 0);
+  pl.wg_map.clear();
   for (int ph = 0; ph < 4; ++ph) {
+    pl.phase_base[ph] = (int)pl.wg_map.size();
     int acc = 0;
     for (int s = 0; s < n; ++s) {
-      pl.phase_off[ph * (n + 1) + s] = acc;
       const Geo &g = pl.geo[s];
       long long wg = 0;
       if (ph == 0) wg = g.n_dwg;
       if (ph == 1) wg = ((long long)g.R_pad * g.n + 255) / 256;
       if (ph == 2) wg = g.R_pad / 8;
       if (ph == 3) wg = ((long long)g.R_pad * g.n + 255) / 256;
+      for (int i = 0; i < (int)wg; ++i) pl.wg_map.push_back(int2{s, i});
       acc += (int)wg;
     }
-    pl.phase_off[ph * (n + 1) + n] = acc;
     pl.phase_total[ph] = acc;
   }
 
   size_t o = 0;
   pl.off_tab = o;     o = a256(o + sizeof(SliceDesc) * n);
   pl.off_items = o;   o = a256(o + sizeof(int4) * pl.items.size());
-  pl.off_phase = o;   o = a256(o + sizeof(int) * pl.phase_off.size());
+  pl.off_map = o;     o = a256(o + sizeof(int2) * pl.wg_map.size());
   pl.off_ips = o;     o = a256(o + sizeof(int) * n);
   pl.off_rem = o;     o = a256(o + sizeof(int) * n);
   pl.off_counter = o; o = a256(o + sizeof(int));
@@ -110,14 +110,17 @@ BatchDev batch_dev(const BatchPlan &pl, void *ws, int n) {
   BatchDev bd;
   bd.tab = (SliceDesc *)(w + pl.off_tab);
   bd.items = (int4 *)(w + pl.off_items);
-  bd.phase_off = (int *)(w + pl.off_phase);
+  bd.wg_map = (int2 *)(w + pl.off_map);
   bd.items_per_slice = (int *)(w + pl.off_ips);
   bd.remaining = (int *)(w + pl.off_rem);
   bd.counter = (int *)(w + pl.off_counter);
   bd.ticks = (unsigned long long *)(w + pl.off_ticks);
   bd.n = n;
   bd.n_items = (int)pl.items.size();
-  for (int i = 0; i < 4; ++i) bd.phase_total[i] = pl.phase_total[i];
+  for (int i = 0; i < 4; ++i) {
+    bd.phase_total[i] = pl.phase_total[i];
+    bd.phase_base[i] = pl.phase_base[i];
+  }
   bd.bits = pl.geo[0].bits;
   bd.rsize = pl.geo[0].n;
   return bd;
@@ -171,8 +174,8 @@ int fic_batch_prepare(const fic_params *slices, int32_t n_slices,
     e = hipMemcpy(w + pl.off_items, pl.items.data(),
                   sizeof(int4) * pl.items.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
-    e = hipMemcpy(w + pl.off_phase, pl.phase_off.data(),
-                  sizeof(int) * pl.phase_off.size(), hipMemcpyHostToDevice);
+    e = hipMemcpy(w + pl.off_map, pl.wg_map.data(),
+                  sizeof(int2) * pl.wg_map.size(), hipMemcpyHostToDevice);
   if (e == hipSuccess)
     e = hipMemcpy(w + pl.off_ips, pl.items_per_slice.data(),
                   sizeof(int) * n_slices, hipMemcpyHostToDevice);

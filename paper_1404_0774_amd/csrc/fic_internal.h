@@ -98,14 +98,16 @@ struct SliceDesc {
 struct BatchDev {
   SliceDesc *tab;             // [n]
   int4 *items;                // [n_items]: slice, row group, first block, end
-  int *phase_off;             // [4][n + 1] workgroup offsets per phase:
-                              //   domain prep, range prep, seed, finalize
+  int2 *wg_map;               // per phase (domain prep, range prep, seed,
+                              //   finalize) and workgroup: slice and the
+                              //   workgroup's index within the slice
   int *items_per_slice;       // [n]
   int *remaining;             // [n] unfinished search items per slice
   int *counter;               // [1] next search item
   unsigned long long *ticks;  // [n + 1] start tick, completion tick per slice
   int n, n_items;
   int phase_total[4];         // workgroups per phase
+  int phase_base[4];          // first entry of each phase in wg_map
   int bits, rsize;            // common to every slice
 };
 

@@ -54,16 +54,17 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
-// The 2N pixels p[0 .. 2N) of one domain row.  wide: p is 4-byte aligned,
-// so the row is read as 32-bit words (four 8-bit or two 16-bit pixels each).
-template <typename Pix, int N>
-__device__ __forceinline__ void load_row(const Pix *p, bool wide,
-                                         int (&v)[2 * N]) {
+// The C pixels p[0 .. C) of an image row (C sizeof(Pix) a multiple of 4).
+// wide: p is 4-byte aligned, so the run is read as 32-bit words (four 8-bit
+// or two 16-bit pixels each).
+template <typename Pix, int C>
+__device__ __forceinline__ void load_run(const Pix *p, bool wide, int (&v)[C]) {
   constexpr int PW = 4 / sizeof(Pix);  // pixels per word
+  static_assert(C % PW == 0, "whole words");
   if (wide) {
     const unsigned *w = (const unsigned *)p;
 #pragma unroll
-    for (int q = 0; q < 2 * N / PW; ++q) {
+    for (int q = 0; q < C / PW; ++q) {
       const unsigned u = w[q];
 #pragma unroll
       for (int e = 0; e < PW; ++e)
@@ -72,8 +73,24 @@ __device__ __forceinline__ void load_row(const Pix *p, bool wide,
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 2 * N; ++k) v[k] = (int)p[k];
+    for (int k = 0; k < C; ++k) v[k] = (int)p[k];
   }
+}
+
+// The 2N pixels of one domain row.
+template <typename Pix, int N>
+__device__ __forceinline__ void load_row(const Pix *p, bool wide,
+                                         int (&v)[2 * N]) {
+  load_run<Pix, 2 * N>(p, wide, v);
+}
+
+// Whether every domain row starts on a 4-byte boundary: the image, its width
+// and the domain step allow it.
+template <typename Pix>
+__device__ __forceinline__ bool domain_rows_aligned(const Geo &g,
+                                                    const Pix *img) {
+  return ((uintptr_t)img & 3) == 0 &&
+         ((g.W | g.step) & (sizeof(Pix) == 1 ? 3 : 1)) == 0;
 }
 
 // One thread per (domain, cell row): N threads per domain, domains in
@@ -113,10 +130,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
               : ((long long)d * g.dom_stride_inv) % g.ND;
     const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
     const Pix *r0 = img + (size_t)(Y + 2 * i) * g.W + X;
-    // rows start on 4-byte boundaries when the image, its width and the
-    // domain step allow it (the same for every thread)
-    const bool wide = ((uintptr_t)img & 3) == 0 &&
-                      ((g.W | g.step) & (sizeof(Pix) == 1 ? 3 : 1)) == 0;
+    const bool wide = domain_rows_aligned(g, img);
     int p0[2 * N], p1[2 * N];
     load_row<Pix, N>(r0, wide, p0);
     load_row<Pix, N>(r0 + g.W, wide, p1);
@@ -193,10 +207,23 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
   if (ri < g.R) {
     const int ry = ri / g.RW, rx = ri % g.RW;
     const Pix *p = img + (size_t)(ry * N + i) * g.W + rx * N + j0;
+    if constexpr (P == N) {
+      // a range row and a cell row of domain 0 (at (0, 0)), as words when
+      // the rows are aligned
+      const bool wide = domain_rows_aligned(g, img);
+      int p0[2 * N], p1[2 * N];
+      load_run<Pix, N>(p, wide, v);
+      load_row<Pix, N>(img + (size_t)(2 * i) * g.W, wide, p0);
+      load_row<Pix, N>(img + (size_t)(2 * i + 1) * g.W, wide, p1);
 #pragma unroll
-    for (int e = 0; e < P; ++e) {
-      v[e] = (int)p[e];
-      A0[e] = cell_sum(img, g.W, 2 * i, 2 * (j0 + e));  // domain 0: (0, 0)
+      for (int e = 0; e < P; ++e)
+        A0[e] = p0[2 * e] + p0[2 * e + 1] + p1[2 * e] + p1[2 * e + 1];
+    } else {
+#pragma unroll
+      for (int e = 0; e < P; ++e) {
+        v[e] = (int)p[e];
+        A0[e] = cell_sum(img, g.W, 2 * i, 2 * (j0 + e));  // domain 0: (0, 0)
+      }
     }
   }
   Acc Sb = 0, Sbb = 0, G0 = 0, SA0 = 0, SAA0 = 0;
@@ -271,22 +298,13 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
   const int slot = (int)(t / L), q0 = (int)(t % L) * P, m = N - 1;
   const bool live = slot < g.R_pad;
   const int r = live ? range_of_slot(g, slot) : g.R;  // image range
-  // independent loads first: the key, the range sums, the range row, the
-  // flat-domain table
+  // independent loads first: the key, the range sums, the flat-domain table
   unsigned long long key = ~0ull;
   double Sb0 = 0.0, Sbb0 = 0.0;
-  int v[P];
-#pragma unroll
-  for (int e = 0; e < P; ++e) v[e] = 0;
   if (live && r < g.R) {
     key = b.best[slot];
     Sb0 = b.rng_sb[slot];
     Sbb0 = b.rng_sbb[slot];
-    // the lane's pixels lie in one row of the range
-    const Pix *p = img + (size_t)((r / g.RW) * N + q0 / N) * g.W +
-                   (r % g.RW) * N + q0 % N;
-#pragma unroll
-    for (int e = 0; e < P; ++e) v[e] = (int)p[e];
   }
   int mf = INT_MAX;
   for (int w = threadIdx.x; w < g.n_dwg; w += blockDim.x)
@@ -306,18 +324,39 @@ __device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
   const long long c = (long long)(key & ((1ull << g.cbits) - 1));
   const int d = (int)(c >> 3), k = (int)(c & 7);
   const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
-  // integer sums (below 2^63 per lane and 2^53 in total): exact
+  // The lane takes cells (ci, cj0 ..) of the domain in natural order and
+  // the range pixels they meet, sigma_k^-1 of each cell: G = sum_q
+  // A[sigma_k(q)] b[q] = sum_p A[p] b[sigma_k^-1(p)].  Integer sums (below
+  // 2^63 per lane and 2^53 in total): exact.
+  const int ci = q0 / N, cj0 = q0 % N;
+  int A[P];
+  if constexpr (P == N) {
+    // one cell row: two image rows, as words when they are aligned
+    int p0[2 * N], p1[2 * N];
+    const Pix *c0 = img + (size_t)(Y + 2 * ci) * g.W + X;
+    const bool wide = domain_rows_aligned(g, img);
+    load_row<Pix, N>(c0, wide, p0);
+    load_row<Pix, N>(c0 + g.W, wide, p1);
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+      A[e] = p0[2 * e] + p0[2 * e + 1] + p1[2 * e] + p1[2 * e + 1];
+  } else {
+#pragma unroll
+    for (int e = 0; e < P; ++e)
+      A[e] = cell_sum(img, g.W, Y + 2 * ci, X + 2 * (cj0 + e));
+  }
+  const Pix *rb = img + (size_t)((r / g.RW) * N) * g.W + (r % g.RW) * N;
   long long G = 0, SA = 0, SAA = 0, Sb = 0, Sbb = 0;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    int si, sj;
-    sigma(k, q0 / N, q0 % N + e, m, si, sj);
-    const long long A = cell_sum(img, g.W, Y + 2 * si, X + 2 * sj);
-    G += A * v[e];
-    SA += A;
-    SAA += A * A;
-    Sb += v[e];
-    Sbb += (long long)v[e] * v[e];
+    int bi, bj;
+    sigma_inv(k, ci, cj0 + e, m, bi, bj);
+    const long long bv = (long long)rb[(size_t)bi * g.W + bj];
+    G += (long long)A[e] * bv;
+    SA += A[e];
+    SAA += (long long)A[e] * A[e];
+    Sb += bv;
+    Sbb += bv * bv;
   }
   G = group_sum<L>(G);
   SA = group_sum<L>(SA);
@@ -439,18 +478,6 @@ __global__ __launch_bounds__(1024) void k_compact(Geo g, EncBufs b) {
 
 // Slice of workgroup `bid` in a phase with offsets off[0..n] (off[n] is the
 // total): the s with off[s] <= bid < off[s + 1].
-__device__ __forceinline__ int slice_of(const int *off, int n, int bid) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= bid)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
 __global__ void k_batch_init(BatchDev bd) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
@@ -467,29 +494,26 @@ __global__ void k_batch_init(BatchDev bd) {
 // phase laid out slice after slice.
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_prep_batch(BatchDev bd) {
-  const int bid = blockIdx.x;
-  const bool dom = bid < bd.phase_total[0];
-  const int *off = bd.phase_off + (dom ? 0 : bd.n + 1);
-  const int pb = dom ? bid : bid - bd.phase_total[0];
-  const int s = slice_of(off, bd.n, pb);
-  const Geo g = load_uniform(&bd.tab[s].g);
-  const EncBufs b = load_uniform(&bd.tab[s].b);
-  const Pix *img = (const Pix *)load_uniform(&bd.tab[s].image);
+  // the two phases are consecutive in the map: (slice, workgroup in slice)
+  const bool dom = (int)blockIdx.x < bd.phase_total[0];
+  const int2 m = load_uniform(&bd.wg_map[bd.phase_base[0] + blockIdx.x]);
+  const Geo g = load_uniform(&bd.tab[m.x].g);
+  const EncBufs b = load_uniform(&bd.tab[m.x].b);
+  const Pix *img = (const Pix *)load_uniform(&bd.tab[m.x].image);
   if (dom)
-    prep_domains_body<Pix, N>(g, img, b, pb - off[s]);
+    prep_domains_body<Pix, N>(g, img, b, m.y);
   else
-    prep_ranges_body<Pix, N, N>(g, img, b, pb - off[s]);
+    prep_ranges_body<Pix, N, N>(g, img, b, m.y);
 }
 
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
-  const int *off = bd.phase_off + 3 * (bd.n + 1);
-  const int s = slice_of(off, bd.n, blockIdx.x);
-  const Geo g = load_uniform(&bd.tab[s].g);
-  const EncBufs b = load_uniform(&bd.tab[s].b);
-  const fic_codes out = load_uniform(&bd.tab[s].out);
-  finalize_body<Pix, N, N>(g, (const Pix *)bd.tab[s].image, b, out,
-                        blockIdx.x - off[s]);
+  const int2 m = load_uniform(&bd.wg_map[bd.phase_base[3] + blockIdx.x]);
+  const Geo g = load_uniform(&bd.tab[m.x].g);
+  const EncBufs b = load_uniform(&bd.tab[m.x].b);
+  const fic_codes out = load_uniform(&bd.tab[m.x].out);
+  const Pix *img = (const Pix *)load_uniform(&bd.tab[m.x].image);
+  finalize_body<Pix, N, N>(g, img, b, out, m.y);
 }
 
 // One workgroup per slice.

@@ -163,19 +163,11 @@ __global__ __launch_bounds__(256) void k_seed_dense(Geo g, EncBufs b,
 
 template <int K, bool B12>
 __global__ __launch_bounds__(256) void k_seed_batch(BatchDev bd, int nblocks) {
-  const int *off = bd.phase_off + 2 * (bd.n + 1);
-  int lo = 0, hi = bd.n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (off[mid] <= (int)blockIdx.x)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  const int nb = min(nblocks, bd.tab[lo].seed_blocks);
-  const Geo g = load_uniform(&bd.tab[lo].g);
-  const EncBufs b = load_uniform(&bd.tab[lo].b);
-  seed_dense_body<K, B12>(g, b, nb, blockIdx.x - off[lo]);
+  const int2 m = load_uniform(&bd.wg_map[bd.phase_base[2] + blockIdx.x]);
+  const int nb = min(nblocks, load_uniform(&bd.tab[m.x].seed_blocks));
+  const Geo g = load_uniform(&bd.tab[m.x].g);
+  const EncBufs b = load_uniform(&bd.tab[m.x].b);
+  seed_dense_body<K, B12>(g, b, nb, m.y);
 }
 
 }  // namespace
