@@ -174,7 +174,7 @@ struct WaveState {
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
   int qn;                    // queued pairs (wave-uniform)
-  unsigned long long gsnap;  // global keys as last seen (lanes < 16)
+  unsigned long long gsnap;  // global keys as last read (lanes < 16)
   int wr0, h, cl, lane;
 };
 
@@ -292,18 +292,20 @@ __device__ __forceinline__ void sweep_block(
 
   const int jn = cb - c0 + 1;  // blocks done in this chunk
   if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
-    // merge the global snapshot taken at the previous sync, publish this
-    // wave's bests with a non-returning atomic and take a new snapshot
-    // (the last block also drains what is left in the queue)
+    // publish this wave's bests with a non-returning atomic where they
+    // beat the global keys as last read, then read the global keys and use
+    // them at once: waiting for the read costs less than sweeping on with a
+    // stale bound (the last block first drains what is left in the queue;
+    // its read is kept too, which measured faster than leaving it out)
     if (cb + 1 == c1 && w.qn > 0)
       drain(w.queue, w.cands, w.qn, w.qn, w.best, w.rstat, g);
     if (w.lane < kWaveRanges) {
       const int sl = w.slots[w.lane];
-      const unsigned long long m = min(w.best[w.lane], w.gsnap);
-      w.best[w.lane] = m;
       if (sl >= 0) {
+        const unsigned long long m = w.best[w.lane];
         if (m < w.gsnap) atomicMin(&b.best[sl], m);
         w.gsnap = load_best(&b.best[sl]);
+        w.best[w.lane] = min(m, w.gsnap);
       }
     }
     refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);

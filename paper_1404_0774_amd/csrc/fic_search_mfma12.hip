@@ -286,11 +286,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
     if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
       if (cb + 1 == c1 && qn > 0)
         drain12(queue, cands, qn, qn, my_best, rstat, g);
+      // publish, then read the global keys and use them at once
       if (lane < kWR) {
-        const unsigned long long m = min(my_best[lane], gsnap);
-        my_best[lane] = m;
+        const unsigned long long m = my_best[lane];
         if (m < gsnap) atomicMin(&b.best[wr0 + lane], m);
         gsnap = load_best(&b.best[wr0 + lane]);
+        my_best[lane] = min(m, gsnap);
       }
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
