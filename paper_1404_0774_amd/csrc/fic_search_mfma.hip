@@ -326,22 +326,27 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
                                             WaveState &w,
                                             const half8 (&af)[kRB][K / 16],
                                             const float (&bbar)[kSlots],
-                                            int c0, int nb) {
+                                            const half8 (&b0)[K / 16],
+                                            const ColRec &sd0, int c0,
+                                            int nb) {
   constexpr int KS = K / 16;
   // per (half, slot, column): score, and block << 27 | G << 3 | transform
   float *sc_tab = (float *)w.cands;
   unsigned *gk_tab = (unsigned *)w.cands + 2 * kSlots * 32;
   ColRec *col_tab = (ColRec *)w.queue;  // [kSeedBlocks][32]
-  float best[kSlots];
-  unsigned gk[kSlots];
+  // per slot: best score (0: none), its G and block * 8 + transform
+  float best[kSlots], bestg[kSlots];
+  unsigned bestk[kSlots];
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
-    best[s] = -1.0f;
-    gk[s] = 0;
+    best[s] = 0.0f;
+    bestg[s] = 0.0f;
+    bestk[s] = 0;
   }
-  half8 bf[KS];
-  ColRec sd;
-  load_column<K>(b, column_of(b, w.nD, c0, w.cl), w.h, bf, sd);
+  half8 bf[KS];  // the first block is the sweep's, already loaded
+  ColRec sd = sd0;
+#pragma unroll
+  for (int kk = 0; kk < KS; ++kk) bf[kk] = b0[kk];
   for (int blk = 0; blk < nb; ++blk) {
     f32x16 acc[kRB];
 #pragma unroll
@@ -356,9 +361,9 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
     if (blk + 1 < nb)
       load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, bf, sd);
-    // flat domains and padding columns (D' = +inf) take no part
-    const bool live = cur.dp != __builtin_inff();
-    const float idp = live ? 1.0f / cur.dp : 0.0f;
+    // flat domains and padding columns (D' = +inf) score 0 and take no
+    // part (as does a candidate with G exactly at the mean)
+    const float idp = cur.dp != __builtin_inff() ? 1.0f / cur.dp : 0.0f;
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
@@ -369,24 +374,25 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
         for (int k = 0; k < 8; ++k) {
           const float gv = acc[rb][8 * e + k];
           const float d = gv - c;
-          const float v = live ? d * d * idp : -1.0f;
-          if (v > best[s]) {
-            best[s] = v;
-            gk[s] = ((unsigned)blk << 27) | ((unsigned)gv << 3) | (unsigned)k;
-          }
+          const float v = d * d * idp;
+          const bool up = v > best[s];
+          best[s] = up ? v : best[s];
+          bestg[s] = up ? gv : bestg[s];
+          bestk[s] = up ? (unsigned)(8 * blk + k) : bestk[s];
         }
       }
   }
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     sc_tab[(w.h * kSlots + s) * 32 + w.cl] = best[s];
-    gk_tab[(w.h * kSlots + s) * 32 + w.cl] = gk[s];
+    gk_tab[(w.h * kSlots + s) * 32 + w.cl] =
+        ((bestk[s] >> 3) << 27) | ((unsigned)bestg[s] << 3) | (bestk[s] & 7);
   }
   __builtin_amdgcn_wave_barrier();
   if (w.lane < kWaveRanges) {
     const int lr = w.lane, h = (lr >> 1) & 1, s = 2 * (lr >> 2) + (lr & 1);
     const float4 *row = (const float4 *)(sc_tab + (h * kSlots + s) * 32);
-    float bv = -1.0f;
+    float bv = 0.0f;
     int bc = -1;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -570,7 +576,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     bbar[s] = (float)(w.rstat[4 * (s >> 1) + 2 * w.h + (s & 1)].x * g.invK);
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
 
-  seed_blocks<K>(g, b, w, af, bbar, c0, min(kSeedBlocks, c1 - c0));
+  seed_blocks<K>(g, b, w, af, bbar, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
   refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
