@@ -55,18 +55,34 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void k_fill_i32n(int32_t *p, int n, int v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 // --- the domain -> ranges table --------------------------------------------
 
 constexpr int kSeg = 16;  // ranges per list segment
 
-__global__ void k_count_domains(Geo g, const int32_t *domain, int32_t *cnt) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r < g.R) atomicAdd(&cnt[clamp_dom(domain[r], g.ND)], 1);
+// Number of entries of the sorted keys key[0 .. n) below v.
+__device__ __forceinline__ int lower_bound(const int32_t *key, int n, int v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (key[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// From the ranges sorted by domain: where each domain's list starts
+// (off[0 .. ND]) and its length (cnt[0 .. ND)).  A binary search per domain
+// instead of counting with atomics, which would queue up on a domain that
+// thousands of ranges share.
+__global__ void k_bounds(Geo g, const int32_t *sorted, int32_t *off,
+                         int32_t *cnt) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d > g.ND) return;
+  const int a = lower_bound(sorted, g.R, d);
+  off[d] = a;
+  if (d < g.ND) cnt[d] = lower_bound(sorted, g.R, d + 1) - a;
 }
 
 // Exclusive scan of ceil(in[i] / div), i < n, into out[0..n]; one workgroup
@@ -137,13 +153,21 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin,
 }
 
 // Segment table: segment s covers list entries [beg, end) of one domain.
+// One thread per segment; its domain is the last d with segoff[d] <= s.
 __global__ void k_seg_fill(Geo g, const int32_t *off, const int32_t *segoff,
-                           int2 *seg) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= g.ND) return;
-  const int b = off[d], e = off[d + 1];
-  for (int s = segoff[d], x = b; s < segoff[d + 1]; ++s, x += kSeg)
-    seg[s] = int2{x, min(x + kSeg, e)};
+                           int max_seg, int2 *seg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= max_seg || s >= segoff[g.ND]) return;
+  int lo = 0, hi = g.ND - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segoff[mid] <= s)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const int x = off[lo] + (s - segoff[lo]) * kSeg;
+  seg[s] = int2{x, min(x + kSeg, off[lo + 1])};
 }
 
 // --- reverse steps ----------------------------------------------------------
@@ -312,13 +336,6 @@ AdjWs adj_layout(const Geo &g, void *ws) {
 void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
                          hipStream_t st) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_fill_i32n, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0,
-                     st, a.cnt, g.ND + 1, 0);
-  hipLaunchKernelGGL(k_count_domains, dim3((g.R + bs - 1) / bs), dim3(bs), 0,
-                     st, g, domain, a.cnt);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, 1, a.off);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, kSeg,
-                     a.segoff);
   hipLaunchKernelGGL(k_rs_init, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st, g,
                      domain, a.key0, a.val0);
   int bits = 0;
@@ -335,8 +352,12 @@ void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
     std::swap(vin, vout);
   }
   a.list = vin;
-  hipLaunchKernelGGL(k_seg_fill, dim3((g.ND + bs - 1) / bs), dim3(bs), 0, st,
-                     g, a.off, a.segoff, a.seg);
+  hipLaunchKernelGGL(k_bounds, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0, st,
+                     g, kin, a.off, a.cnt);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, kSeg,
+                     a.segoff);
+  hipLaunchKernelGGL(k_seg_fill, dim3((a.max_seg + bs - 1) / bs), dim3(bs), 0,
+                     st, g, a.off, a.segoff, a.max_seg, a.seg);
 }
 
 // The reverse steps, with the table already built.
