@@ -258,6 +258,7 @@ def main():
         ws12 = torch.empty(ws12b + 256, dtype=torch.uint8, device=dev)
         c12 = 8 * R12 * ND12
         o12, ms12, ph12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
+        n_rs12, n_ds12 = F.search_counts(o12, p12)   # ranges / domains with variance
         p12.method = F.METHOD_DIRECT
         o12d, ms12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
         same12 = all(np.array_equal(a, b) for a, b in zip(codes_np(o12).values(), codes_np(o12d).values()))
@@ -265,8 +266,11 @@ def main():
             "workload": "512x512 12-bit slice, 8x8 ranges, 16x16 domains stride 2",
             "candidates": c12, "value": c12 / (ms12 / 1e3), "unit": "comparisons/s",
             "ms_per_step": ms12, "phases_ms": ph12,
-            # four FP16 partial products per searched candidate (hi/lo planes)
-            "mfma_frac": 4 * 2.0 * 64 * c12 / (ph12["search"] / 1e3) / MFMA_FP16_PEAK,
+            # four FP16 partial products per searched candidate (hi/lo planes),
+            # over the sub-table of ranges and domains with variance
+            "ranges_searched": n_rs12, "domains_searched": n_ds12,
+            "mfma_frac": 4 * 2.0 * 64 * 8 * n_rs12 * n_ds12 / (ph12["search"] / 1e3)
+                         / MFMA_FP16_PEAK,
             "direct_value": c12 / (ms12d / 1e3), "mfma_over_direct": ms12d / ms12,
             "codes_identical_mfma_direct": bool(same12)}
 

@@ -111,13 +111,13 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
 
 /*
  * fic_search_counts -- host, synchronous.  After an fic_encode of `p` with
- * the matrix-core method on an 8-bit image has completed on `workspace`,
+ * the matrix-core method has completed on `workspace`,
  * reports how many ranges and how many domains the search visited: those
  * with variance.  A flat range (all pixels equal) ties on every candidate
  * and keeps candidate 0; a flat domain ties with the first flat domain,
  * which code extraction compares (Section V: shadow blocks need no search).
  * Errors: FIC_E_INVALID (null pointers, workspace smaller than fic_query
- * reports), FIC_E_UNSUPPORTED (another method or bit depth), FIC_E_HIP.
+ * reports), FIC_E_UNSUPPORTED (the plain method), FIC_E_HIP.
  */
 int fic_search_counts(const fic_params *p, const void *workspace,
                       size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains);

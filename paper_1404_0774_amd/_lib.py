@@ -219,7 +219,7 @@ def encode(image: torch.Tensor, p: Params, workspace=None):
 
 def search_counts(out, p: Params):
     """(ranges, domains) the search visited in the encode that produced
-    `out` (8-bit, matrix-core method); synchronises the device."""
+    `out` (matrix-core method); synchronises the device."""
     ws, ew = out["_ws_ptr"]
     nr, nd = ctypes.c_int64(), ctypes.c_int64()
     cp = p.c()

@@ -267,9 +267,9 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   // the seed pass ranks the leading column blocks to give every range a
   // starting bound; the search still covers every column block
   const Tune t = resolve_tune(g, p->method);
-  if (p->method == FIC_METHOD_MFMA && g.bits == 8) {
-    // the 8-bit matrix-core search visits only ranges and domains with
-    // variance (lists built here, in order)
+  if (p->method == FIC_METHOD_MFMA) {
+    // the matrix-core searches visit only ranges and domains with variance
+    // (lists built here, in order)
     e = launch_compact(g, b, s);
     if (e != hipSuccess) return hip_fail(e, "compact");
   }
@@ -279,7 +279,8 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   if (p->method == FIC_METHOD_DIRECT)
     e = launch_search_direct(g, b, t.chunks, 0, s);
   else if (g.bits == 12)
-    e = launch_search_mfma12(g, b, t.chunks, 0, s);
+    e = launch_search_mfma12(
+        g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
   else
     e = launch_search_mfma(g, b, image, t.chunks * (g.R_pad / kMfmaRangesPerWG),
                            s);
@@ -299,9 +300,9 @@ int fic_search_counts(const fic_params *p, const void *workspace,
   if (st) return st;
   if (!workspace || !n_ranges || !n_domains)
     return fail(FIC_E_INVALID, "null workspace or output pointer");
-  if (p->method != FIC_METHOD_MFMA || g.bits != 8)
+  if (p->method != FIC_METHOD_MFMA)
     return fail(FIC_E_UNSUPPORTED,
-                "search counts exist for the 8-bit matrix-core method only");
+                "search counts exist for the matrix-core method only");
   const EncLayout L = enc_layout(g);
   if (ws_bytes < L.total)
     return fail(FIC_E_INVALID, "workspace %zu bytes < %zu", ws_bytes, L.total);

@@ -119,8 +119,8 @@ hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
 hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
                               const void *image, int workgroups,
                               hipStream_t st);
-hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
-                                int first_block, hipStream_t st);
+hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
+                                int workgroups, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
                                 int first_block, hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,

@@ -111,37 +111,70 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
   qn = rem;
 }
 
-// grid: (chunks, R_pad / 16); block: 4 waves of 4 ranges each.  Same lane
-// layout as the 8-bit kernel: accumulator v of lane l holds transform v mod 8
-// of range 2 (l / 32) + v / 8 of the wave, for domain column l mod 32.
+// Column ci of the searched list for block cb and lane column cl (-1 past
+// the list).
+__device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
+                                        int cl) {
+  const int j = cb * 32 + cl;
+  return j < nD ? b.act_col[j] : -1;
+}
+
+// A 1-D grid of G workgroups over the searched lists (ranges and domains
+// with variance, built by the compaction; the lengths are read on the
+// device): rows of 16 searched ranges, each split into G / rows chunks of
+// 32-column blocks (at least one).  Block: 4 waves of 4 ranges each.  Same
+// lane layout as the 8-bit kernel: accumulator v of lane l holds transform
+// v mod 8 of range 2 (l / 32) + v / 8 of the wave, for domain column
+// l mod 32.
 template <int K>
-__global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
-                                                           int cb_begin,
-                                                           int cb_end,
-                                                           int cb_per_chunk) {
+__global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
   constexpr int KS = K / 16;
   __shared__ unsigned long long s_best[4][kWR];
   __shared__ double2 s_rstat[4][kWR];
+  __shared__ int s_slot[4][kWR];
   __shared__ QEntry12 s_queue[4][kQueue];
   __shared__ unsigned s_cands[4][8 * 64];
+  const int nA = __builtin_amdgcn_readfirstlane(b.n_act[0]);
+  const int nD = __builtin_amdgcn_readfirstlane(b.n_act[1]);
+  const int rows = (nA + 4 * kWR - 1) / (4 * kWR);
+  const int ncb = (nD + 31) / 32;
+  if (rows == 0 || ncb == 0) return;
+  const int chunks = max(1, min((int)gridDim.x / rows, ncb));
+  const int rg = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+  if (rg >= rows) return;
+  const int cbpc = (ncb + chunks - 1) / chunks;
+  const int c0 = chunk * cbpc, c1 = min(c0 + cbpc, ncb);
+  if (c0 >= c1) return;
+
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int h = lane >> 5;
   const int cl = lane & 31;
-  const int wr0 = blockIdx.y * (4 * kWR) + wave * kWR;
+  const int wr0 = rg * (4 * kWR) + wave * kWR;  // entries of the range list
   unsigned long long *my_best = s_best[wave];
   double2 *rstat = s_rstat[wave];
+  int *slots = s_slot[wave];
   QEntry12 *queue = s_queue[wave];
   unsigned *cands = s_cands[wave];
   int qn = 0;
   const double Kd = (double)g.K;
 
+  // the wave's range slots (-1: none), their keys and sums
   unsigned long long gsnap = ~0ull;
+  int my_slot = -1;
   if (lane < kWR) {
-    gsnap = load_best(&b.best[wr0 + lane]);
+    my_slot = wr0 + lane < nA ? b.act_slot[wr0 + lane] : -1;
+    slots[lane] = my_slot;
+    double sb = 0.0, sbb = 0.0;
+    if (my_slot >= 0) {
+      gsnap = load_best(&b.best[my_slot]);
+      sb = b.rng_sb[my_slot];
+      sbb = b.rng_sbb[my_slot];
+    }
     my_best[lane] = gsnap;
-    rstat[lane] = double2{b.rng_sb[wr0 + lane], b.rng_sbb[wr0 + lane]};
+    rstat[lane] = double2{sb, sbb};
   }
+  __builtin_amdgcn_wave_barrier();
 
   const size_t aplane = (size_t)g.R_pad * 8 * K;
   const size_t bplane = (size_t)g.NC_pad * K;
@@ -150,11 +183,13 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
     const int rho = lane & 31;
     const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
     const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
-    const _Float16 *src = b.aop + ((size_t)(wr0 + rl) * 8 + iso) * K + 8 * h;
+    const int sl = slots[rl];
+    const _Float16 *src =
+        b.aop + ((size_t)(sl >= 0 ? sl : 0) * 8 + iso) * K + 8 * h;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      ah[kk] = *(const half8 *)(src + 16 * kk);
-      al[kk] = *(const half8 *)(src + aplane + 16 * kk);
+      ah[kk] = sl >= 0 ? *(const half8 *)(src + 16 * kk) : half8{};
+      al[kk] = sl >= 0 ? *(const half8 *)(src + aplane + 16 * kk) : half8{};
     }
   }
 
@@ -167,16 +202,15 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
     wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
   }
 
-  const int c0 = cb_begin + blockIdx.x * cb_per_chunk;
-  const int c1 = min(c0 + cb_per_chunk, cb_end);
-  if (c0 >= c1) return;
-
+  // a column past the searched list reads column 0 and is marked flat
+  // (D' = +inf), so it never passes the prune
   half8 bh[KS], bl[KS];
   float csa, cdp;
   int cdom;
   double csaa;
   {
-    const int col = c0 * 32 + cl;
+    const int ci = column12(b, nD, c0, cl);
+    const int col = ci >= 0 ? ci : 0;
     const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
@@ -185,15 +219,19 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
     }
     const float2 sadp = b.col_sadp[col];
     csa = sadp.x;
-    cdp = sadp.y;
+    cdp = ci >= 0 ? sadp.y : __builtin_inff();
     cdom = b.col_dom[col];
     csaa = b.col_saa[col];
   }
+  // column index of the next block, read a block ahead
+  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl) : -1;
 
   for (int cb = c0; cb < c1; ++cb) {
     const int slot = (cb - c0) % kSync;
     half8 bhn[KS], bln[KS];
-    const int ncol = (cb + 1 < c1 ? cb + 1 : cb) * 32 + cl;
+    const int ncol = ci_next >= 0 ? ci_next : 0;
+    const bool nlive = ci_next >= 0;
+    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl) : -1;
     {
       const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
 #pragma unroll
@@ -203,7 +241,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
       }
     }
     const float2 nsadp = b.col_sadp[ncol];
-    const float nsa = nsadp.x, ndp = nsadp.y;
+    const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
     const int ndom = b.col_dom[ncol];
     const double nsaa = b.col_saa[ncol];
 
@@ -287,10 +325,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
       if (cb + 1 == c1 && qn > 0)
         drain12(queue, cands, qn, qn, my_best, rstat, g);
       // publish, then read the global keys and use them at once
-      if (lane < kWR) {
+      if (lane < kWR && my_slot >= 0) {
         const unsigned long long m = my_best[lane];
-        if (m < gsnap) atomicMin(&b.best[wr0 + lane], m);
-        gsnap = load_best(&b.best[wr0 + lane]);
+        if (m < gsnap) atomicMin(&b.best[my_slot], m);
+        gsnap = load_best(&b.best[my_slot]);
         my_best[lane] = min(m, gsnap);
       }
 #pragma unroll
@@ -314,20 +352,13 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b,
 
 }  // namespace
 
-hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b, int chunks,
-                                int first_block, hipStream_t st) {
+hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
+                                int workgroups, hipStream_t st) {
   if (g.bits != 12) return hipErrorInvalidValue;
   static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
-  const int rg = g.R_pad / (4 * kWR);
-  const int rest = g.NCB - first_block;
-  if (rest <= 0) return hipSuccess;
-  if (chunks > rest) chunks = rest;
-  if (chunks < 1) chunks = 1;
-  const int cbpc = (rest + chunks - 1) / chunks;
-  const int nchunks = (rest + cbpc - 1) / cbpc;
+  if (workgroups < 1) workgroups = 1;
   auto kern = g.K == 64 ? k_search_mfma_12<64> : k_search_mfma_12<16>;
-  hipLaunchKernelGGL(kern, dim3(nchunks, rg), dim3(256), 0, st, g, b,
-                     first_block, g.NCB, cbpc);
+  hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b);
   return hipGetLastError();
 }
 

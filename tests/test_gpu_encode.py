@@ -56,13 +56,15 @@ def test_parity_small_images(method, H, W, n, step, seed):
     assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), f"{H}x{W}")
 
 
-def test_search_visits_exactly_the_ranges_and_domains_with_variance():
-    """The 8-bit matrix-core search skips flat ranges and flat domains (their
-    outcome is fixed); the counts it reports match a direct count."""
+@pytest.mark.parametrize("bits", [8, 12])
+def test_search_visits_exactly_the_ranges_and_domains_with_variance(bits):
+    """The matrix-core searches skip flat ranges and flat domains (their
+    outcome is fixed); the counts they report match a direct count."""
     H, W, n, step = 128, 96, 8, 4
-    img = gen_image(H, W, 8, 19)
-    p = F.Params(H, W, 8, n, step)
-    out = F.encode(torch.from_numpy(img).cuda(), p)
+    img = gen_image(H, W, bits, 19)
+    p = F.Params(H, W, bits, n, step)
+    host = img.astype(np.uint8 if bits == 8 else np.int16)
+    out = F.encode(torch.from_numpy(host).cuda(), p)
     nr, nd = F.search_counts(out, p)
     blocks = img.reshape(H // n, n, W // n, n).transpose(0, 2, 1, 3).reshape(-1, n * n)
     want_r = int((blocks.max(1) != blocks.min(1)).sum())
@@ -73,7 +75,8 @@ def test_search_visits_exactly_the_ranges_and_domains_with_variance():
     want_d = sum(int(c.max() != c.min()) for c in cells)
     assert (nr, nd) == (want_r, want_d)
     assert 0 < nr < len(blocks) and 0 < nd < ny * nx   # the image has background
-    assert_same({k: out[k].cpu().numpy() for k in KEYS}, O.encode(img, n, step), "counts image")
+    assert_same({k: out[k].cpu().numpy() for k in KEYS}, O.encode(img, n, step, bits=bits),
+                f"counts image {bits}-bit")
 
 
 def test_unaligned_image_takes_range_operand_path():
