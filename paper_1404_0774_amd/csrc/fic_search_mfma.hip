@@ -634,9 +634,11 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const int c1 = min(w.w, (nD + 31) / 32);
     if (row0 < nA && w.z < c1)
       search_rows<K>(g, b, img, lds, row0, nA, nD, w.z, c1);
+    // (no fence before the count: the completion tick is only a timestamp,
+    // and a device-wide fence compiles to an L2 write-back and invalidate,
+    // once per item)
     __syncthreads();
     if (threadIdx.x == 0) {
-      __threadfence();
       if (atomicSub(&bd.remaining[w.x], 1) == 1)
         bd.ticks[1 + w.x] = (unsigned long long)wall_clock64();
     }
