@@ -186,8 +186,9 @@ __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
   const int c = ci >= 0 ? ci : 0;
   const _Float16 *bsrc = b.bop + (size_t)c * K + 8 * h;
 #pragma unroll
-  for (int kk = 0; kk < K / 16; ++kk) bn[kk] = *(const half8 *)(bsrc + 16 * kk);
-  nsd = b.col_rec[c];
+  for (int kk = 0; kk < K / 16; ++kk) bn[kk] = gld((const half8 *)(bsrc + 16 * kk));
+  // as one 16-byte vector: a struct copy would go through a generic reference
+  nsd = __builtin_bit_cast(ColRec, gld((const u32x4 *)&b.col_rec[c]));
   if (ci < 0) nsd.dp = __builtin_inff();
 }
 
@@ -195,7 +196,7 @@ __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
 __device__ __forceinline__ int column_of(const EncBufs &b, int nD, int cb,
                                          int cl) {
   const int j = cb * 32 + cl;
-  return j < nD ? b.act_col[j] : -1;
+  return j < nD ? gld(&b.act_col[j]) : -1;
 }
 
 // One 32-column block: prefetch the next block's operand and column records
@@ -303,7 +304,7 @@ __device__ __forceinline__ void sweep_block(
       const int sl = w.slots[w.lane];
       if (sl >= 0) {
         const unsigned long long m = w.best[w.lane];
-        if (m < w.gsnap) atomicMin(&b.best[sl], m);
+        if (m < w.gsnap) publish_best(&b.best[sl], m);
         w.gsnap = load_best(&b.best[sl]);
         w.best[w.lane] = min(m, w.gsnap);
       }
@@ -414,7 +415,7 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     }
     // share it with the other chunks of these ranges right away
     const int sl = w.slots[lr];
-    if (sl >= 0 && w.best[lr] < w.gsnap) atomicMin(&b.best[sl], w.best[lr]);
+    if (sl >= 0 && w.best[lr] < w.gsnap) publish_best(&b.best[sl], w.best[lr]);
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -458,8 +459,8 @@ __device__ __forceinline__ void range_fragments_from_pixels(
     if (ri < g.R) {
       const uint8_t *p =
           img + (size_t)((ri / g.RW) * 8 + i0) * g.W + (size_t)(ri % g.RW) * 8;
-      r0 = *(const uint2 *)p;
-      r1 = *(const uint2 *)(p + g.W);
+      r0 = __builtin_bit_cast(uint2, gld((const u32x2 *)p));
+      r1 = __builtin_bit_cast(uint2, gld((const u32x2 *)(p + g.W)));
     }
     rows[lr * 8 + i0] = r0;
     rows[lr * 8 + i0 + 1] = r1;
@@ -533,13 +534,13 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   // the wave's range slots, their keys and sums; the first two columns
   if (w.lane < kWaveRanges) {
     const int j = w.wr0 + w.lane;
-    const int sl = j < nA ? b.act_slot[j] : -1;
+    const int sl = j < nA ? gld(&b.act_slot[j]) : -1;
     w.slots[w.lane] = sl;
     double sb = 0.0, sbb = 0.0;
     if (sl >= 0) {
       w.gsnap = load_best(&b.best[sl]);
-      sb = b.rng_sb[sl];
-      sbb = b.rng_sbb[sl];
+      sb = gld(&b.rng_sb[sl]);
+      sbb = gld(&b.rng_sbb[sl]);
     }
     w.best[w.lane] = w.gsnap;
     w.rstat[w.lane] = double2{sb, sbb};
@@ -566,7 +567,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
           b.aop + ((size_t)(sl >= 0 ? sl : 0) * 8 + iso) * K + 8 * w.h;
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk)
-        af[rb][kk] = sl >= 0 ? *(const half8 *)(src + 16 * kk) : half8{};
+        af[rb][kk] = sl >= 0 ? gld((const half8 *)(src + 16 * kk)) : half8{};
     }
   }
   // per lane: wave ranges 4 rb + 2 h + e for slot s = 2 rb + e
@@ -628,8 +629,8 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const uint8_t *img =
         g.pix_a ? (const uint8_t *)load_uniform(&bd.tab[w.x].image) : nullptr;
     // the item's row and blocks within the slice's searched lists
-    const int nA = __builtin_amdgcn_readfirstlane(b.n_act[0]);
-    const int nD = __builtin_amdgcn_readfirstlane(b.n_act[1]);
+    const int nA = __builtin_amdgcn_readfirstlane(gld(&b.n_act[0]));
+    const int nD = __builtin_amdgcn_readfirstlane(gld(&b.n_act[1]));
     const int row0 = w.y * kMfmaRangesPerWG;
     const int c1 = min(w.w, (nD + 31) / 32);
     if (row0 < nA && w.z < c1)
