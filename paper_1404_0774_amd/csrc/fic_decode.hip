@@ -176,14 +176,14 @@ __global__ void k_seg_fill(Geo g, const int32_t *off, const int32_t *segoff,
 // ranges): dL/ds and dL/do of step t summed over the range by a fixed
 // butterfly (first = true overwrites the outputs).
 template <int N>
-__global__ __launch_bounds__(256) void k_grad_so(Geo g, const int32_t *domain,
-                                                 const uint8_t *iso,
-                                                 const float *x,
-                                                 const float *gnext,
-                                                 float *grad_s, float *grad_o,
-                                                 int first) {
+__device__ __forceinline__ void grad_so_body(Geo g, const int32_t *domain,
+                                             const uint8_t *iso,
+                                             const float *x,
+                                             const float *gnext,
+                                             float *grad_s, float *grad_o,
+                                             int first, int bid) {
   constexpr int K = N * N;
-  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long tid = (long long)bid * blockDim.x + threadIdx.x;
   const int r = (int)(tid / K), pix = (int)(tid % K);
   const bool live = r < g.R;
   float as = 0.0f, ao = 0.0f;
@@ -222,11 +222,12 @@ __global__ __launch_bounds__(256) void k_grad_so(Geo g, const int32_t *domain,
 // in three independent batches (list, codes, gradient) before the ordered
 // sum, so a thread waits for three memory round trips, not 3 kSeg.
 template <int N>
-__global__ __launch_bounds__(256) void k_seg_partial(
+__device__ __forceinline__ void seg_partial_body(
     Geo g, const int32_t *nseg, const int2 *seg, const int32_t *list,
-    const uint8_t *iso, const float *s, const float *gnext, float *partial) {
+    const uint8_t *iso, const float *s, const float *gnext, float *partial,
+    int bid) {
   constexpr int K = N * N;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = bid * blockDim.x + threadIdx.x;
   const int sg = tid / K, c = tid % K, ci = c / N, cj = c % N;
   if (sg >= *nseg) return;
   const int2 be = seg[sg];
@@ -253,6 +254,22 @@ __global__ __launch_bounds__(256) void k_seg_partial(
   for (int u = 0; u < kSeg; ++u)
     if (rr[u] >= 0) acc = fmaf(w[u], gv[u], acc);
   partial[tid] = acc;
+}
+
+// One launch for the two independent parts of a reverse step: workgroups
+// [0, nb_so) form dL/ds and dL/do, the rest (if any) the segment partials.
+template <int N>
+__global__ __launch_bounds__(256) void k_adj_step(
+    Geo g, const int32_t *domain, const uint8_t *iso, const float *x,
+    const float *gnext, float *grad_s, float *grad_o, int first, int nb_so,
+    const int32_t *nseg, const int2 *seg, const int32_t *list, const float *s,
+    float *partial) {
+  if ((int)blockIdx.x < nb_so)
+    grad_so_body<N>(g, domain, iso, x, gnext, grad_s, grad_o, first,
+                    blockIdx.x);
+  else
+    seg_partial_body<N>(g, nseg, seg, list, iso, s, gnext, partial,
+                        blockIdx.x - nb_so);
 }
 
 // One thread per pixel q: g_t[q] = sum of the segment partials of the
@@ -373,15 +390,16 @@ void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
   for (int t = iters - 1; t >= 0; --t) {
     const float *x = traj + (size_t)t * HW;
     const long long nso = (long long)g.R * N * N;
-    hipLaunchKernelGGL((k_grad_so<N>), dim3((unsigned)((nso + bs - 1) / bs)),
+    const int nb_so = (int)((nso + bs - 1) / bs);
+    // the segment partials feed g_t, needed only while t > 0
+    const long long np = t > 0 ? (long long)a.max_seg * N * N : 0;
+    const int nb_sp = (int)((np + bs - 1) / bs);
+    hipLaunchKernelGGL((k_adj_step<N>), dim3((unsigned)(nb_so + nb_sp)),
                        dim3(bs), 0, st, g, domain, iso, x, gnext, grad_s,
-                       grad_o, t == iters - 1 ? 1 : 0);
+                       grad_o, t == iters - 1 ? 1 : 0, nb_so,
+                       a.segoff + g.ND, a.seg, a.list, s, a.partial);
     if (t > 0) {
       float *gout = bufs[t & 1];
-      const long long np = (long long)a.max_seg * N * N;
-      hipLaunchKernelGGL((k_seg_partial<N>), dim3((unsigned)((np + bs - 1) / bs)),
-                         dim3(bs), 0, st, g, a.segoff + g.ND, a.seg, a.list, iso, s,
-                         gnext, a.partial);
       hipLaunchKernelGGL((k_grad_x<N>), dim3((HW + bs - 1) / bs), dim3(bs), 0,
                          st, g, a.segoff, a.partial, gout);
       gnext = gout;
