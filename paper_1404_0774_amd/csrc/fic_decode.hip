@@ -57,7 +57,8 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 
 // --- the domain -> ranges table --------------------------------------------
 
-constexpr int kSeg = 16;  // ranges per list segment
+constexpr int kSeg = 16;     // ranges per list segment
+constexpr int kGather = 32;  // segment partials loaded per round
 
 // Number of entries of the sorted keys key[0 .. n) below v.
 __device__ __forceinline__ int lower_bound(const int32_t *key, int n, int v) {
@@ -273,7 +274,9 @@ __global__ __launch_bounds__(256) void k_adj_step(
 }
 
 // One thread per pixel q: g_t[q] = sum of the segment partials of the
-// cells containing q, over the domains covering q (loads batched by 8).
+// cells containing q, over the domains covering q (loads batched by
+// kGather: a domain shared by a thousand flat ranges has ~100 segments, and
+// the pixels it covers would otherwise wait for ~13 rounds of loads).
 template <int N>
 __global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
                                                 const float *partial,
@@ -294,13 +297,13 @@ __global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
       const int d = dy * g.NX + dx;
       const int s0 = segoff[d], s1 = segoff[d + 1];
       const int cell = ((qy - dy * g.step) >> 1) * N + ((qx - dx * g.step) >> 1);
-      for (int sb = s0; sb < s1; sb += 8) {
-        float v[8];
+      for (int sb = s0; sb < s1; sb += kGather) {
+        float v[kGather];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kGather; ++u)
           v[u] = sb + u < s1 ? partial[(size_t)(sb + u) * K + cell] : 0.0f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
+        for (int u = 0; u < kGather; ++u)
           if (sb + u < s1) acc += v[u];
       }
     }
