@@ -393,32 +393,49 @@ hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
 
 // Ordered compaction of the indices whose flag byte is 1, for two flag
 // arrays at once (lengths multiples of 16), by one workgroup of 1024
-// threads.  Thread t owns a contiguous run of 16-byte words of each array
-// and counts it with one popcount per word; a shuffle scan inside each wave
-// and one pass over the 16 wave totals in LDS give every thread its output
-// position, and it writes its selected indices in order.
-__device__ __forceinline__ void count_words(const uint8_t *flag, int w0,
-                                            int w1, int &c) {
-  const uint4 *fw = (const uint4 *)flag;
-  c = 0;
-  for (int i = w0; i < w1; ++i) {
-    const uint4 v = fw[i];  // 16 flags of 0 or 1
-    c += __builtin_popcount(v.x) + __builtin_popcount(v.y) +
-         __builtin_popcount(v.z) + __builtin_popcount(v.w);
-  }
+// threads.  Wave w owns a contiguous stretch of each array, a multiple of
+// 256 flags long.  In rounds of 256 flags, lane l reads flags 4l .. 4l + 3
+// as one 32-bit word; one ballot per byte position gives every set flag its
+// rank (set flags in lower lanes: the sum of the four ballots' mbcnt; in the
+// lane itself: the set bytes below it), so each round's stores land next to
+// each other.  A first pass counts each wave's flags, the 16 totals are
+// exchanged in LDS, and a second pass writes.
+__device__ __forceinline__ unsigned flag_bits(const uint8_t *flag, int i,
+                                              int end) {
+  // bit e: flag i + e (i a multiple of 4, end a multiple of 16)
+  const unsigned u = i < end ? *(const unsigned *)(flag + i) : 0u;
+  return (u & 1u) | ((u >> 7) & 2u) | ((u >> 14) & 4u) | ((u >> 21) & 8u);
 }
 
-__device__ __forceinline__ void write_selected(const uint8_t *flag, int w0,
-                                               int w1, int pos, int32_t *out) {
-  const uint4 *fw = (const uint4 *)flag;
-  for (int i = w0; i < w1; ++i) {
-    const uint4 v = fw[i];
-    const unsigned u[4] = {v.x, v.y, v.z, v.w};
+__device__ __forceinline__ int wave_count(const uint8_t *flag, int beg,
+                                          int end, int lane) {
+  int c = 0;
+  for (int b = beg; b < end; b += 256)
+    c += __builtin_popcount(flag_bits(flag, b + 4 * lane, end));
+  // lanes hold partial counts: sum over the wave
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  return c;
+}
+
+__device__ __forceinline__ void wave_write(const uint8_t *flag, int beg,
+                                           int end, int lane, int pos,
+                                           int32_t *out) {
+  for (int b = beg; b < end; b += 256) {
+    const int i = b + 4 * lane;
+    const unsigned bits = flag_bits(flag, i, end);
+    int below = 0, total = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int e = 0; e < 4; ++e) {
+      const unsigned long long m = __builtin_amdgcn_ballot_w64((bits >> e) & 1u);
+      below += __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+      total += __popcll(m);
+    }
+    int at = pos + below;
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if ((u[q] >> (8 * e)) & 1u) out[pos++] = 16 * i + 4 * q + e;
+    for (int e = 0; e < 4; ++e)
+      if ((bits >> e) & 1u) out[at++] = i + e;
+    pos += total;
   }
 }
 
@@ -427,24 +444,15 @@ __device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
                                                const uint8_t *f1, int32_t *o1,
                                                int32_t *count) {
   __shared__ int2 wtot[16];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int p0 = (n0 / 16 + 1023) / 1024, p1 = (n1 / 16 + 1023) / 1024;
-  const int a0 = min(t * p0, n0 / 16), a1 = min(a0 + p0, n0 / 16);
-  const int b0 = min(t * p1, n1 / 16), b1 = min(b0 + p1, n1 / 16);
-  int c0, c1;
-  count_words(f0, a0, a1, c0);
-  count_words(f1, b0, b1, c1);
-  // inclusive scan over the wave
-  int s0 = c0, s1 = c1;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const int u0 = __shfl_up(s0, o), u1 = __shfl_up(s1, o);
-    if (lane >= o) {
-      s0 += u0;
-      s1 += u1;
-    }
-  }
-  if (lane == 63) wtot[wave] = int2{s0, s1};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // each wave's stretch: whole rounds of 256 flags
+  const int s0 = (n0 + 16 * 256 - 1) / (16 * 256) * 256;
+  const int s1 = (n1 + 16 * 256 - 1) / (16 * 256) * 256;
+  const int a0 = min(wave * s0, n0), a1 = min(a0 + s0, n0);
+  const int b0 = min(wave * s1, n1), b1 = min(b0 + s1, n1);
+  const int c0 = wave_count(f0, a0, a1, lane);
+  const int c1 = wave_count(f1, b0, b1, lane);
+  if (lane == 0) wtot[wave] = int2{c0, c1};
   __syncthreads();
   int q0 = 0, q1 = 0, t0 = 0, t1 = 0;
   for (int w = 0; w < 16; ++w) {
@@ -456,9 +464,9 @@ __device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
     t0 += v.x;
     t1 += v.y;
   }
-  write_selected(f0, a0, a1, q0 + s0 - c0, o0);
-  write_selected(f1, b0, b1, q1 + s1 - c1, o1);
-  if (t == 0) {
+  wave_write(f0, a0, a1, lane, q0, o0);
+  wave_write(f1, b0, b1, lane, q1, o1);
+  if (threadIdx.x == 0) {
     count[0] = t0;
     count[1] = t1;
   }
