@@ -207,7 +207,9 @@ int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
 /*
  * Launch-shape tuning (host only; no GPU work).  The search grid splits the
  * candidate table of eq. (8) into row groups of ranges and column chunks of
- * domains; these entries choose how many chunks, how many leading 32-column
+ * domains; these entries choose how many chunks (the matrix-core searches
+ * launch col_chunks workgroups per row group of all ranges and spread them
+ * over the row groups of the ranges they search), how many leading 32-column
  * blocks a seed pass ranks first to give each range a starting bound (the
  * search still covers every block; the 8-bit, n = 8 matrix-core search seeds
  * itself and always resolves this to 0), and how many
@@ -248,12 +250,13 @@ int fic_get_tuning(const fic_params *p, fic_tuning *out);
 /*
  * Benchmark support (not needed to encode).  fic_timing_begin enables and
  * resets phase timing: while enabled, every fic_encode records HIP events on
- * its own stream before operand preparation, before the seeding pass, before
- * the search, before code extraction and at its end (the most recent 256
- * calls are kept).  fic_timing_end waits for those events, returns the number
- * of timed calls and the summed milliseconds of each phase (the search phase
- * is the one search kernel launch), and disables timing.  Not
- * thread-safe: meant for a single benchmarking thread.  Errors: FIC_E_HIP
+ * its own stream before operand preparation, before the list compaction and
+ * seeding pass, before the search, before code extraction and at its end
+ * (the most recent 256 calls are kept).  fic_timing_end waits for those
+ * events, returns the number of timed calls and the summed milliseconds of
+ * each phase (the search phase is the one search kernel launch), and
+ * disables timing.  Not thread-safe: meant for a single benchmarking
+ * thread.  Errors: FIC_E_HIP
  * (event creation or query failed), FIC_E_INVALID (end without begin).
  */
 int fic_timing_begin(void);
