@@ -273,10 +273,15 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
                                               EncBufs b) {
-  if ((int)blockIdx.x < g.n_dwg)
+  if ((int)blockIdx.x < g.n_dwg) {
     prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
-  else
+  } else if (g.pix_a) {
+    // a row per lane when only statistics are needed, a pixel per lane when
+    // the range operand is written as well (its scattered stores spread)
+    prep_ranges_body<Pix, N, N>(g, img, b, blockIdx.x - g.n_dwg);
+  } else {
     prep_ranges_body<Pix, N, N * N>(g, img, b, blockIdx.x - g.n_dwg);
+  }
 }
 
 // One group of L lanes per range (L = N or K = N^2), each lane holding K / L
@@ -382,7 +387,8 @@ __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
 template <typename Pix>
 hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
                      hipStream_t st) {
-  const long long rwg = ((long long)g.R_pad * g.K + 255) / 256;
+  const long long lanes = g.pix_a ? g.n : g.K;  // per range, as k_prep
+  const long long rwg = ((long long)g.R_pad * lanes + 255) / 256;
   const dim3 grid((unsigned)(g.n_dwg + rwg));
   if (g.n == 8)
     hipLaunchKernelGGL((k_prep<Pix, 8>), grid, dim3(256), 0, st, g, img, b);
