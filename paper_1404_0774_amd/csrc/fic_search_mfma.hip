@@ -67,13 +67,12 @@ __device__ __forceinline__ bool pair_passes(float gmx, float gmn, float csa,
   return mm * mm >= wp * cdp;
 }
 
-// Reload the lane's 8 prune weights.  Lane l < 16 computes the weight of
-// wave range l once and stores it at wtab[h][s] (range 4 (s / 2) + 2 h +
-// s mod 2); every lane then reads the 8 weights of its half-wave h.
-__device__ __forceinline__ void refresh_weights(float *wp,
-                                                const unsigned long long *best,
+// Recompute the prune weights: lane l < 16 computes the weight of wave
+// range l once and stores it at wtab[h][s] (range 4 (s / 2) + 2 h + s mod 2,
+// the layout of a lane's 8 slots); the sweep reads its 8 from LDS.
+__device__ __forceinline__ void refresh_weights(const unsigned long long *best,
                                                 const double2 *rstat,
-                                                float *wtab, int h, int lane,
+                                                float *wtab, int lane,
                                                 const Geo &g) {
   if (lane < kWaveRanges) {
     const double2 rs = rstat[lane];
@@ -82,10 +81,15 @@ __device__ __forceinline__ void refresh_weights(float *wp,
     wtab[((lane >> 1) & 1) * kSlots + 2 * (lane >> 2) + (lane & 1)] = wv;
   }
   __builtin_amdgcn_wave_barrier();
-  const float4 *wt = (const float4 *)(wtab + h * kSlots);
-  const float4 w0 = wt[0], w1 = wt[1];
-  wp[0] = w0.x; wp[1] = w0.y; wp[2] = w0.z; wp[3] = w0.w;
-  wp[4] = w1.x; wp[5] = w1.y; wp[6] = w1.z; wp[7] = w1.w;
+}
+
+// The 8 values of a lane's half h from a [2][kSlots] LDS table.
+__device__ __forceinline__ void read_slots(const float *tab, int h,
+                                           float (&v)[kSlots]) {
+  const float4 *t = (const float4 *)(tab + h * kSlots);
+  const float4 a = t[0], c = t[1];
+  v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+  v[4] = c.x; v[5] = c.y; v[6] = c.z; v[7] = c.w;
 }
 
 // Process the first n queued pairs (64 per round, one per lane): re-test
@@ -170,6 +174,7 @@ struct WaveState {
   QEntry *queue;             // LDS: queued pairs
   Cand *cands;               // LDS: drain candidates
   float *wtab;               // LDS: prune weights [2][kSlots]
+  float *btab;               // LDS: range means Sb / K [2][kSlots]
   int *slots;                // LDS: range slot of each wave range (-1: none)
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
@@ -205,10 +210,13 @@ __device__ __forceinline__ int column_of(const EncBufs &b, int nD, int cb,
 template <int K>
 __device__ __forceinline__ void sweep_block(
     const Geo &g, const EncBufs &b, WaveState &w, const half8 (&af)[kRB][K / 16],
-    float (&wp)[kSlots], const float (&bbar)[kSlots], const half8 (&bf)[K / 16],
-    const ColRec &sd, half8 (&bn)[K / 16], ColRec &nsd, int cb, int c0,
-    int c1) {
+    const half8 (&bf)[K / 16], const ColRec &sd, half8 (&bn)[K / 16],
+    ColRec &nsd, int cb, int c0, int c1) {
   constexpr int KS = K / 16;
+  // the lane's 8 prune weights and range means, kept in LDS between blocks
+  float wp[kSlots], bbar[kSlots];
+  read_slots(w.wtab, w.h, wp);
+  read_slots(w.btab, w.h, bbar);
   const int slot = (cb - c0) % kSync;
   {
     // the next block (its column index came a block earlier) and the index
@@ -288,7 +296,7 @@ __device__ __forceinline__ void sweep_block(
           drained = true;
         }
       }
-    if (drained) refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
+    if (drained) refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   }
 
   const int jn = cb - c0 + 1;  // blocks done in this chunk
@@ -309,7 +317,7 @@ __device__ __forceinline__ void sweep_block(
         w.best[w.lane] = min(m, w.gsnap);
       }
     }
-    refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
+    refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   }
 }
 
@@ -438,6 +446,7 @@ struct SearchLds {
   QEntry queue[4][kQueue];
   Cand cands[4][8 * 64];
   float wtab[4][2 * kSlots];
+  float btab[4][2 * kSlots];
   int slots[4][kWaveRanges];
 };
 
@@ -525,6 +534,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.queue = lds.queue[wave];
   w.cands = lds.cands[wave];
   w.wtab = lds.wtab[wave];
+  w.btab = lds.btab[wave];
   w.slots = lds.slots[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
@@ -570,19 +580,22 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
         af[rb][kk] = sl >= 0 ? gld((const half8 *)(src + 16 * kk)) : half8{};
     }
   }
-  // per lane: wave ranges 4 rb + 2 h + e for slot s = 2 rb + e
-  float wp[kSlots], bbar[kSlots];
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s)
-    bbar[s] = (float)(w.rstat[4 * (s >> 1) + 2 * w.h + (s & 1)].x * g.invK);
-  refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
-
-  seed_blocks<K>(g, b, w, af, bbar, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
-  refresh_weights(wp, w.best, w.rstat, w.wtab, w.h, w.lane, g);
+  // per lane: wave ranges 4 rb + 2 h + e for slot s = 2 rb + e; the range
+  // means go to LDS in the weights' layout
+  if (w.lane < kWaveRanges)
+    w.btab[((w.lane >> 1) & 1) * kSlots + 2 * (w.lane >> 2) + (w.lane & 1)] =
+        (float)(w.rstat[w.lane].x * g.invK);
+  __builtin_amdgcn_wave_barrier();
+  {
+    float bbar[kSlots];
+    read_slots(w.btab, w.h, bbar);
+    seed_blocks<K>(g, b, w, af, bbar, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
+  }
+  refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
-    sweep_block<K>(g, b, w, af, wp, bbar, bA, sdA, bB, sdB, cb, c0, c1);
+    sweep_block<K>(g, b, w, af, bA, sdA, bB, sdB, cb, c0, c1);
     if (cb + 1 < c1)
-      sweep_block<K>(g, b, w, af, wp, bbar, bB, sdB, bA, sdA, cb + 1, c0, c1);
+      sweep_block<K>(g, b, w, af, bB, sdB, bA, sdA, cb + 1, c0, c1);
   }
 }
 
