@@ -328,7 +328,7 @@ __device__ __forceinline__ void sweep_block(
 // (the empty candidate and queue buffers) and lane l < 16 picks range l's
 // best and fits that one candidate exactly.  Any candidate's exact residual
 // is a valid bound; the sweep then covers these blocks as usual.
-constexpr int kSeedBlocks = 2;
+constexpr int kSeedBlocks = 1;
 
 template <int K>
 __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
