@@ -1,13 +1,18 @@
 """Benchmark of the PIFS range-domain search on one MI355X.
 
 A step is one fic_encode of a 512x512 8-bit synthetic slice with 8x8 ranges
-and 16x16 domains at stride 4 (4096 ranges x 15,625 domains x 8 transforms =
-5.12e8 candidate comparisons): operand preparation, the dense seed block, the
-matrix-core search with its fused fit/quantise/residual epilogue, and code
-extraction, with the image already resident in HBM.  Secondary fields cover
-the plain (direct) kernel on the same slice, the 512x512 12-bit slice at
-stride 2, and the 256x256 decode workload (decoder, adjoint, refinement).
-Prints one JSON line.
+and 16x16 domains at stride 4, every range against every domain under the 8
+transforms (4096 x 15,625 x 8 = 5.12e8 candidates, each through the FP16
+contraction and the least-squares test): operand preparation, the search
+with its fused fit/quantise/residual epilogue, and code extraction, with the
+image already resident in HBM.  `value` is those candidates per second.
+
+Secondary fields: the same slice with the shadow-block skip (flat ranges and
+domains left out; its own evaluated count), the plain (direct) kernel on
+identical work in both modes, the 512x512 12-bit slice at stride 2, the
+paper's own workload shape (4x4 ranges) at its three image sizes beside its
+Table III, the 256x256 decode workload (decoder, adjoint, refinement), the
+64-slice batch, and the CPU oracle.  Prints one JSON line.
 """
 import argparse
 import csv
@@ -149,13 +154,60 @@ def codes_np(out):
     return {k: out[k].cpu().numpy() for k in ("domain", "iso", "s_idx", "o_idx", "err")}
 
 
+# Table III of the paper: encode times of its own CUDA kernel and of a
+# sequential CPU program, 4x4 ranges and 8x8 domains on a 4-pixel grid with
+# the eight transforms, on its medical scans (not available here).  The units
+# are not printed; seconds is the reading under which the GPU figures stay
+# below that card's peak.
+PAPER_TABLE3 = {
+    "source": "Table III (encode time, CPU vs GPU; size reduction 40-41 %)",
+    "gpu": "Fermi-class, compute capability 2.0, 16 SM x 32 = 512 cores at 1.30 GHz, 4 GB, CUDA 5.0",
+    "cpu": "2.30 GHz, 64 KB L1D, 512 KB L2, 2 GB RAM, sequential program",
+    "rows": [{"side": 256, "cpu_s": 247.432, "gpu_s": 0.232},
+             {"side": 512, "cpu_s": 2369.4, "gpu_s": 3.521},
+             {"side": 1024, "cpu_s": 39276.5, "gpu_s": 45.407}],
+}
+
+
+def mean_ms(torch, dev, fn, reps, warmup=2):
+    """Mean milliseconds of fn() over `reps` back-to-back calls (events on
+    the current stream around the whole run)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize(dev)
+    return e0.elapsed_time(e1) / reps
+
+
+def encode_line(F, torch, timg, p, ws, steps, warmup, k_flop):
+    """One encode workload: codes, ms per call, phase split, the searched
+    sub-table and the search kernel's achieved FLOP rate (k_flop FP16 MFMA
+    FLOP per evaluated candidate; 0 for the plain method)."""
+    out, ms, ph = time_encode(F, torch, timg, p, ws, steps, warmup)
+    n_rs, n_ds = F.search_counts(out, p)
+    ev = 8 * n_rs * n_ds
+    line = {"ms_per_step": ms, "phases_ms": ph, "steps": steps,
+            "ranges_searched": n_rs, "domains_searched": n_ds,
+            "candidates_evaluated": ev, "evaluated_per_s": ev / (ms / 1e3)}
+    if k_flop:
+        line["search_tflops"] = k_flop * ev / (ph["search"] / 1e3) / 1e12
+        line["search_mfma_frac"] = k_flop * ev / (ph["search"] / 1e3) / MFMA_FP16_PEAK
+    return out, line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline workload (full search, matrix cores)")
     ap.add_argument("--cpu-sample", type=int, default=4096, help="ranges timed on the CPU oracle")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic summary of two rocprofv3 --pmc runs and exit")
@@ -185,41 +237,27 @@ def main():
     dev = torch.device("cuda:0")
     t_wall0 = time.time()
 
-    # ---- headline: 512x512 u8, n = 8, stride 4 -------------------------------
+    # ---- headline: 512x512 u8, n = 8, stride 4, every candidate searched ------
     H = W = 512
     n, step, bits = 8, 4, 8
     img = gen_image(H, W, bits, 2)
     timg = torch.from_numpy(img).to(dev)
-    p = F.Params(H, W, bits, n, step, method=F.METHOD_MFMA)
+    p = F.Params(H, W, bits, n, step, method=F.METHOD_MFMA, full_search=1)
     R, ND, ws_bytes, _ = F.query(p)
     cand = 8 * R * ND
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device=dev)
+    kf = 2.0 * n * n   # FP16 MFMA FLOP per candidate (one K-long inner product)
 
-    out_m, ms_m, ph_m = time_encode(F, torch, timg, p, ws, args.steps, args.warmup)
+    out_m, full_m = encode_line(F, torch, timg, p, ws, args.steps, args.warmup, kf)
+    assert full_m["candidates_evaluated"] == cand, "full search must visit every candidate"
     codes_m = codes_np(out_m)
-    # the search kernel visits ranges and domains with variance only (flat
-    # ones have fixed outcomes): its algorithmic work is that sub-table
-    n_rs, n_ds = F.search_counts(out_m, p)
-    cand_search = 8 * n_rs * n_ds
-    flops = 2.0 * n * n * cand_search
-    p.method = F.METHOD_DIRECT
-    dsteps = max(2, args.steps // 4)
-    out_d, ms_d, ph_d = time_encode(F, torch, timg, p, ws, dsteps, 1)
-    codes_d = codes_np(out_d)
-    same = all(np.array_equal(codes_m[k], codes_d[k]) for k in codes_m)
-
-    p.method = F.METHOD_MFMA
-    s, o = F.dequantize(out_m["s_idx"], out_m["o_idx"], p)
-    traj = F.decode(out_m["domain"], out_m["iso"], s.contiguous(), o.contiguous(), p, 12, 128.0)
-    x = traj[-1].double().cpu().numpy()
-    ref = img.astype(np.float64)
-
-    value = cand / (ms_m / 1e3)
-    achieved = flops / (ph_m["search"] / 1e3)
+    ms_m = full_m["ms_per_step"]
+    flops = kf * cand
+    achieved = flops / (full_m["phases_ms"]["search"] / 1e3)
     traffic = read_traffic()
     result = {
         "metric": "range-domain comparisons/s (MFMA GEMM vs direct) at bit-exact codes; decode PSNR",
-        "value": value,
+        "value": cand / (ms_m / 1e3),
         "unit": "comparisons/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -230,86 +268,132 @@ def main():
         "vs_baseline": None,
         "dtype": "fp16",
         "data": "synthetic",
-        "config": {"workload": "u8_512: 512x512 uint8 slice, 8x8 ranges, 16x16 domains stride 4",
+        "config": {"workload": "u8_512: 512x512 uint8 slice, 8x8 ranges, 16x16 domains stride 4, "
+                               "every range against every domain (full search)",
                    "ranges": R, "domains": ND, "candidates": cand, "seed": 2},
-        "phases_ms": ph_m,
+        "phases_ms": full_m["phases_ms"],
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": MFMA_FP16_PEAK / 1e12,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_FP16_PEAK,
                      "traffic": None if traffic is None else traffic["fetch"] + traffic["write"],
                      "kernel": SEARCH_KERNEL, "flop_per_launch": flops,
-                     "candidates_per_launch": cand_search,
-                     "ranges_searched": n_rs, "domains_searched": n_ds,
-                     "note": "flat ranges and domains have fixed outcomes and are not "
-                             "visited; value counts the whole candidate table"},
-        "direct": {"value": cand / (ms_d / 1e3), "ms_per_step": ms_d, "phases_ms": ph_d,
-                   "steps": dsteps},
-        "mfma_over_direct": ms_d / ms_m,
-        "codes_identical_mfma_direct": bool(same),
-        "decode_psnr_db": {"T": 12, "unclamped": psnr(x, ref, 255.0),
-                           "clamped_rounded": psnr(np.clip(np.rint(x), 0, 255), ref, 255.0)},
+                     "candidates_per_launch": cand,
+                     "note": "every (range, domain, transform) candidate goes through the FP16 "
+                             "contraction and the least-squares test: 128 FLOP each"},
     }
 
     if not args.no_extras:
+        # the same slice with the shadow-block skip: flat ranges and domains
+        # have fixed outcomes and are left out of the contraction
+        p.full_search = 0
+        out_s, skip_m = encode_line(F, torch, timg, p, ws, args.steps, args.warmup, kf)
+        same_skip = all(np.array_equal(codes_np(out_s)[k], codes_m[k]) for k in codes_m)
+        # the plain method on identical work, in both modes
+        p.method = F.METHOD_DIRECT
+        dsteps = max(2, args.steps // 4)
+        p.full_search = 1
+        out_d, full_d = encode_line(F, torch, timg, p, ws, dsteps, 1, 0)
+        p.full_search = 0
+        out_ds, skip_d = encode_line(F, torch, timg, p, ws, dsteps, 1, 0)
+        same_d = all(np.array_equal(codes_np(o)[k], codes_m[k]) for o in (out_d, out_ds)
+                     for k in codes_m)
+        result["skip_flat"] = dict(skip_m, note="ranges and domains without variance left out "
+                                   "(their outcome is fixed); value = evaluated candidates / s",
+                                   codes_identical_to_full=bool(same_skip))
+        result["direct"] = {"full": full_d, "skip_flat": skip_d}
+        result["mfma_over_direct"] = full_d["ms_per_step"] / ms_m
+        result["mfma_over_direct_skip_flat"] = skip_d["ms_per_step"] / skip_m["ms_per_step"]
+        result["mfma_over_direct_search_kernel"] = (full_d["phases_ms"]["search"]
+                                                    / full_m["phases_ms"]["search"])
+        result["codes_identical_mfma_direct"] = bool(same_d)
+        p.method, p.full_search = F.METHOD_MFMA, 1
+
+        s, o = F.dequantize(out_m["s_idx"], out_m["o_idx"], p)
+        traj = F.decode(out_m["domain"], out_m["iso"], s.contiguous(), o.contiguous(), p, 12, 128.0)
+        x = traj[-1].double().cpu().numpy()
+        ref = img.astype(np.float64)
+        result["decode_psnr_db"] = {"T": 12, "unclamped": psnr(x, ref, 255.0),
+                                    "clamped_rounded": psnr(np.clip(np.rint(x), 0, 255), ref, 255.0)}
+
         # ---- 512x512 12-bit, n = 8, stride 2 ------------------------------------
         img12 = gen_image(512, 512, 12, 3)
         t12 = torch.from_numpy(img12.astype(np.int16)).to(dev)
-        p12 = F.Params(512, 512, 12, 8, 2, method=F.METHOD_MFMA)
+        p12 = F.Params(512, 512, 12, 8, 2, method=F.METHOD_MFMA, full_search=1)
         R12, ND12, ws12b, _ = F.query(p12)
         ws12 = torch.empty(ws12b + 256, dtype=torch.uint8, device=dev)
         c12 = 8 * R12 * ND12
-        o12, ms12, ph12 = time_encode(F, torch, t12, p12, ws12, max(3, args.steps // 4), 2)
-        n_rs12, n_ds12 = F.search_counts(o12, p12)   # ranges / domains with variance
-        p12.method = F.METHOD_DIRECT
-        o12d, ms12d, _ = time_encode(F, torch, t12, p12, ws12, 2, 1)
-        same12 = all(np.array_equal(a, b) for a, b in zip(codes_np(o12).values(), codes_np(o12d).values()))
+        kf12 = 4 * 2.0 * 64   # four FP16 partial products (hi/lo planes) per candidate
+        st12 = max(3, args.steps // 4)
+        o12, full12 = encode_line(F, torch, t12, p12, ws12, st12, 2, kf12)
+        p12.full_search = 0
+        o12s, skip12 = encode_line(F, torch, t12, p12, ws12, st12, 2, kf12)
+        p12.method, p12.full_search = F.METHOD_DIRECT, 1
+        o12d, full12d = encode_line(F, torch, t12, p12, ws12, 2, 1, 0)
+        p12.full_search = 0
+        o12ds, skip12d = encode_line(F, torch, t12, p12, ws12, 2, 1, 0)
+        ref12 = codes_np(o12)
+        same12 = all(np.array_equal(codes_np(o)[k], ref12[k]) for o in (o12s, o12d, o12ds)
+                     for k in ref12)
         result["ct12_512"] = {
             "workload": "512x512 12-bit slice, 8x8 ranges, 16x16 domains stride 2",
-            "candidates": c12, "value": c12 / (ms12 / 1e3), "unit": "comparisons/s",
-            "ms_per_step": ms12, "phases_ms": ph12,
-            # four FP16 partial products per searched candidate (hi/lo planes),
-            # over the sub-table of ranges and domains with variance
-            "ranges_searched": n_rs12, "domains_searched": n_ds12,
-            "mfma_frac": 4 * 2.0 * 64 * 8 * n_rs12 * n_ds12 / (ph12["search"] / 1e3)
-                         / MFMA_FP16_PEAK,
-            "direct_value": c12 / (ms12d / 1e3), "mfma_over_direct": ms12d / ms12,
-            "codes_identical_mfma_direct": bool(same12)}
+            "candidates": c12, "value": c12 / (full12["ms_per_step"] / 1e3),
+            "unit": "comparisons/s", "full": full12, "skip_flat": skip12,
+            "direct": {"full": full12d, "skip_flat": skip12d},
+            "mfma_over_direct": full12d["ms_per_step"] / full12["ms_per_step"],
+            "mfma_over_direct_skip_flat": skip12d["ms_per_step"] / skip12["ms_per_step"],
+            "codes_identical_all_modes_and_methods": bool(same12)}
+
+        # ---- the paper's own workload shape: 4x4 ranges, 8x8 domains stride 4 ---
+        pw = []
+        for row in PAPER_TABLE3["rows"]:
+            side = row["side"]
+            pimg = torch.from_numpy(gen_image(side, side, 8, 7000 + side)).to(dev)
+            pp = F.Params(side, side, 8, 4, 4, method=F.METHOD_MFMA, full_search=1)
+            pR, pND, pwsb, _ = F.query(pp)
+            pws = torch.empty(pwsb + 256, dtype=torch.uint8, device=dev)
+            _, pl = encode_line(F, torch, pimg, pp, pws, max(3, args.steps // 4), 2, 2.0 * 16)
+            pc = 8 * pR * pND
+            pw.append({"side": side, "candidates": pc, "ms": pl["ms_per_step"],
+                       "comparisons_per_s": pc / (pl["ms_per_step"] / 1e3),
+                       "search_mfma_frac": pl["search_mfma_frac"],
+                       "paper_gpu_s": row["gpu_s"], "paper_cpu_s": row["cpu_s"],
+                       "paper_gpu_comparisons_per_s_if_seconds": pc / row["gpu_s"],
+                       "speedup_over_paper_gpu_if_seconds": row["gpu_s"] / (pl["ms_per_step"] / 1e3)})
+        result["paper_workloads"] = {
+            "workload": "synthetic uint8 slices of the paper's sizes, 4x4 ranges, 8x8 domains "
+                        "stride 4, full search (seed 7000 + side)",
+            "rows": pw, "paper": PAPER_TABLE3}
 
         # ---- 256x256 u8, n = 4, stride 4: encode, decode, adjoint, refine ---------
         img5 = gen_image(256, 256, 8, 5)
         t5 = torch.from_numpy(img5).to(dev)
-        p5 = F.Params(256, 256, 8, 4, 4, method=F.METHOD_MFMA)
+        p5 = F.Params(256, 256, 8, 4, 4, method=F.METHOD_MFMA, full_search=1)
         R5, ND5, ws5b, bw5 = F.query(p5)
         ws5 = torch.empty(ws5b + 256, dtype=torch.uint8, device=dev)
-        o5, ms5, _ = time_encode(F, torch, t5, p5, ws5, args.steps, 2)
+        o5, enc5 = encode_line(F, torch, t5, p5, ws5, args.steps, 2, 2.0 * 16)
         s5, o5v = F.dequantize(o5["s_idx"], o5["o_idx"], p5)
         s5, o5v = s5.contiguous(), o5v.contiguous()
         T = 12
         HW = 256 * 256
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        for _ in range(3):
-            tr5 = F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T, 128.0)
-        torch.cuda.synchronize(dev)
-        e0.record()
-        for _ in range(20):
-            tr5 = F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T, 128.0)
-        e1.record()
-        torch.cuda.synchronize(dev)
-        ms_dec = e0.elapsed_time(e1) / 20
+        tr5 = F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T, 128.0)
+        ms_dec = mean_ms(torch, dev, lambda: F.decode(o5["domain"], o5["iso"], s5, o5v, p5, T,
+                                                      128.0), 20, 3)
         gxt = (2.0 * (tr5[-1] - t5.float()) / HW).contiguous()
-        for _ in range(3):
-            F.decode_backward(o5["domain"], o5["iso"], s5, o5v, tr5, gxt, p5)
-        torch.cuda.synchronize(dev)
-        e0.record()
-        for _ in range(20):
-            F.decode_backward(o5["domain"], o5["iso"], s5, o5v, tr5, gxt, p5)
-        e1.record()
-        torch.cuda.synchronize(dev)
-        ms_bwd = e0.elapsed_time(e1) / 20
+        ms_bwd = mean_ms(torch, dev, lambda: F.decode_backward(o5["domain"], o5["iso"], s5, o5v,
+                                                               tr5, gxt, p5), 20, 3)
         # algorithmic bytes: each iteration reads x_t and writes x_{t+1} once
         # (4 B each per pixel) and reads the codes (13 B per range); the
         # adjoint also reads the trajectory image and the domain->range table
         dec_bytes = T * (2 * 4 * HW + 13 * R5)
         bwd_bytes = T * (3 * 4 * HW + 13 * R5 + 4 * (ND5 + R5))
+        scaled = {}
+        for (num, den) in ((1, 2), (2, 1), (4, 1)):
+            ms_z = mean_ms(torch, dev, lambda: F.decode_scaled(o5["domain"], o5["iso"], s5, o5v, p5,
+                                                               (num, den), T, 128.0), 10, 2)
+            hwz = HW * num * num // (den * den)
+            zb = T * (2 * 4 * hwz + 13 * R5)
+            scaled[f"{num}/{den}"] = {"side": 256 * num // den, "ms": ms_z,
+                                      "gbps": zb / (ms_z / 1e3) / 1e9,
+                                      "hbm_frac": zb / (ms_z / 1e3) / HBM_PEAK}
         x0 = tr5[-1].double().cpu().numpy()
         ref5 = img5.astype(np.float64)
         sr, orf = s5.clone(), o5v.clone()
@@ -324,53 +408,86 @@ def main():
         xq = F.decode(o5["domain"], o5["iso"], sqv.contiguous(), oqv.contiguous(), p5, T, 128.0)[-1].double().cpu().numpy()
         result["decode256"] = {
             "workload": "256x256 uint8, 4x4 ranges, 8x8 domains stride 4; decoder T = 12 from 128",
-            "encode_value": 8 * R5 * ND5 / (ms5 / 1e3), "encode_ms": ms5,
+            "encode_value": 8 * R5 * ND5 / (enc5["ms_per_step"] / 1e3),
+            "encode_ms": enc5["ms_per_step"],
             "decode_ms": ms_dec, "decode_gbps": dec_bytes / (ms_dec / 1e3) / 1e9,
             "decode_hbm_frac": dec_bytes / (ms_dec / 1e3) / HBM_PEAK,
             "adjoint_ms": ms_bwd, "adjoint_gbps": bwd_bytes / (ms_bwd / 1e3) / 1e9,
             "adjoint_hbm_frac": bwd_bytes / (ms_bwd / 1e3) / HBM_PEAK,
             "psnr_db": psnr(x0, ref5, 255.0),
+            "scaled_decode": scaled,
             "refine": {"steps": 50, "lr_s": 5e-3, "lr_o": 0.5, "ms": ms_ref,
                        "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
                        "psnr_db": psnr(xr, ref5, 255.0), "psnr_requantised_db": psnr(xq, ref5, 255.0)}}
+
+        # ---- code stream: bytes per encode and the size reduction ---------------
+        def stream_line(out, prm, raw_bytes):
+            data = F.stream_pack(out, prm)
+            back = F.stream_unpack(data, prm)
+            torch.cuda.synchronize(dev)
+            ok = all(torch.equal(back[k], out[k]) for k in ("domain", "iso", "s_idx", "o_idx"))
+            nb, B = F.stream_query(prm)
+            return {"bytes": nb, "record_bits": B, "raw_bytes": raw_bytes,
+                    "ratio": raw_bytes / nb, "size_reduction": 1.0 - nb / raw_bytes,
+                    "pack_ms": mean_ms(torch, dev, lambda: F.stream_pack(out, prm), 20),
+                    "unpack_ms": mean_ms(torch, dev, lambda: F.stream_unpack(data, prm), 20),
+                    "round_trip_identical": bool(ok)}
+        p.full_search = 1
+        result["stream"] = {
+            "format": "32-byte header + one record per range: domain index (ceil(log2 N_d) "
+                      "bits), transform (3), s index (5), o index (7)",
+            "u8_512": stream_line(out_m, p, H * W),
+            "ct12_512": stream_line(o12, F.Params(512, 512, 12, 8, 2), 512 * 512 * 12 // 8),
+            "u8_256_n4": stream_line(o5, p5, 256 * 256),
+            "paper_size_reduction": "40 % (256^2 and 512^2), 41 % (1024^2); 85 % when "
+                                    "decoding at 4x the size (Table III and its text)"}
 
         # ---- 64 uneven slices, 8x8 ranges, 16x16 domains stride 8 ---------------
         from fic_inputs import batch_sides
         sides = batch_sides(64)
         bimgs = [torch.from_numpy(gen_image(sd, sd, 8, 4000 + i)).to(dev) for i, sd in enumerate(sides)]
-        bparams = [F.Params(sd, sd, 8, 8, 8) for sd in sides]
-        bat = F.Batch(bimgs, bparams)
-        bcand = sum(8 * F.query(bp)[0] * F.query(bp)[1] for bp in bparams)
-        for _ in range(2):
-            bat.run()
-        torch.cuda.synchronize(dev)
-        graph = torch.cuda.CUDAGraph()
-        gs = torch.cuda.Stream(device=dev)
-        gs.wait_stream(torch.cuda.current_stream(dev))
-        with torch.cuda.stream(gs):
-            with torch.cuda.graph(graph, stream=gs):
+        bcand = sum(8 * F.query(F.Params(sd, sd, 8, 8, 8))[0] * F.query(F.Params(sd, sd, 8, 8, 8))[1]
+                    for sd in sides)
+        batch_lines = {}
+        for full in (1, 0):
+            bparams = [F.Params(sd, sd, 8, 8, 8, full_search=full) for sd in sides]
+            bat = F.Batch(bimgs, bparams)
+            for _ in range(2):
                 bat.run()
-        torch.cuda.current_stream(dev).wait_stream(gs)
-        torch.cuda.synchronize(dev)
-        nrep = max(3, args.steps // 2)
-        lat = []
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        total = 0.0
-        for _ in range(nrep):
-            e0.record()
-            graph.replay()
-            e1.record()
             torch.cuda.synchronize(dev)
-            total += e0.elapsed_time(e1)
-            tk = bat.ticks.cpu().numpy().astype(np.int64)
-            lat.append((tk[1:] - tk[0]) / 100.0)   # 100 MHz ticks -> us
-        ms_b = total / nrep
-        lat = np.concatenate(lat)
+            graph = torch.cuda.CUDAGraph()
+            gs = torch.cuda.Stream(device=dev)
+            gs.wait_stream(torch.cuda.current_stream(dev))
+            with torch.cuda.stream(gs):
+                with torch.cuda.graph(graph, stream=gs):
+                    bat.run()
+            torch.cuda.current_stream(dev).wait_stream(gs)
+            torch.cuda.synchronize(dev)
+            nrep = max(3, args.steps // 2)
+            lat = []
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            total = 0.0
+            for _ in range(nrep):
+                e0.record()
+                graph.replay()
+                e1.record()
+                torch.cuda.synchronize(dev)
+                total += e0.elapsed_time(e1)
+                tk = bat.ticks.cpu().numpy().astype(np.int64)
+                lat.append((tk[1:] - tk[0]) / 100.0)   # 100 MHz ticks -> us
+            ms_b = total / nrep
+            lat = np.concatenate(lat)
+            batch_lines[full] = {"ms_per_batch": ms_b, "slices_per_s": 64 / (ms_b / 1e3),
+                                 "latency_us_p50": float(np.percentile(lat, 50)),
+                                 "latency_us_p99": float(np.percentile(lat, 99))}
+            del graph, bat
         result["batch64"] = {
-            "workload": "64 uint8 slices, sides from {256..512}^2, 8x8 ranges, 16x16 domains stride 8; one graph replay",
-            "slices": 64, "candidates": bcand, "ms_per_batch": ms_b,
-            "slices_per_s": 64 / (ms_b / 1e3), "value": bcand / (ms_b / 1e3), "unit": "comparisons/s",
-            "latency_us_p50": float(np.percentile(lat, 50)), "latency_us_p99": float(np.percentile(lat, 99)),
+            "workload": "64 uint8 slices, sides from {256..512}^2, 8x8 ranges, 16x16 domains "
+                        "stride 8; one graph replay; full search",
+            "slices": 64, "candidates": bcand,
+            "value": bcand / (batch_lines[1]["ms_per_batch"] / 1e3), "unit": "comparisons/s",
+            **batch_lines[1],
+            "skip_flat": batch_lines[0],
             "latency_note": "device clock at each slice's search completion minus search start"}
 
     if not args.no_cpu_baseline:

@@ -69,9 +69,23 @@ typedef struct {
   int32_t range_size;    /* n: 4 or 8 */
   int32_t domain_step;   /* STEP >= 1 */
   int32_t s_bits;        /* contrast bits, 1..8 (5 in the reference setup) */
-  int32_t o_bits;        /* offset bits, 1..bit_depth+1 (7) */
+  int32_t o_bits;        /* offset bits, 1..min(8, bit_depth+1) (7) */
   int32_t method;        /* enum fic_method */
+  int32_t full_search;   /* 0: skip the candidates whose outcome is fixed
+                            (below); 1: every range meets every domain in
+                            the contraction.  The codes are identical. */
 } fic_params;
+
+/*
+ * Shadow blocks.  A range without variance (all pixels equal) ties on every
+ * candidate and keeps candidate 0 (Section V: such blocks need no search).
+ * A domain without variance fits every range with s = 0 and the range mean
+ * (eqs. 11-12), so all such domains tie and only the first can win.  With
+ * full_search = 0 the search leaves both kinds out of the contraction and
+ * code extraction compares the first flat domain; with full_search = 1 they
+ * go through the contraction and the least-squares test like every other
+ * candidate (the test rejects them).  Both give the same codes.
+ */
 
 /* Codes, one entry per range (structure of arrays, device memory). */
 typedef struct {
@@ -87,7 +101,8 @@ typedef struct {
  * and domain counts and the workspace bytes that fic_encode and
  * fic_decode_backward need for these parameters.  Any output pointer may be
  * NULL.  Errors: FIC_E_INVALID (null p, height or width not a multiple of n,
- * 2n larger than a side, STEP < 1), FIC_E_UNSUPPORTED (bit_depth not 8 or 12,
+ * 2n larger than a side, STEP < 1, full_search not 0 or 1),
+ * FIC_E_UNSUPPORTED (bit_depth not 8 or 12,
  * n not 4 or 8, s_bits/o_bits out of range, more candidates than the packed
  * 64-bit search key can index).
  */
@@ -110,14 +125,13 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /*
- * fic_search_counts -- host, synchronous.  After an fic_encode of `p` with
- * the matrix-core method has completed on `workspace`,
- * reports how many ranges and how many domains the search visited: those
- * with variance.  A flat range (all pixels equal) ties on every candidate
- * and keeps candidate 0; a flat domain ties with the first flat domain,
- * which code extraction compares (Section V: shadow blocks need no search).
+ * fic_search_counts -- host, synchronous.  After an fic_encode of `p` has
+ * completed on `workspace`, reports how many ranges and how many domains the
+ * search kernel visited (either method): with full_search = 0 those with
+ * variance, with full_search = 1 all of them.  The search evaluated
+ * 8 * n_ranges * n_domains candidates.
  * Errors: FIC_E_INVALID (null pointers, workspace smaller than fic_query
- * reports), FIC_E_UNSUPPORTED (the plain method), FIC_E_HIP.
+ * reports), FIC_E_HIP.
  */
 int fic_search_counts(const fic_params *p, const void *workspace,
                       size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains);
@@ -169,6 +183,27 @@ int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
                float *traj, void *stream);
 
 /*
+ * fic_decode_scaled -- fic_decode at another resolution.  A range's code
+ * names its domain by grid position, not by pixels, so the codes of a
+ * height x width image decode at any size (Section I; Section VI decodes at
+ * four times the original size).  At scale z = scale_num / scale_den every
+ * length of the partition scales by z: the output is (height z) x (width z),
+ * ranges are n z pixels on a side, domains 2 n z, the domain grid spacing
+ * STEP z; each range keeps its domain index, transform, s and o, and the map
+ * keeps its definition (the transform of the 2x2-mean contraction, times s,
+ * plus o).  `p` describes the encoded image (its range and domain counts
+ * index the codes).  traj receives (iters + 1) images of
+ * (height z) x (width z) floats, traj[0] = x0.  z = 1 is fic_decode.
+ * Errors: FIC_E_INVALID (null pointers, iters < 0, scale_num or scale_den
+ * < 1, n z or STEP z not a whole number), FIC_E_UNSUPPORTED (an output
+ * larger than 2^30 pixels).
+ */
+int fic_decode_scaled(const fic_params *p, int32_t scale_num,
+                      int32_t scale_den, const int32_t *domain,
+                      const uint8_t *iso, const float *s, const float *o,
+                      int32_t iters, float x0, float *traj, void *stream);
+
+/*
  * fic_decode_backward -- reverse pass of fic_decode with respect to s and o.
  * Given traj from fic_decode (same codes, same iters) and grad_xT = dL/dx_T
  * (height*width floats), writes dL/ds and dL/do (n_ranges floats each,
@@ -203,6 +238,47 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
 
 /* Workspace bytes fic_refine needs for these parameters and iters (host). */
 int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
+
+/*
+ * Code stream: the codes written compactly for the encoding file (Section
+ * IV saves the codes; Table III reports the size reduction).  The paper
+ * gives no format; this library's is a 32-byte header and one fixed-width
+ * record per range:
+ *   header, little-endian: bytes 0-3 "PIFS"; 4-7 height; 8-11 width;
+ *     12 bit_depth; 13 range_size; 14 s_bits; 15 o_bits; 16-19 domain_step;
+ *     20 D; 21-23 zero; 24-31 number of ranges R.
+ *   payload: range r occupies bits [r B, (r + 1) B), B = D + 3 + s_bits +
+ *     o_bits, D the smallest number of bits that indexes the N_d domains
+ *     (2^D >= N_d); from a record's first bit: domain index (D bits),
+ *     transform (3), contrast index (s_bits), offset index (o_bits), each
+ *     least significant bit first.  Payload bit i is bit (i mod 8) of payload
+ *     byte i / 8, zero-padded to a multiple of 32 bits.
+ * Size: 32 + 4 ceil(R B / 32) bytes.  The codes' residuals are not stored.
+ *
+ * fic_stream_query -- host only: stream bytes and B for `p`.
+ * fic_stream_pack -- writes the stream of the codes (device arrays of R
+ *   entries) into `out` (device, >= the queried bytes, 4-byte aligned).
+ *   Each field is masked to its width, so codes outside their ranges (not
+ *   produced by fic_encode) do not spill into neighbouring fields.
+ * fic_stream_header -- host only: reads the 32-byte header (host memory)
+ *   into `p` (method 0, full_search 0) after checking the magic, the
+ *   parameters and that D and R agree with them.
+ * fic_stream_unpack -- reads the R records of a stream (device, 4-byte
+ *   aligned, >= the queried bytes for `p`) into the code arrays (device);
+ *   the header is not read (pass the parameters fic_stream_header returned).
+ * Errors: FIC_E_INVALID (null pointers, misalignment, a short or foreign
+ * stream), FIC_E_UNSUPPORTED (parameters as fic_query), FIC_E_WORKSPACE
+ * (output buffer too small), FIC_E_HIP.
+ */
+int fic_stream_query(const fic_params *p, size_t *bytes, int32_t *record_bits);
+int fic_stream_pack(const fic_params *p, const int32_t *domain,
+                    const uint8_t *iso, const uint8_t *s_idx,
+                    const uint8_t *o_idx, void *out, size_t out_bytes,
+                    void *stream);
+int fic_stream_header(const void *header, size_t bytes, fic_params *p);
+int fic_stream_unpack(const fic_params *p, const void *in, size_t in_bytes,
+                      int32_t *domain, uint8_t *iso, uint8_t *s_idx,
+                      uint8_t *o_idx, void *stream);
 
 /*
  * Launch-shape tuning (host only; no GPU work).  The search grid splits the

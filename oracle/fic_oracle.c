@@ -94,7 +94,7 @@ static void mirror_lr(const double *in, int n, double *out) {
 
 /* S_k: k in 0..7; k >= 4 mirrors first, then (k mod 4) quarter turns.
  * Blocks are at most ORACLE_MAX_N x ORACLE_MAX_N. */
-#define ORACLE_MAX_N 16
+#define ORACLE_MAX_N 32
 void oracle_isometry(const double *in, int n, int k, double *out) {
   double a[ORACLE_MAX_N * ORACLE_MAX_N], t[ORACLE_MAX_N * ORACLE_MAX_N];
   if (n <= 0 || n > ORACLE_MAX_N) return;
@@ -188,7 +188,9 @@ static int check_params(int height, int width, int bits, int n, int step,
   if (height % n || width % n) return OR_EINVAL;
   if (2 * n > height || 2 * n > width) return OR_EINVAL;
   if (bits < 1 || bits > 16) return OR_EINVAL;
-  if (s_bits < 1 || s_bits > 16 || o_bits < 1 || o_bits > bits + 1)
+  /* the code arrays hold one byte per index */
+  if (s_bits < 1 || s_bits > 8 || o_bits < 1 || o_bits > bits + 1 ||
+      o_bits > 8)
     return OR_EINVAL;
   return OR_OK;
 }
@@ -354,6 +356,34 @@ int oracle_decode(int height, int width, int n, int step, const int32_t *domain,
 }
 
 /*
+ * Decoding at another resolution.  The code of a range refers to a domain by
+ * its grid position, not by pixels, so it can be decoded at any size
+ * (Section I; Section VI decodes at four times the original size).  Reading
+ * used here: at scale z = num / den every length of the partition scales by
+ * z -- the image becomes (H z) x (W z), a range n z pixels on a side, a
+ * domain 2 n z, the domain grid spacing STEP z -- while the map keeps its
+ * definition (each range becomes s S_k(tau(domain)) + o, tau the 2x2 mean)
+ * and every range keeps its domain index, transform, s and o.  Needs n z and
+ * STEP z to be whole numbers; the domain grid then has the same shape at
+ * every scale.  traj holds (iters + 1) images of (H z) x (W z).
+ */
+int oracle_decode_scaled(int height, int width, int n, int step, int num,
+                         int den, const int32_t *domain, const uint8_t *iso,
+                         const double *s, const double *o, int iters,
+                         double x0, double *traj) {
+  if (num <= 0 || den <= 0 || n <= 0 || step <= 0 || height % n || width % n)
+    return OR_EINVAL;
+  if ((n * num) % den || (step * num) % den) return OR_EINVAL;
+  const int nz = n * num / den, sz = step * num / den;
+  const int hz = height / n * nz, wz = width / n * nz;
+  if (nz < 1 || nz > ORACLE_MAX_N) return OR_EINVAL;
+  if (domain_axis(hz, nz, sz) != domain_axis(height, n, step) ||
+      domain_axis(wz, nz, sz) != domain_axis(width, n, step))
+    return OR_EINVAL;
+  return oracle_decode(hz, wz, nz, sz, domain, iso, s, o, iters, x0, traj);
+}
+
+/*
  * Reverse-mode derivative of the unrolled decoder.  Given g = dL/dx_T it
  * returns dL/ds and dL/do.  The PIFS map is affine in (s, o) for a fixed
  * x_t (eq. 6), so with u_t = S_k(tau(x_t)) on every range:
@@ -424,6 +454,111 @@ int oracle_decode_backward(int height, int width, int n, int step,
   free(u);
   free(idx);
   free(idxk);
+  return OR_OK;
+}
+
+/* ---------------------------------------------------------------------------
+ * Code stream (Section IV: the codes are saved to the encoding file; Table III
+ * reports the size reduction).  The paper gives no file format; this build's
+ * format is a 32-byte header followed by one fixed-width record per range.
+ *   header (little-endian): bytes 0-3 "PIFS"; 4-7 height; 8-11 width;
+ *     12 bit depth; 13 range size n; 14 s_bits; 15 o_bits; 16-19 domain
+ *     step; 20 domain bits D; 21-23 zero; 24-31 number of ranges R.
+ *   records: range r occupies stream bits [r B, (r + 1) B) of the payload,
+ *     B = D + 3 + s_bits + o_bits, D = the bits that index N_d domains
+ *     (the smallest D with 2^D >= N_d); within a record, from its first bit:
+ *     domain index (D bits), transform (3), contrast index (s_bits), offset
+ *     index (o_bits), each field least significant bit first.  Stream bit i
+ *     is bit (i mod 8) of payload byte i / 8; the payload is padded with
+ *     zero bits to a multiple of 32 bits.
+ * The oracle writes and reads the stream one bit at a time.
+ * ------------------------------------------------------------------------- */
+
+int oracle_stream_domain_bits(int64_t n_domains) {
+  int D = 0;
+  while (((int64_t)1 << D) < n_domains) ++D;
+  return D;
+}
+
+int64_t oracle_stream_bytes(int height, int width, int n, int step,
+                            int s_bits, int o_bits) {
+  const int64_t R = oracle_n_ranges(height, width, n);
+  const int64_t ND = oracle_n_domains(height, width, n, step);
+  if (R < 0 || ND <= 0) return -1;
+  const int64_t B = oracle_stream_domain_bits(ND) + 3 + s_bits + o_bits;
+  return 32 + 4 * ((R * B + 31) / 32);
+}
+
+static void put_bits(uint8_t *pay, int64_t *pos, uint64_t v, int nbits) {
+  for (int b = 0; b < nbits; ++b, ++*pos)
+    if ((v >> b) & 1u) pay[*pos / 8] |= (uint8_t)(1u << (*pos % 8));
+}
+
+static uint64_t get_bits(const uint8_t *pay, int64_t *pos, int nbits) {
+  uint64_t v = 0;
+  for (int b = 0; b < nbits; ++b, ++*pos)
+    v |= (uint64_t)((pay[*pos / 8] >> (*pos % 8)) & 1u) << b;
+  return v;
+}
+
+static void put_le(uint8_t *p, uint64_t v, int nbytes) {
+  for (int i = 0; i < nbytes; ++i) p[i] = (uint8_t)(v >> (8 * i));
+}
+
+/* Writes the whole stream (header and records) into out (bytes long). */
+int oracle_stream_pack(int height, int width, int bits, int n, int step,
+                       int s_bits, int o_bits, const int32_t *domain,
+                       const uint8_t *iso, const uint8_t *s_idx,
+                       const uint8_t *o_idx, uint8_t *out, int64_t bytes) {
+  const int64_t need =
+      oracle_stream_bytes(height, width, n, step, s_bits, o_bits);
+  if (need < 0 || bytes < need) return OR_EINVAL;
+  const int64_t R = oracle_n_ranges(height, width, n);
+  const int64_t ND = oracle_n_domains(height, width, n, step);
+  const int D = oracle_stream_domain_bits(ND);
+  memset(out, 0, (size_t)need);
+  memcpy(out, "PIFS", 4);
+  put_le(out + 4, (uint64_t)height, 4);
+  put_le(out + 8, (uint64_t)width, 4);
+  out[12] = (uint8_t)bits;
+  out[13] = (uint8_t)n;
+  out[14] = (uint8_t)s_bits;
+  out[15] = (uint8_t)o_bits;
+  put_le(out + 16, (uint64_t)step, 4);
+  out[20] = (uint8_t)D;
+  put_le(out + 24, (uint64_t)R, 8);
+  uint8_t *pay = out + 32;
+  int64_t pos = 0;
+  for (int64_t r = 0; r < R; ++r) {
+    if (domain[r] < 0 || domain[r] >= ND || iso[r] > 7 ||
+        s_idx[r] >= (1u << s_bits) || o_idx[r] >= (1u << o_bits))
+      return OR_EINVAL;
+    put_bits(pay, &pos, (uint64_t)domain[r], D);
+    put_bits(pay, &pos, iso[r], 3);
+    put_bits(pay, &pos, s_idx[r], s_bits);
+    put_bits(pay, &pos, o_idx[r], o_bits);
+  }
+  return OR_OK;
+}
+
+/* Reads the R records of a stream whose header matches the geometry. */
+int oracle_stream_unpack(int height, int width, int n, int step, int s_bits,
+                         int o_bits, const uint8_t *in, int64_t bytes,
+                         int32_t *domain, uint8_t *iso, uint8_t *s_idx,
+                         uint8_t *o_idx) {
+  const int64_t need =
+      oracle_stream_bytes(height, width, n, step, s_bits, o_bits);
+  if (need < 0 || bytes < need || memcmp(in, "PIFS", 4) != 0) return OR_EINVAL;
+  const int64_t R = oracle_n_ranges(height, width, n);
+  const int D = oracle_stream_domain_bits(oracle_n_domains(height, width, n, step));
+  const uint8_t *pay = in + 32;
+  int64_t pos = 0;
+  for (int64_t r = 0; r < R; ++r) {
+    domain[r] = (int32_t)get_bits(pay, &pos, D);
+    iso[r] = (uint8_t)get_bits(pay, &pos, 3);
+    s_idx[r] = (uint8_t)get_bits(pay, &pos, s_bits);
+    o_idx[r] = (uint8_t)get_bits(pay, &pos, o_bits);
+  }
   return OR_OK;
 }
 

@@ -40,10 +40,20 @@ def lib():
                                          p, p, p, p, p]
         L.oracle_decode.restype = i32
         L.oracle_decode.argtypes = [i32, i32, i32, i32, p, p, p, p, i32, dbl, p]
+        L.oracle_decode_scaled.restype = i32
+        L.oracle_decode_scaled.argtypes = [i32, i32, i32, i32, i32, i32, p, p, p, p, i32, dbl, p]
         L.oracle_decode_backward.restype = i32
         L.oracle_decode_backward.argtypes = [i32, i32, i32, i32, p, p, p, p, i32, p, p, p, p]
         L.oracle_pifs_apply.restype = i32
         L.oracle_pifs_apply.argtypes = [i32, i32, i32, i32, p, p, p, p, p, p]
+        L.oracle_stream_domain_bits.restype = i32
+        L.oracle_stream_domain_bits.argtypes = [i64]
+        L.oracle_stream_bytes.restype = i64
+        L.oracle_stream_bytes.argtypes = [i32, i32, i32, i32, i32, i32]
+        L.oracle_stream_pack.restype = i32
+        L.oracle_stream_pack.argtypes = [i32, i32, i32, i32, i32, i32, i32, p, p, p, p, p, i64]
+        L.oracle_stream_unpack.restype = i32
+        L.oracle_stream_unpack.argtypes = [i32, i32, i32, i32, i32, i32, p, i64, p, p, p, p]
         L.oracle_max_threads.restype = i32
         L.oracle_max_threads.argtypes = []
         _LIB = L
@@ -165,6 +175,23 @@ def decode(h, w, n, step, domain, iso, s, o, iters, x0):
     return traj
 
 
+def decode_scaled(h, w, n, step, num, den, domain, iso, s, o, iters, x0):
+    """Decode the codes of an h x w image at scale num/den; returns the
+    trajectory (iters+1, h*num/den, w*num/den)."""
+    domain = np.ascontiguousarray(domain, np.int32)
+    iso = np.ascontiguousarray(iso, np.uint8)
+    s = np.ascontiguousarray(s, np.float64)
+    o = np.ascontiguousarray(o, np.float64)
+    if (h * num) % den or (w * num) % den:
+        raise ValueError("decode_scaled: the scaled image is not whole pixels")
+    traj = np.zeros((iters + 1, h * num // den, w * num // den), np.float64)
+    rc = lib().oracle_decode_scaled(h, w, n, step, num, den, _ptr(domain), _ptr(iso), _ptr(s),
+                                    _ptr(o), iters, float(x0), _ptr(traj))
+    if rc != 0:
+        raise ValueError("oracle_decode_scaled: invalid parameters")
+    return traj
+
+
 def decode_backward(h, w, n, step, domain, iso, s, o, iters, traj, grad_xT):
     domain = np.ascontiguousarray(domain, np.int32)
     iso = np.ascontiguousarray(iso, np.uint8)
@@ -179,6 +206,40 @@ def decode_backward(h, w, n, step, domain, iso, s, o, iters, traj, grad_xT):
     if rc != 0:
         raise ValueError("oracle_decode_backward: invalid parameters")
     return gs, go
+
+
+def stream_domain_bits(n_domains):
+    return int(lib().oracle_stream_domain_bits(int(n_domains)))
+
+
+def stream_bytes(h, w, n, step, s_bits=5, o_bits=7):
+    return int(lib().oracle_stream_bytes(h, w, n, step, s_bits, o_bits))
+
+
+def stream_pack(h, w, n, step, codes, bits=8, s_bits=5, o_bits=7):
+    """The code stream (header and records) of a dict of code arrays, as bytes."""
+    nb = stream_bytes(h, w, n, step, s_bits, o_bits)
+    out = np.zeros(nb, np.uint8)
+    arr = [np.ascontiguousarray(codes["domain"], np.int32), np.ascontiguousarray(codes["iso"], np.uint8),
+           np.ascontiguousarray(codes["s_idx"], np.uint8), np.ascontiguousarray(codes["o_idx"], np.uint8)]
+    rc = lib().oracle_stream_pack(h, w, bits, n, step, s_bits, o_bits, *[_ptr(a) for a in arr],
+                                  _ptr(out), nb)
+    if rc != 0:
+        raise ValueError("oracle_stream_pack: invalid parameters or codes")
+    return out
+
+
+def stream_unpack(h, w, n, step, data, s_bits=5, o_bits=7):
+    data = np.ascontiguousarray(data, np.uint8)
+    R = n_ranges(h, w, n)
+    out = dict(domain=np.zeros(R, np.int32), iso=np.zeros(R, np.uint8),
+               s_idx=np.zeros(R, np.uint8), o_idx=np.zeros(R, np.uint8))
+    rc = lib().oracle_stream_unpack(h, w, n, step, s_bits, o_bits, _ptr(data), len(data),
+                                    _ptr(out["domain"]), _ptr(out["iso"]), _ptr(out["s_idx"]),
+                                    _ptr(out["o_idx"]))
+    if rc != 0:
+        raise ValueError("oracle_stream_unpack: invalid stream")
+    return out
 
 
 def max_threads():

@@ -32,7 +32,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
                 ("bit_depth", ctypes.c_int32), ("range_size", ctypes.c_int32),
                 ("domain_step", ctypes.c_int32), ("s_bits", ctypes.c_int32),
-                ("o_bits", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("o_bits", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("full_search", ctypes.c_int32)]
 
 
 class _Codes(ctypes.Structure):
@@ -62,10 +63,12 @@ class Params:
     s_bits: int = 5
     o_bits: int = 7
     method: int = METHOD_MFMA
+    full_search: int = 0   # 1: ranges and domains without variance are searched too
 
     def c(self):
         return _Params(self.height, self.width, self.bit_depth, self.range_size,
-                       self.domain_step, self.s_bits, self.o_bits, self.method)
+                       self.domain_step, self.s_bits, self.o_bits, self.method,
+                       int(self.full_search))
 
 
 _LIB = None
@@ -90,6 +93,16 @@ def lib():
         L.fic_encode.argtypes = [P, vp, _Codes, vp, sz, vp]
         L.fic_decode.restype = ctypes.c_int
         L.fic_decode.argtypes = [P, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.fic_decode_scaled.restype = ctypes.c_int
+        L.fic_decode_scaled.argtypes = [P, i32, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.fic_stream_query.restype = ctypes.c_int
+        L.fic_stream_query.argtypes = [P, ctypes.POINTER(sz), ctypes.POINTER(i32)]
+        L.fic_stream_pack.restype = ctypes.c_int
+        L.fic_stream_pack.argtypes = [P, vp, vp, vp, vp, vp, sz, vp]
+        L.fic_stream_header.restype = ctypes.c_int
+        L.fic_stream_header.argtypes = [vp, sz, P]
+        L.fic_stream_unpack.restype = ctypes.c_int
+        L.fic_stream_unpack.argtypes = [P, vp, sz, vp, vp, vp, vp, vp]
         L.fic_decode_backward.restype = ctypes.c_int
         L.fic_decode_backward.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
         PP = ctypes.POINTER(_Params)
@@ -218,8 +231,9 @@ def encode(image: torch.Tensor, p: Params, workspace=None):
 
 
 def search_counts(out, p: Params):
-    """(ranges, domains) the search visited in the encode that produced
-    `out` (matrix-core method); synchronises the device."""
+    """(ranges, domains) the search kernel visited in the encode that
+    produced `out`; it evaluated 8 * ranges * domains candidates.
+    Synchronises the device."""
     ws, ew = out["_ws_ptr"]
     nr, nd = ctypes.c_int64(), ctypes.c_int64()
     cp = p.c()
@@ -275,6 +289,59 @@ class Batch:
         return self.codes
 
 
+def stream_query(p: Params):
+    """Host-only: (stream bytes, bits per range record)."""
+    nb, rb = ctypes.c_size_t(), ctypes.c_int32()
+    cp = p.c()
+    _check(lib().fic_stream_query(ctypes.byref(cp), ctypes.byref(nb), ctypes.byref(rb)))
+    return nb.value, rb.value
+
+
+def stream_pack(codes, p: Params):
+    """The code stream of device codes (dict with domain, iso, s_idx, o_idx)
+    as a device uint8 tensor."""
+    nb, _ = stream_query(p)
+    dev = codes["domain"].device
+    out = torch.empty((nb + 3) // 4, dtype=torch.int32, device=dev)
+    cp = p.c()
+    _check(lib().fic_stream_pack(ctypes.byref(cp), _dev_ptr(codes["domain"], torch.int32, "domain"),
+                                 _dev_ptr(codes["iso"], torch.uint8, "iso"),
+                                 _dev_ptr(codes["s_idx"], torch.uint8, "s_idx"),
+                                 _dev_ptr(codes["o_idx"], torch.uint8, "o_idx"),
+                                 out.data_ptr(), nb, _stream(dev)))
+    return out.view(torch.uint8)[:nb]
+
+
+def stream_header(data) -> Params:
+    """Params of a stream from its first 32 bytes (bytes or a host array)."""
+    buf = bytes(memoryview(data)[:32]) if not isinstance(data, torch.Tensor) else \
+        bytes(data[:32].cpu().numpy().tobytes())
+    q = _Params()
+    _check(lib().fic_stream_header(ctypes.c_char_p(buf), len(buf), ctypes.byref(q)))
+    return Params(q.height, q.width, q.bit_depth, q.range_size, q.domain_step, q.s_bits,
+                  q.o_bits, q.method, q.full_search)
+
+
+def stream_unpack(data: torch.Tensor, p: Params = None):
+    """Codes (device dict: domain, iso, s_idx, o_idx) of a device stream."""
+    if p is None:
+        p = stream_header(data)
+    nr = query(p)[0]
+    dev = data.device
+    buf = data
+    if buf.data_ptr() % 4:
+        buf = buf.clone()
+    out = dict(domain=torch.empty(nr, dtype=torch.int32, device=dev),
+               iso=torch.empty(nr, dtype=torch.uint8, device=dev),
+               s_idx=torch.empty(nr, dtype=torch.uint8, device=dev),
+               o_idx=torch.empty(nr, dtype=torch.uint8, device=dev))
+    cp = p.c()
+    _check(lib().fic_stream_unpack(ctypes.byref(cp), _dev_ptr(buf, torch.uint8, "stream"),
+                                   buf.numel(), out["domain"].data_ptr(), out["iso"].data_ptr(),
+                                   out["s_idx"].data_ptr(), out["o_idx"].data_ptr(), _stream(dev)))
+    return out
+
+
 def dequantize(s_idx, o_idx, p: Params):
     """Grid values of quantised codes: s = s_idx/2^(s_bits-1) - 1, o = o_idx*delta_o - 2^bits."""
     s = s_idx.to(torch.float32) / float(2 ** (p.s_bits - 1)) - 1.0
@@ -294,6 +361,26 @@ def decode(domain, iso, s, o, p: Params, iters=12, x0=None):
                             _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
                             _dev_ptr(o, torch.float32, "o"), iters, ctypes.c_float(x0),
                             traj.data_ptr(), _stream(dev)))
+    return traj
+
+
+def decode_scaled(domain, iso, s, o, p: Params, scale=(2, 1), iters=12, x0=None):
+    """Decode codes of the image described by p at scale num/den; returns the
+    trajectory (iters+1, H*num/den, W*num/den) float32."""
+    num, den = scale
+    if x0 is None:
+        x0 = float(2 ** (p.bit_depth - 1))
+    if (p.height * num) % den or (p.width * num) % den:
+        raise ValueError("the scaled image is not whole pixels")
+    dev = s.device
+    traj = torch.empty((iters + 1, p.height * num // den, p.width * num // den),
+                       dtype=torch.float32, device=dev)
+    cp = p.c()
+    _check(lib().fic_decode_scaled(ctypes.byref(cp), num, den,
+                                   _dev_ptr(domain, torch.int32, "domain"),
+                                   _dev_ptr(iso, torch.uint8, "iso"),
+                                   _dev_ptr(s, torch.float32, "s"), _dev_ptr(o, torch.float32, "o"),
+                                   iters, ctypes.c_float(x0), traj.data_ptr(), _stream(dev)))
     return traj
 
 

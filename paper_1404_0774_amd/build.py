@@ -13,7 +13,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfic.so")
 SOURCES = ["fic_abi.hip", "fic_batch.hip", "fic_prep.hip", "fic_seed.hip",
            "fic_search_mfma.hip", "fic_search_mfma12.hip", "fic_search_direct.hip",
-           "fic_decode.hip", "fic_tuning.hip"]
+           "fic_decode.hip", "fic_tuning.hip", "fic_stream.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

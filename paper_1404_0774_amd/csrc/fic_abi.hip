@@ -87,8 +87,12 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
     return fail(FIC_E_UNSUPPORTED, "range_size %d (4 or 8)", n);
   if (p->s_bits < 1 || p->s_bits > 8)
     return fail(FIC_E_UNSUPPORTED, "s_bits %d (1..8)", p->s_bits);
-  if (p->o_bits < 1 || p->o_bits > p->bit_depth + 1)
-    return fail(FIC_E_UNSUPPORTED, "o_bits %d (1..bit_depth+1)", p->o_bits);
+  // the code arrays hold one byte per index
+  if (p->o_bits < 1 || p->o_bits > p->bit_depth + 1 || p->o_bits > 8)
+    return fail(FIC_E_UNSUPPORTED, "o_bits %d (1..min(8, bit_depth+1))",
+                p->o_bits);
+  if (p->full_search != 0 && p->full_search != 1)
+    return fail(FIC_E_INVALID, "full_search %d (0 or 1)", p->full_search);
   if (for_encode && p->method != FIC_METHOD_MFMA &&
       p->method != FIC_METHOD_DIRECT)
     return fail(FIC_E_INVALID, "method %d", p->method);
@@ -141,6 +145,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   while (gcd_ll(rs, g.R_pad) != 1) ++rs;
   g.rng_stride = (int)rs;
   g.pix_a = 0;
+  g.full = p->full_search;
   return FIC_OK;
 }
 
@@ -188,6 +193,32 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   return b;
 }
 
+// Layout and header of the code stream of an encode with geometry g.
+StreamGeo stream_geo(const Geo &g) {
+  StreamGeo sg;
+  sg.D = 0;
+  while ((1ll << sg.D) < (long long)g.ND) ++sg.D;
+  sg.sb = g.sb;
+  sg.ob = g.ob;
+  sg.B = sg.D + 3 + g.sb + g.ob;
+  sg.R = g.R;
+  sg.words = (sg.R * sg.B + 31) / 32;
+  sg.header[0] = 0x53464950u;  // "PIFS" in little-endian byte order
+  sg.header[1] = (uint32_t)g.H;
+  sg.header[2] = (uint32_t)g.W;
+  sg.header[3] = (uint32_t)g.bits | (uint32_t)g.n << 8 | (uint32_t)g.sb << 16 |
+                 (uint32_t)g.ob << 24;
+  sg.header[4] = (uint32_t)g.step;
+  sg.header[5] = (uint32_t)sg.D;
+  sg.header[6] = (uint32_t)((unsigned long long)sg.R & 0xffffffffu);
+  sg.header[7] = (uint32_t)((unsigned long long)sg.R >> 32);
+  return sg;
+}
+
+size_t stream_total_bytes(const StreamGeo &sg) {
+  return 32 + 4 * (size_t)sg.words;
+}
+
 int hip_fail(hipError_t e, const char *what) {
   return fail(FIC_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
@@ -208,6 +239,9 @@ void timing_mark(int phase, hipStream_t s) {
   const int slot = g_timing.calls % kTimedCalls;
   hipEventRecord(g_timing.ev[kMarks * slot + phase], s);
 }
+
+int encode_launch(const fic_params *p, Geo g, const void *image,
+                  fic_codes out, void *workspace, void *stream);
 
 }  // namespace
 
@@ -254,7 +288,19 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   if (ws_bytes < L.total)
     return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
                 L.total);
-  const EncBufs b = enc_bufs(L, workspace);
+  return encode_launch(p, g, image, out, workspace, stream);
+}
+
+}  // extern "C"
+
+namespace fic {
+namespace {
+
+// The launches of one encode on a validated workspace of at least
+// enc_layout(g).total bytes.
+int encode_launch(const fic_params *p, Geo g, const void *image,
+                  fic_codes out, void *workspace, void *stream) {
+  const EncBufs b = enc_bufs(enc_layout(g), workspace);
   hipStream_t s = (hipStream_t)stream;
   // 8x8 ranges on the matrix cores take their range fragments straight from
   // the (8-byte aligned) image
@@ -267,17 +313,15 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   // the seed pass ranks the leading column blocks to give every range a
   // starting bound; the search still covers every column block
   const Tune t = resolve_tune(g, p->method);
-  if (p->method == FIC_METHOD_MFMA) {
-    // the matrix-core searches visit only ranges and domains with variance
-    // (lists built here, in order)
-    e = launch_compact(g, b, s);
-    if (e != hipSuccess) return hip_fail(e, "compact");
-  }
+  // both searches walk the lists of range slots and domain columns they
+  // visit (all of them, or those with variance), built here in order
+  e = launch_compact(g, b, s);
+  if (e != hipSuccess) return hip_fail(e, "compact");
   e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
   timing_mark(2, s);
   if (p->method == FIC_METHOD_DIRECT)
-    e = launch_search_direct(g, b, t.chunks, 0, s);
+    e = launch_search_direct(g, b, t.chunks, s);
   else if (g.bits == 12)
     e = launch_search_mfma12(
         g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
@@ -293,6 +337,11 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
   return ok();
 }
 
+}  // namespace
+}  // namespace fic
+
+extern "C" {
+
 int fic_search_counts(const fic_params *p, const void *workspace,
                       size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains) {
   Geo g;
@@ -300,9 +349,6 @@ int fic_search_counts(const fic_params *p, const void *workspace,
   if (st) return st;
   if (!workspace || !n_ranges || !n_domains)
     return fail(FIC_E_INVALID, "null workspace or output pointer");
-  if (p->method != FIC_METHOD_MFMA)
-    return fail(FIC_E_UNSUPPORTED,
-                "search counts exist for the matrix-core method only");
   const EncLayout L = enc_layout(g);
   if (ws_bytes < L.total)
     return fail(FIC_E_INVALID, "workspace %zu bytes < %zu", ws_bytes, L.total);
@@ -327,6 +373,47 @@ int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   hipError_t e = launch_decode(g, domain, iso, s, o, iters, x0, traj,
                                (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "decode");
+  return ok();
+}
+
+int fic_decode_scaled(const fic_params *p, int32_t scale_num,
+                      int32_t scale_den, const int32_t *domain,
+                      const uint8_t *iso, const float *s, const float *o,
+                      int32_t iters, float x0, float *traj, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !traj)
+    return fail(FIC_E_INVALID, "null code or trajectory pointer");
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  if (scale_num < 1 || scale_den < 1)
+    return fail(FIC_E_INVALID, "scale %d/%d is not positive", scale_num,
+                scale_den);
+  const long long nz = (long long)g.n * scale_num, sz = (long long)g.step * scale_num;
+  if (nz % scale_den || sz % scale_den)
+    return fail(FIC_E_INVALID,
+                "scale %d/%d leaves ranges (%d) or the domain grid (%d) "
+                "without whole pixels",
+                scale_num, scale_den, g.n, g.step);
+  DecGeo d;
+  d.n = (int)(nz / scale_den);
+  d.step = (int)(sz / scale_den);
+  const long long Hz = (long long)g.RH * d.n, Wz = (long long)g.RW * d.n;
+  if (Hz * Wz > (1ll << 30))
+    return fail(FIC_E_UNSUPPORTED, "scaled image %lldx%lld larger than 2^30 "
+                "pixels", Hz, Wz);
+  d.H = (int)Hz;
+  d.W = (int)Wz;
+  d.RW = g.RW;
+  d.NX = g.NX;
+  d.ND = g.ND;
+  // the domain grid keeps its shape: (W z - 2 n z) / (STEP z) = (W - 2n) / STEP
+  if ((d.W - 2 * d.n) / d.step + 1 != g.NX || (d.H - 2 * d.n) / d.step + 1 != g.NY)
+    return fail(FIC_E_INVALID, "scale %d/%d changes the domain grid",
+                scale_num, scale_den);
+  hipError_t e = launch_decode_scaled(d, domain, iso, s, o, iters, x0, traj,
+                                      (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_scaled");
   return ok();
 }
 
@@ -387,6 +474,87 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   hipError_t e = launch_refine(g, domain, iso, s, o, image, iters, x0, steps,
                                lr_s, lr_o, loss, workspace, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "refine");
+  return ok();
+}
+
+int fic_stream_query(const fic_params *p, size_t *bytes,
+                     int32_t *record_bits) {
+  Geo g;
+  const int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  const StreamGeo sg = stream_geo(g);
+  if (bytes) *bytes = stream_total_bytes(sg);
+  if (record_bits) *record_bits = sg.B;
+  return ok();
+}
+
+int fic_stream_pack(const fic_params *p, const int32_t *domain,
+                    const uint8_t *iso, const uint8_t *s_idx,
+                    const uint8_t *o_idx, void *out, size_t out_bytes,
+                    void *stream) {
+  Geo g;
+  const int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s_idx || !o_idx || !out)
+    return fail(FIC_E_INVALID, "null code or stream pointer");
+  if ((uintptr_t)out & 3)
+    return fail(FIC_E_INVALID, "stream buffer is not 4-byte aligned");
+  const StreamGeo sg = stream_geo(g);
+  if (out_bytes < stream_total_bytes(sg))
+    return fail(FIC_E_WORKSPACE, "stream buffer %zu bytes < %zu needed",
+                out_bytes, stream_total_bytes(sg));
+  const hipError_t e = launch_stream_pack(sg, domain, iso, s_idx, o_idx, out,
+                                          (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream_pack");
+  return ok();
+}
+
+int fic_stream_header(const void *header, size_t bytes, fic_params *p) {
+  if (!header || !p) return fail(FIC_E_INVALID, "null header or params");
+  if (bytes < 32) return fail(FIC_E_INVALID, "a stream header is 32 bytes");
+  uint32_t h[8];
+  memcpy(h, header, sizeof h);
+  if (h[0] != 0x53464950u) return fail(FIC_E_INVALID, "not a PIFS code stream");
+  fic_params q;
+  memset(&q, 0, sizeof q);
+  q.height = (int32_t)h[1];
+  q.width = (int32_t)h[2];
+  q.bit_depth = (int32_t)(h[3] & 255u);
+  q.range_size = (int32_t)((h[3] >> 8) & 255u);
+  q.s_bits = (int32_t)((h[3] >> 16) & 255u);
+  q.o_bits = (int32_t)(h[3] >> 24);
+  q.domain_step = (int32_t)h[4];
+  q.method = FIC_METHOD_MFMA;
+  Geo g;
+  if (h[1] > 0x7fffffffu || h[2] > 0x7fffffffu || h[4] > 0x7fffffffu ||
+      make_geo(&q, g, /*for_encode=*/false) != FIC_OK)
+    return fail(FIC_E_INVALID, "stream header holds invalid parameters");
+  const StreamGeo sg = stream_geo(g);
+  if (h[5] != (uint32_t)sg.D || h[6] != sg.header[6] || h[7] != sg.header[7])
+    return fail(FIC_E_INVALID,
+                "stream header's domain bits or range count disagree with "
+                "its geometry");
+  *p = q;
+  return ok();
+}
+
+int fic_stream_unpack(const fic_params *p, const void *in, size_t in_bytes,
+                      int32_t *domain, uint8_t *iso, uint8_t *s_idx,
+                      uint8_t *o_idx, void *stream) {
+  Geo g;
+  const int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!in || !domain || !iso || !s_idx || !o_idx)
+    return fail(FIC_E_INVALID, "null stream or code pointer");
+  if ((uintptr_t)in & 3)
+    return fail(FIC_E_INVALID, "stream is not 4-byte aligned");
+  const StreamGeo sg = stream_geo(g);
+  if (in_bytes < stream_total_bytes(sg))
+    return fail(FIC_E_INVALID, "stream %zu bytes < %zu for these parameters",
+                in_bytes, stream_total_bytes(sg));
+  const hipError_t e = launch_stream_unpack(sg, in, domain, iso, s_idx, o_idx,
+                                            (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "stream_unpack");
   return ok();
 }
 

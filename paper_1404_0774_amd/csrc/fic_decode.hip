@@ -50,6 +50,25 @@ __global__ void k_decode_step(Geo g, const int32_t *domain, const uint8_t *iso,
   y[p] = fmaf(s[r], u, o[r]);
 }
 
+// Any range size n (a decode at another scale): one thread per output pixel.
+__global__ void k_decode_step_any(DecGeo d, const int32_t *domain,
+                                  const uint8_t *iso, const float *s,
+                                  const float *o, const float *x, float *y) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= d.H * d.W) return;
+  const int py = p / d.W, px = p % d.W;
+  const int ry = py / d.n, rx = px / d.n, i = py % d.n, j = px % d.n;
+  const int r = ry * d.RW + rx;
+  const int dm = clamp_dom(domain[r], d.ND);
+  int si, sj;
+  sigma(iso[r], i, j, d.n - 1, si, sj);
+  const int cy = (dm / d.NX) * d.step + 2 * si;
+  const int cx = (dm % d.NX) * d.step + 2 * sj;
+  const float *c = x + (size_t)cy * d.W + cx;
+  const float u = ((c[0] + c[1]) + (c[d.W] + c[d.W + 1])) * 0.25f;
+  y[p] = fmaf(s[r], u, o[r]);
+}
+
 __global__ void k_fill_f32(float *p, long long n, float v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -501,6 +520,21 @@ hipError_t launch_decode(const Geo &g, const int32_t *domain,
       hipLaunchKernelGGL(k_decode_step<4>, grid, dim3(bs), 0, st, g, domain,
                          iso, s, o, x, y);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
+                                const uint8_t *iso, const float *s,
+                                const float *o, int iters, float x0,
+                                float *traj, hipStream_t st) {
+  const long long HW = (long long)d.H * d.W;
+  const int bs = 256;
+  const dim3 grid((unsigned)((HW + bs - 1) / bs));
+  hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
+  for (int t = 0; t < iters; ++t)
+    hipLaunchKernelGGL(k_decode_step_any, grid, dim3(bs), 0, st, d, domain,
+                       iso, s, o, traj + (size_t)t * HW,
+                       traj + (size_t)(t + 1) * HW);
   return hipGetLastError();
 }
 

@@ -29,6 +29,8 @@ struct Geo {
                      //   (slots of ranges >= R are padding)
   int pix_a;         // 1: the 8-bit n = 8 matrix-core search builds its range
                      //   fragments from the image; no range operand is written
+  int full;          // 1: ranges and domains without variance are searched
+                     //   too (0: they are left out; their outcome is fixed)
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step
@@ -111,6 +113,21 @@ struct BatchDev {
   int bits, rsize;            // common to every slice
 };
 
+// Geometry of a decode at any range size (the encoded geometry scaled):
+// image H x W, ranges n x n (RW per row), domains 2n x 2n on a grid of
+// spacing step with NX per row and ND in all.
+struct DecGeo {
+  int H, W, n, step, RW, NX, ND;
+};
+
+// Layout of a code stream: R records of B bits (D of them the domain index)
+// in `words` payload words after the 8-word header.
+struct StreamGeo {
+  long long R, words;
+  int B, D, sb, ob;
+  uint32_t header[8];
+};
+
 // Launchers (one per kernel file).  All return hipError_t of the launch.
 hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
                        hipStream_t st);
@@ -122,7 +139,7 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
                                 int workgroups, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                int first_block, hipStream_t st);
+                                hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
                            fic_codes out, hipStream_t st);
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
@@ -133,7 +150,18 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                                   const float *o, int iters, const float *traj,
                                   const float *grad_xT, float *grad_s,
                                   float *grad_o, void *ws, hipStream_t st);
+hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
+                                const uint8_t *iso, const float *s,
+                                const float *o, int iters, float x0,
+                                float *traj, hipStream_t st);
 size_t decode_backward_ws_bytes(const Geo &g);
+hipError_t launch_stream_pack(const StreamGeo &sg, const int32_t *domain,
+                              const uint8_t *iso, const uint8_t *s_idx,
+                              const uint8_t *o_idx, void *out,
+                              hipStream_t st);
+hipError_t launch_stream_unpack(const StreamGeo &sg, const void *in,
+                                int32_t *domain, uint8_t *iso, uint8_t *s_idx,
+                                uint8_t *o_idx, hipStream_t st);
 hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st);
 hipError_t launch_compact(const Geo &g, const EncBufs &b, hipStream_t st);
 hipError_t launch_compact_batch(const BatchDev &bd, hipStream_t st);

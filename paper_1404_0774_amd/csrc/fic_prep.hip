@@ -173,7 +173,8 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     rec.dom = d;
     rec.saa = g.bits == 8 ? (unsigned)SAA : 0u;
     b.col_rec[col] = rec;
-    b.col_flag[col] = dp != __builtin_inff() ? 1 : 0;
+    // searched: a domain with variance, or any domain in a full search
+    b.col_flag[col] = d >= 0 && (g.full || dp != __builtin_inff()) ? 1 : 0;
   }
   __syncthreads();
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
@@ -257,8 +258,9 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
   if (q0 != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
-  // searched iff a real range with variance (K Sbb - Sb^2 != 0, exact)
-  b.rng_flag[r] = ri < g.R && (Acc)K * Sbb - Sb * Sb != 0 ? 1 : 0;
+  // searched: a real range with variance (K Sbb - Sb^2 != 0, exact), or
+  // any real range in a full search
+  b.rng_flag[r] = ri < g.R && (g.full || (Acc)K * Sbb - Sb * Sb != 0) ? 1 : 0;
   if (ri >= g.R) {
     b.best[r] = ~0ull;
     return;
@@ -478,8 +480,8 @@ __device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
   }
 }
 
-// The search's work lists: range slots holding a range with variance and
-// domain columns holding a domain with variance (flags written by the
+// The search's work lists: range slots and domain columns it visits (those
+// with variance, or every real one in a full search; flags written by the
 // preparation), both in slot / sweep order.
 __device__ __forceinline__ void compact_body(const Geo &g, const EncBufs &b) {
   block_compact2(g.R_pad, b.rng_flag, b.act_slot, g.NC_pad, b.col_flag,

@@ -1,6 +1,9 @@
 // fic_search_direct.hip -- the plain method: Alg. 3's per-candidate sums
 // computed directly on the vector ALUs, with the operands staged in LDS.
 //
+// Both walk the same lists of range slots and domain columns as the
+// matrix-core kernels (all of them in a full search, those with variance
+// otherwise), so the two methods evaluate the same candidates.
 // Each thread owns one range and four domain columns and accumulates the 32
 // inner products sum_p Rop[(r, k), p] * Bop[d, p] (8 transforms x 4 domains)
 // with scalar FP32 multiply-adds (exact: integers below 2^24).  The range
@@ -29,35 +32,74 @@ __device__ __noinline__ float eval_survivor_d(float Gf, int col, int r, int k,
   return prune_weight(key_err(nb, g), Sb, Sbb, g);
 }
 
-// grid: (chunks, R_pad / 32); block: 256 threads.  Thread t: range slot
-// t / 8 of the tile, columns 4 (t mod 8) .. +3 of each 32-column block.
+// The workgroup's share of the searched lists: entries [r0, r0 + nr) of the
+// range-slot list (written to s_slot, -1 past its end) and column blocks
+// [cb0, cb1) of the column list, from the list lengths read on the device.
+// Returns false when the workgroup has nothing to do (uniform).
+__device__ __forceinline__ bool direct_share(const EncBufs &b, int nr,
+                                             int *s_slot, int &cb0, int &cb1) {
+  const int nA = b.n_act[0], nD = b.n_act[1];
+  const int r0 = blockIdx.y * nr;
+  const int ncb = (nD + 31) / 32;
+  const int cbpc = (ncb + (int)gridDim.x - 1) / (int)gridDim.x;
+  cb0 = blockIdx.x * cbpc;
+  cb1 = min(cb0 + cbpc, ncb);
+  if (r0 >= nA || cb0 >= cb1) return false;
+  if ((int)threadIdx.x < nr)
+    s_slot[threadIdx.x] = r0 + (int)threadIdx.x < nA
+                              ? b.act_slot[r0 + threadIdx.x] : -1;
+  return true;
+}
+
+// Columns of searched block cb (-1 past the list) into s_col.
+__device__ __forceinline__ void direct_columns(const EncBufs &b, int cb,
+                                               int *s_col) {
+  if (threadIdx.x < 32) {
+    const int j = cb * 32 + (int)threadIdx.x;
+    s_col[threadIdx.x] = j < b.n_act[1] ? b.act_col[j] : -1;
+  }
+}
+
+// grid: (chunks, R_pad / 32); block: 256 threads.  Workgroup y takes entries
+// 32 y .. 32 y + 31 of the searched range list; thread t owns entry t / 8 and
+// columns 4 (t mod 8) .. +3 of each 32-column block of the searched column
+// list.
 template <int K>
-__global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
-                                                          int cb_begin,
-                                                          int cb_per_chunk) {
+__global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b) {
   __shared__ __attribute__((aligned(16))) float As[K][256];  // [p][8 rs + k]
   __shared__ __attribute__((aligned(16))) float Bs[K][32];   // [p][column]
+  __shared__ int s_slot[32], s_col[32];
+  int cb0, cb1;
+  if (!direct_share(b, 32, s_slot, cb0, cb1)) return;
   const int t = threadIdx.x;
   const int rs = t >> 3, cg = t & 7;
-  const int r0 = blockIdx.y * 32;
-  const int r = r0 + rs;
+  __syncthreads();
 
   // stage the range tile (transposed so that a thread's 8 rows are adjacent)
   for (int i = t; i < 256 * K; i += 256) {
     const int row = i / K, p = i % K;
-    As[p][row] = (float)b.aop[((size_t)r0 * 8 + row) * K + p];
+    const int sl = s_slot[row >> 3];
+    As[p][row] =
+        sl >= 0 ? (float)b.aop[((size_t)sl * 8 + (row & 7)) * K + p] : 0.0f;
   }
-  const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
+  const int r = s_slot[rs];
+  double Sb = 0.0, Sbb = 0.0;
+  float wp = __builtin_inff();  // no range: nothing passes
+  if (r >= 0) {
+    Sb = b.rng_sb[r];
+    Sbb = b.rng_sbb[r];
+    wp = prune_weight(key_err(b.best[r], g), Sb, Sbb, g);
+  }
   const float bbar = (float)(Sb / K);
-  float wp = prune_weight(key_err(b.best[r], g), Sb, Sbb, g);
 
-  const int cb0 = cb_begin + blockIdx.x * cb_per_chunk;
-  const int cb1 = min(cb0 + cb_per_chunk, g.NCB);
   for (int cb = cb0; cb < cb1; ++cb) {
+    __syncthreads();
+    direct_columns(b, cb, s_col);
     __syncthreads();
     for (int i = t; i < 32 * K; i += 256) {
       const int c = i / K, p = i % K;
-      Bs[p][c] = (float)b.bop[((size_t)cb * 32 + c) * K + p];
+      const int col = s_col[c];
+      Bs[p][c] = col >= 0 ? (float)b.bop[(size_t)col * K + p] : 0.0f;
     }
     __syncthreads();
 
@@ -81,8 +123,10 @@ __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
 
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const int col = cb * 32 + 4 * cg + c;
-      const float2 sadp = b.col_sadp[col];
+      const int col = s_col[4 * cg + c];
+      // past the list: a flat column, which never passes
+      const float2 sadp =
+          col >= 0 ? b.col_sadp[col] : float2{0.0f, __builtin_inff()};
       const float csa = sadp.x, cdp = sadp.y;
       float mx = acc[c][0], mn = mx;
 #pragma unroll
@@ -100,7 +144,7 @@ __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
         }
       }
     }
-    if ((cb & 7) == 7)
+    if (((cb - cb0) & 7) == 7 && r >= 0)
       wp = prune_weight(
           key_err(__hip_atomic_load(&b.best[r], __ATOMIC_RELAXED,
                                     __HIP_MEMORY_SCOPE_AGENT),
@@ -109,44 +153,53 @@ __global__ __launch_bounds__(256) void k_search_direct_u8(Geo g, EncBufs b,
   }
 }
 
-// 12-bit plain method: grid (chunks, R_pad / 16); block 256 threads.  Thread
-// t: range slot t / 16 of the tile, columns 2 (t mod 16), +1 of each block.
+// 12-bit plain method: grid (chunks, R_pad / 16); block 256 threads.
+// Workgroup y takes entries 16 y .. 16 y + 15 of the searched range list;
+// thread t owns entry t / 16 and columns 2 (t mod 16), +1 of each block.
 // Three exact FP32 partial sums per candidate (as in the matrix-core split:
 // G = 8192 G_hh + 64 M + G_ll), rebuilt exactly in FP64 for the test.
 template <int K>
-__global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b,
-                                                          int cb_begin,
-                                                          int cb_per_chunk) {
+__global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b) {
   __shared__ __attribute__((aligned(16))) float Ah[K][128];  // [p][8 rs + k]
   __shared__ __attribute__((aligned(16))) float Al[K][128];
   __shared__ __attribute__((aligned(16))) float Bh[K][32];   // [p][column]
   __shared__ __attribute__((aligned(16))) float Bl[K][32];
+  __shared__ int s_slot[16], s_col[32];
+  int cb0, cb1;
+  if (!direct_share(b, 16, s_slot, cb0, cb1)) return;
   const int t = threadIdx.x;
   const int rs = t >> 4, cg = t & 15;
-  const int r0 = blockIdx.y * 16;
-  const int r = r0 + rs;
   const size_t aplane = (size_t)g.R_pad * 8 * K;
   const size_t bplane = (size_t)g.NC_pad * K;
+  __syncthreads();
 
   for (int i = t; i < 128 * K; i += 256) {
     const int row = i / K, p = i % K;
-    const size_t o = ((size_t)r0 * 8 + row) * K + p;
-    Ah[p][row] = (float)b.aop[o];
-    Al[p][row] = (float)b.aop[aplane + o];
+    const int sl = s_slot[row >> 3];
+    const size_t o = ((size_t)(sl >= 0 ? sl : 0) * 8 + (row & 7)) * K + p;
+    Ah[p][row] = sl >= 0 ? (float)b.aop[o] : 0.0f;
+    Al[p][row] = sl >= 0 ? (float)b.aop[aplane + o] : 0.0f;
   }
-  const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
+  const int r = s_slot[rs];
+  double Sb = 0.0, Sbb = 0.0;
+  float wp = __builtin_inff();  // no range: nothing passes
+  if (r >= 0) {
+    Sb = b.rng_sb[r];
+    Sbb = b.rng_sbb[r];
+    wp = prune_weight(key_err(b.best[r], g), Sb, Sbb, g);
+  }
   const double Kd = (double)g.K;
-  float wp = prune_weight(key_err(b.best[r], g), Sb, Sbb, g);
 
-  const int cb0 = cb_begin + blockIdx.x * cb_per_chunk;
-  const int cb1 = min(cb0 + cb_per_chunk, g.NCB);
   for (int cb = cb0; cb < cb1; ++cb) {
+    __syncthreads();
+    direct_columns(b, cb, s_col);
     __syncthreads();
     for (int i = t; i < 32 * K; i += 256) {
       const int c = i / K, p = i % K;
-      const size_t o = ((size_t)cb * 32 + c) * K + p;
-      Bh[p][c] = (float)b.bop[o];
-      Bl[p][c] = (float)b.bop[bplane + o];
+      const int col = s_col[c];
+      const size_t o = (size_t)(col >= 0 ? col : 0) * K + p;
+      Bh[p][c] = col >= 0 ? (float)b.bop[o] : 0.0f;
+      Bl[p][c] = col >= 0 ? (float)b.bop[bplane + o] : 0.0f;
     }
     __syncthreads();
 
@@ -179,7 +232,8 @@ __global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b,
 
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
-      const int col = cb * 32 + 2 * cg + c;
+      const int col = s_col[2 * cg + c];
+      if (col < 0) continue;  // past the list
       const float2 sadp = b.col_sadp[col];
       const float cdp = sadp.y;
       const double csa = (double)sadp.x;
@@ -197,7 +251,7 @@ __global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b,
         }
       }
     }
-    if ((cb & 7) == 7)
+    if (((cb - cb0) & 7) == 7 && r >= 0)
       wp = prune_weight(
           key_err(__hip_atomic_load(&b.best[r], __ATOMIC_RELAXED,
                                     __HIP_MEMORY_SCOPE_AGENT),
@@ -209,30 +263,26 @@ __global__ __launch_bounds__(256) void k_search_direct_12(Geo g, EncBufs b,
 }  // namespace
 
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
-                                int first_block, hipStream_t st) {
-  const int rest = g.NCB - first_block;
-  if (rest <= 0) return hipSuccess;
-  if (chunks > rest) chunks = rest;
+                                hipStream_t st) {
+  // the lists' lengths are read on the device: the grid covers the longest
+  // possible lists and workgroups past them leave at once
+  if (chunks > g.NCB) chunks = g.NCB;
   if (chunks < 1) chunks = 1;
-  const int cbpc = (rest + chunks - 1) / chunks;
-  const int nchunks = (rest + cbpc - 1) / cbpc;
   if (g.bits == 12) {
-    const dim3 grid12(nchunks, g.R_pad / 16);
+    const dim3 grid12(chunks, g.R_pad / 16);
     if (g.K == 64)
       hipLaunchKernelGGL(k_search_direct_12<64>, grid12, dim3(256), 0, st, g,
-                         b, first_block, cbpc);
+                         b);
     else
       hipLaunchKernelGGL(k_search_direct_12<16>, grid12, dim3(256), 0, st, g,
-                         b, first_block, cbpc);
+                         b);
     return hipGetLastError();
   }
-  dim3 grid(nchunks, g.R_pad / kDirectRangesPerWG);
+  dim3 grid(chunks, g.R_pad / kDirectRangesPerWG);
   if (g.K == 64)
-    hipLaunchKernelGGL(k_search_direct_u8<64>, grid, dim3(256), 0, st, g, b,
-                       first_block, cbpc);
+    hipLaunchKernelGGL(k_search_direct_u8<64>, grid, dim3(256), 0, st, g, b);
   else
-    hipLaunchKernelGGL(k_search_direct_u8<16>, grid, dim3(256), 0, st, g, b,
-                       first_block, cbpc);
+    hipLaunchKernelGGL(k_search_direct_u8<16>, grid, dim3(256), 0, st, g, b);
   return hipGetLastError();
 }
 

@@ -2,6 +2,8 @@
 every entry point declared in include/fic.h, and rejects bad arguments with
 the documented status codes before touching the GPU."""
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -49,7 +51,8 @@ def test_query_counts_and_workspace():
     (dict(height=500), 1), (dict(width=0), 1), (dict(domain_step=0), 1),
     (dict(range_size=3, height=63, width=63), 2), (dict(bit_depth=10), 2),
     (dict(s_bits=0), 2), (dict(s_bits=9), 2), (dict(o_bits=10), 2),
-    (dict(height=8, width=8), 1),
+    (dict(bit_depth=12, o_bits=9), 2),   # offset indices are one byte
+    (dict(height=8, width=8), 1), (dict(full_search=2), 1), (dict(full_search=-1), 1),
 ])
 def test_query_rejects(kw, status):
     base = dict(height=512, width=512, bit_depth=8, range_size=8, domain_step=4)
@@ -245,7 +248,55 @@ def test_search_counts_validation():
     assert L.fic_search_counts(ctypes.byref(p), None, ws, ctypes.byref(nr), ctypes.byref(nd)) == 1
     assert L.fic_search_counts(ctypes.byref(p), fake, ws, None, ctypes.byref(nd)) == 1
     assert L.fic_search_counts(ctypes.byref(p), fake, 16, ctypes.byref(nr), ctypes.byref(nd)) == 1
-    pd = F.Params(64, 64, 8, 8, 4, method=F.METHOD_DIRECT).c()
-    assert L.fic_search_counts(ctypes.byref(pd), fake, ws, ctypes.byref(nr), ctypes.byref(nd)) == 2
+    pd = F.Params(64, 64, 8, 8, 4, method=F.METHOD_DIRECT, full_search=3).c()
+    assert L.fic_search_counts(ctypes.byref(pd), fake, ws, ctypes.byref(nr), ctypes.byref(nd)) == 1
     p12 = F.Params(64, 64, 12, 8, 4).c()  # 12-bit: validated like 8-bit
     assert L.fic_search_counts(ctypes.byref(p12), fake, 16, ctypes.byref(nr), ctypes.byref(nd)) == 1
+
+
+@pytest.mark.parametrize("H,W,bits,n,step,sb,ob", [(64, 64, 8, 4, 4, 5, 7), (512, 512, 8, 8, 4, 5, 7),
+                                                   (512, 512, 12, 8, 2, 5, 7), (40, 56, 8, 4, 3, 3, 6)])
+def test_stream_query_and_header_match_the_oracle_format(H, W, bits, n, step, sb, ob):
+    """The library's stream size and header parsing agree with the oracle's
+    writer of the same format (host only)."""
+    from oracle import oracle as O
+    p = F.Params(H, W, bits, n, step, s_bits=sb, o_bits=ob)
+    nb, B = F.stream_query(p)
+    assert nb == O.stream_bytes(H, W, n, step, sb, ob)
+    assert B == O.stream_domain_bits(O.n_domains(H, W, n, step)) + 3 + sb + ob
+    R = (H // n) * (W // n)
+    zero = dict(domain=np.zeros(R, np.int32), iso=np.zeros(R, np.uint8),
+                s_idx=np.zeros(R, np.uint8), o_idx=np.zeros(R, np.uint8))
+    data = O.stream_pack(H, W, n, step, zero, bits=bits, s_bits=sb, o_bits=ob)
+    q = F.stream_header(data.tobytes())
+    assert (q.height, q.width, q.bit_depth, q.range_size, q.domain_step, q.s_bits, q.o_bits) == \
+        (H, W, bits, n, step, sb, ob)
+
+
+def test_stream_header_rejects_foreign_or_inconsistent_headers():
+    from oracle import oracle as O
+    R = 256
+    zero = dict(domain=np.zeros(R, np.int32), iso=np.zeros(R, np.uint8),
+                s_idx=np.zeros(R, np.uint8), o_idx=np.zeros(R, np.uint8))
+    good = O.stream_pack(64, 64, 4, 4, zero).tobytes()
+    for at, val in [(0, ord("X")), (12, 9), (13, 3), (20, 7), (24, 5), (14, 0)]:
+        bad = bytearray(good)
+        bad[at] = val
+        with pytest.raises(F.FicError) as e:
+            F.stream_header(bytes(bad))
+        assert e.value.status in (1, 2)
+    with pytest.raises(F.FicError):
+        F.stream_header(good[:16])
+
+
+def test_stream_pack_and_unpack_validate_before_gpu_work():
+    L = F.lib()
+    p = F.Params(64, 64, 8, 4, 4).c()
+    fake = ctypes.c_void_p(1 << 20)
+    nb = F.stream_query(F.Params(64, 64, 8, 4, 4))[0]
+    assert L.fic_stream_pack(ctypes.byref(p), None, fake, fake, fake, fake, nb, None) == 1
+    assert L.fic_stream_pack(ctypes.byref(p), fake, fake, fake, fake, ctypes.c_void_p((1 << 20) + 2),
+                             nb, None) == 1
+    assert L.fic_stream_pack(ctypes.byref(p), fake, fake, fake, fake, fake, nb - 4, None) == 3
+    assert L.fic_stream_unpack(ctypes.byref(p), fake, nb - 4, fake, fake, fake, fake, None) == 1
+    assert L.fic_stream_unpack(ctypes.byref(p), None, nb, fake, fake, fake, fake, None) == 1

@@ -40,22 +40,61 @@ def test_small_uneven_batch_matches_single_and_oracle():
     assert np.all(ticks[1:] >= ticks[0]) and np.all(ticks[1:] > 0)
 
 
-def test_uneven_batch_of_64_slices_matches_single():
+@pytest.mark.parametrize("full", [0, 1])
+def test_uneven_batch_of_64_slices_matches_oracle_and_single(full):
+    """The 64-slice workload (sides drawn from {256, ..., 512}, 8x8 ranges,
+    16x16 domains at stride 8): every range of the first slice of each side
+    length (the smallest and largest among them) against the oracle, and
+    every slice against its single-image encode."""
     sides = batch_sides(64)
     imgs = [gen_image(s, s, 8, 4000 + i) for i, s in enumerate(sides)]
-    params = [F.Params(s, s, 8, 8, 8) for s in sides]
+    params = [F.Params(s, s, 8, 8, 8, full_search=full) for s in sides]
     b = F.Batch([torch.from_numpy(im).cuda() for im in imgs], params)
     codes = b.run()
     torch.cuda.synchronize()
+    got = [{k: codes[i][k].cpu().numpy() for k in KEYS} for i in range(64)]
+    firsts = sorted({s: i for i, s in reversed(list(enumerate(sides)))}.values())
+    assert {sides[i] for i in firsts} == set(sides) and len(firsts) >= 2
+    for i in firsts:
+        assert_codes(got[i], O.encode(imgs[i], 8, 8), f"slice {i} ({sides[i]}^2) oracle")
     for i in range(64):
+        assert_codes(got[i], single(imgs[i], params[i]), f"slice {i}")
+
+
+def test_batch_of_4x4_range_slices_matches_oracle():
+    """4x4 ranges take the batched search's K = 16 kernel, the seed pass and
+    the range operand written by the batched preparation."""
+    shapes = [(64, 64, 4), (96, 80, 2), (48, 64, 4), (128, 96, 8)]
+    imgs = [gen_image(h, w, 8, 110 + i) for i, (h, w, _) in enumerate(shapes)]
+    params = [F.Params(h, w, 8, 4, st) for (h, w, st) in shapes]
+    b = F.Batch([torch.from_numpy(im).cuda() for im in imgs], params)
+    codes = b.run()
+    torch.cuda.synchronize()
+    for i, (im, p) in enumerate(zip(imgs, params)):
         got = {k: codes[i][k].cpu().numpy() for k in KEYS}
-        assert_codes(got, single(imgs[i], params[i]), f"slice {i}")
-    # oracle on sampled ranges of the smallest and largest slices
-    for i in (int(np.argmin(sides)), int(np.argmax(sides))):
-        R = (sides[i] // 8) ** 2
-        rs = np.unique(np.r_[0, R - 1, np.arange(0, R, R // 8)])
-        ora = O.encode_ranges(imgs[i], 8, 8, rs)
-        assert_codes({k: codes[i][k].cpu().numpy()[rs] for k in KEYS}, ora, f"slice {i} oracle")
+        assert_codes(got, O.encode(im, 4, p.domain_step), f"n=4 slice {i} oracle")
+        assert_codes(got, single(im, p), f"n=4 slice {i}")
+
+
+def test_batch_with_a_misaligned_slice_matches_oracle():
+    """An 8x8-range slice whose pixels are not 8-byte aligned cannot build
+    its range fragments from the image; the batched preparation writes its
+    range operand instead.  Its neighbours stay on the pixel path."""
+    shapes = [(96, 128, 4), (64, 64, 8), (128, 96, 4)]
+    imgs = [gen_image(h, w, 8, 120 + i) for i, (h, w, _) in enumerate(shapes)]
+    params = [F.Params(h, w, 8, 8, st) for (h, w, st) in shapes]
+    h, w = shapes[0][:2]
+    buf = torch.zeros(h * w + 8, dtype=torch.uint8, device="cuda")
+    view = buf[3:3 + h * w].view(h, w)
+    view.copy_(torch.from_numpy(imgs[0]))
+    assert view.data_ptr() % 8 != 0
+    dev_imgs = [view] + [torch.from_numpy(im).cuda() for im in imgs[1:]]
+    b = F.Batch(dev_imgs, params)
+    codes = b.run()
+    torch.cuda.synchronize()
+    for i, (im, p) in enumerate(zip(imgs, params)):
+        got = {k: codes[i][k].cpu().numpy() for k in KEYS}
+        assert_codes(got, O.encode(im, 8, p.domain_step), f"slice {i} oracle")
 
 
 def test_graph_replay_matches_eager():

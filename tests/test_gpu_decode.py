@@ -34,6 +34,70 @@ def test_decode_matches_oracle(H, W, n, step):
     assert np.abs(traj - ref).max() <= 1e-3
 
 
+def test_decode_and_adjoint_256_workload_match_oracle():
+    """The 256x256 workload (4x4 ranges, 8x8 domains at stride 4, T = 12 from
+    128): the oracle's codes decoded on the GPU against the FP64 decoder,
+    every pixel of every iterate, and the adjoint against the FP64 gradient
+    and central differences of the FP64 decoder."""
+    H = W = 256
+    n, step, T = 4, 4, 12
+    img, d, k, s, o = codes_for(H, W, n, step, 5)
+    p = F.Params(H, W, 8, n, step)
+    dd, kd = dev(d, torch.int32), dev(k, torch.uint8)
+    sd, od = dev(s, torch.float32), dev(o, torch.float32)
+    traj = F.decode(dd, kd, sd, od, p, T, 128.0)
+    ref = O.decode(H, W, n, step, d, k, s, o, T, 128.0)
+    assert np.abs(traj.cpu().numpy() - ref).max() <= 1e-3
+    target = img.astype(np.float64)
+    g = 2.0 * (traj[-1] - torch.from_numpy(target).float().cuda()) / (H * W)
+    gs, go = F.decode_backward(dd, kd, sd, od, traj, g, p)
+    gs, go = gs.cpu().numpy().astype(np.float64), go.cpu().numpy().astype(np.float64)
+    rg = 2.0 * (ref[-1] - target) / (H * W)
+    rs, ro = O.decode_backward(H, W, n, step, d, k, s, o, T, ref, rg)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(gs, rs) <= 1e-4 and rel(go, ro) <= 1e-4
+    rng = np.random.default_rng(6)
+    idx = rng.choice(len(s), 64, replace=False)
+    loss = lambda ss, oo: (((O.decode(H, W, n, step, d, k, ss, oo, T, 128.0)[-1] - target) ** 2).mean())
+    fs, fo = [], []
+    for r in idx:
+        sp, sm = s.copy(), s.copy(); sp[r] += 1e-4; sm[r] -= 1e-4
+        fs.append((loss(sp, o) - loss(sm, o)) / 2e-4)
+        op, om = o.copy(), o.copy(); op[r] += 1e-2; om[r] -= 1e-2
+        fo.append((loss(s, op) - loss(s, om)) / 2e-2)
+    assert rel(gs[idx], np.array(fs)) <= 1e-3 and rel(go[idx], np.array(fo)) <= 1e-3
+
+
+@pytest.mark.parametrize("num,den", [(1, 2), (2, 1), (4, 1), (1, 1)])
+def test_decode_scaled_matches_oracle(num, den):
+    """The 256x256 workload's codes (4x4 ranges, 8x8 domains at stride 4)
+    decoded at 1/2, 2 and 4 times the size, every pixel of every iterate
+    against the FP64 oracle; the 1x case equals fic_decode bit for bit."""
+    H = W = 256
+    n, step, T = 4, 4, 12
+    img, d, k, s, o = codes_for(H, W, n, step, 5)
+    p = F.Params(H, W, 8, n, step)
+    dd, kd = dev(d, torch.int32), dev(k, torch.uint8)
+    sd, od = dev(s, torch.float32), dev(o, torch.float32)
+    traj = F.decode_scaled(dd, kd, sd, od, p, (num, den), T, 128.0).cpu().numpy()
+    ref = O.decode_scaled(H, W, n, step, num, den, d, k, s, o, T, 128.0)
+    assert traj.shape == ref.shape == (T + 1, H * num // den, W * num // den)
+    assert np.abs(traj - ref).max() <= 1e-3
+    if num == den:
+        base = F.decode(dd, kd, sd, od, p, T, 128.0).cpu().numpy()
+        assert np.array_equal(traj, base)
+
+
+def test_decode_scaled_rejects_fractional_pixels():
+    p = F.Params(64, 64, 8, 4, 4)
+    z = torch.zeros(256, dtype=torch.int32, device="cuda")
+    u = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    f = torch.zeros(256, dtype=torch.float32, device="cuda")
+    for scale in [(1, 8), (1, 3), (3, 8), (0, 1)]:
+        with pytest.raises((F.FicError, ValueError)):
+            F.decode_scaled(z, u, f, f, p, scale, 2, 128.0)
+
+
 def test_backward_matches_fp64_gradient_and_fd():
     H = W = 64
     n, step, T = 4, 4, 12

@@ -14,9 +14,9 @@ KEYS = ("domain", "iso", "s_idx", "o_idx", "err")
 METHODS = [F.METHOD_MFMA, F.METHOD_DIRECT]
 
 
-def gpu_encode(img, n, step, bits, method, ranges=None):
+def gpu_encode(img, n, step, bits, method, ranges=None, full=0):
     H, W = img.shape
-    p = F.Params(H, W, bits, n, step, method=method)
+    p = F.Params(H, W, bits, n, step, method=method, full_search=full)
     dt = torch.uint8 if bits == 8 else torch.int16
     t = torch.from_numpy(np.ascontiguousarray(img).astype(np.uint8 if bits == 8 else np.int16)).to("cuda")
     out = F.encode(t, p)
@@ -36,13 +36,15 @@ def assert_same(gpu, ora, label=""):
                                  + ", ".join(f"{q}={gpu[q][i]}/{ora[q][i]}" for q in KEYS))
 
 
+@pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS)
-def test_plain_64x64_config(method):
+def test_plain_64x64_config(method, full):
     # 64x64 u8, 4x4 ranges, 8x8 domains at stride 4: the plain full-search setup
     img = gen_image(64, 64, 8, 1)
-    assert_same(gpu_encode(img, 4, 4, 8, method), O.encode(img, 4, 4), "plain64")
+    assert_same(gpu_encode(img, 4, 4, 8, method, full=full), O.encode(img, 4, 4), "plain64")
 
 
+@pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("H,W,n,step,seed", [
     (96, 80, 4, 2, 11),     # 480 ranges (ragged tile), 1665 domains (ragged block)
@@ -51,18 +53,22 @@ def test_plain_64x64_config(method):
     (8, 8, 4, 4, 14),       # smallest image: 4 ranges, one domain
     (16, 64, 8, 1, 15),     # one domain row, stride 1
 ])
-def test_parity_small_images(method, H, W, n, step, seed):
+def test_parity_small_images(method, H, W, n, step, seed, full):
     img = gen_image(H, W, 8, seed)
-    assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), f"{H}x{W}")
+    assert_same(gpu_encode(img, n, step, 8, method, full=full), O.encode(img, n, step),
+                f"{H}x{W}")
 
 
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("bits", [8, 12])
-def test_search_visits_exactly_the_ranges_and_domains_with_variance(bits):
-    """The matrix-core searches skip flat ranges and flat domains (their
-    outcome is fixed); the counts they report match a direct count."""
+def test_search_visits_exactly_the_ranges_and_domains_with_variance(bits, method, full):
+    """Without full_search both searches skip flat ranges and flat domains
+    (their outcome is fixed); with it they visit every range and domain.  The
+    counts they report match a direct count."""
     H, W, n, step = 128, 96, 8, 4
     img = gen_image(H, W, bits, 19)
-    p = F.Params(H, W, bits, n, step)
+    p = F.Params(H, W, bits, n, step, method=method, full_search=full)
     host = img.astype(np.uint8 if bits == 8 else np.int16)
     out = F.encode(torch.from_numpy(host).cuda(), p)
     nr, nd = F.search_counts(out, p)
@@ -73,8 +79,11 @@ def test_search_visits_exactly_the_ranges_and_domains_with_variance(bits):
              .reshape(n, 2, n, 2).astype(np.int64).sum(axis=(1, 3))
              for y in range(ny) for x in range(nx)]
     want_d = sum(int(c.max() != c.min()) for c in cells)
-    assert (nr, nd) == (want_r, want_d)
-    assert 0 < nr < len(blocks) and 0 < nd < ny * nx   # the image has background
+    assert 0 < want_r < len(blocks) and 0 < want_d < ny * nx   # the image has background
+    if full:
+        assert (nr, nd) == (len(blocks), ny * nx)
+    else:
+        assert (nr, nd) == (want_r, want_d)
     assert_same({k: out[k].cpu().numpy() for k in KEYS}, O.encode(img, n, step, bits=bits),
                 f"counts image {bits}-bit")
 
@@ -100,9 +109,10 @@ def test_unaligned_image_takes_range_operand_path():
     assert_same(res[1], ora, "unaligned")
 
 
+@pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("kind", ["zeros", "const", "max", "checker", "noise", "levels"])
-def test_parity_degenerate_images(method, kind):
+def test_parity_degenerate_images(method, kind, full):
     H = W = 48
     rng = np.random.default_rng(5)
     img = {"zeros": np.zeros((H, W)), "const": np.full((H, W), 101),
@@ -111,7 +121,7 @@ def test_parity_degenerate_images(method, kind):
            "noise": rng.integers(0, 256, (H, W)),
            "levels": rng.integers(0, 3, (H, W)) * 85}[kind].astype(np.uint8)
     for (n, step) in [(4, 4), (8, 2)]:
-        assert_same(gpu_encode(img, n, step, 8, method), O.encode(img, n, step), kind)
+        assert_same(gpu_encode(img, n, step, 8, method, full=full), O.encode(img, n, step), kind)
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -127,30 +137,34 @@ def test_planted_codes(method):
         assert gpu["err"][r] == 0.0 and gpu["domain"][r] == dy * nx + dx and gpu["iso"][r] == k
 
 
-def _sample_ranges(R, seed, count):
-    rng = np.random.default_rng(seed)
-    return np.unique(np.concatenate([[0, R - 1], np.arange(0, R, R // 32), rng.integers(0, R, count)]))
+# Oracle tables of the full-size workloads, computed once per session (the
+# oracle is plain C over all host threads: ~5 s for 512x512 u8 at stride 4,
+# ~20 s for 512x512 12-bit at stride 2 on 16 threads).
+_ORACLE = {}
 
 
-def test_u8_512_full_size_sampled_and_methods_agree():
-    # 512x512 u8, 8x8 ranges, 16x16 domains at stride 4 (4096 x 125,000 candidates)
+def oracle_table(key, img, n, step, bits=8):
+    if key not in _ORACLE:
+        _ORACLE[key] = O.encode(img, n, step, bits=bits)
+    return _ORACLE[key]
+
+
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("method", METHODS)
+def test_u8_512_every_range_matches_oracle(method, full):
+    # 512x512 u8, 8x8 ranges, 16x16 domains at stride 4 (4096 x 125,000
+    # candidates): all 4096 codes element by element
     img = gen_image(512, 512, 8, 2)
-    mf = gpu_encode(img, 8, 4, 8, F.METHOD_MFMA)
-    di = gpu_encode(img, 8, 4, 8, F.METHOD_DIRECT)
-    assert_same(mf, di, "mfma-vs-direct")
-    rs = _sample_ranges(4096, 0, 96)
-    ora = O.encode_ranges(img, 8, 4, rs)
-    assert_same({k: mf[k][rs] for k in KEYS}, ora, "u8_512 sampled")
+    got = gpu_encode(img, 8, 4, 8, method, full=full)
+    assert_same(got, oracle_table("u8_512", img, 8, 4), f"u8_512 method {method} full {full}")
 
 
-def test_decode_workload_encode_sampled():
+@pytest.mark.parametrize("full", [0, 1])
+def test_decode_workload_encode_matches_oracle(full):
     # 256x256 u8, 4x4 ranges, 8x8 domains at stride 4
     img = gen_image(256, 256, 8, 5)
-    mf = gpu_encode(img, 4, 4, 8, F.METHOD_MFMA)
-    rs = _sample_ranges(4096, 1, 64)
-    ora = O.encode(img, 4, 4)
-    assert_same({k: mf[k][rs] for k in KEYS}, {k: ora[k][rs] for k in KEYS}, "decode256")
-    assert_same(mf, ora, "decode256 full")
+    got = gpu_encode(img, 4, 4, 8, F.METHOD_MFMA, full=full)
+    assert_same(got, oracle_table("u8_256_n4", img, 4, 4), "decode256")
 
 
 def test_deterministic_repeat():
@@ -162,27 +176,31 @@ def test_deterministic_repeat():
 
 # --- 12-bit images: hi/lo split contraction ---------------------------------
 
+@pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("H,W,n,step,seed", [
     (48, 64, 4, 2, 41),     # 192 ranges, ragged tiles
     (64, 64, 8, 4, 42),
     (40, 56, 4, 3, 43),
 ])
-def test_parity_12bit_small(method, H, W, n, step, seed):
+def test_parity_12bit_small(method, H, W, n, step, seed, full):
     img = gen_image(H, W, 12, seed)
-    assert_same(gpu_encode(img, n, step, 12, method), O.encode(img, n, step, bits=12), f"12b {H}x{W}")
+    assert_same(gpu_encode(img, n, step, 12, method, full=full), O.encode(img, n, step, bits=12),
+                f"12b {H}x{W}")
 
 
+@pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS)
 @pytest.mark.parametrize("kind", ["zeros", "max", "noise", "checker"])
-def test_parity_12bit_degenerate(method, kind):
+def test_parity_12bit_degenerate(method, kind, full):
     H = W = 48
     rng = np.random.default_rng(7)
     img = {"zeros": np.zeros((H, W)), "max": np.full((H, W), 4095),
            "noise": rng.integers(0, 4096, (H, W)),
            "checker": (np.indices((H, W)).sum(0) % 2) * 4095}[kind].astype(np.uint16)
     for (n, step) in [(4, 4), (8, 2)]:
-        assert_same(gpu_encode(img, n, step, 12, method), O.encode(img, n, step, bits=12), kind)
+        assert_same(gpu_encode(img, n, step, 12, method, full=full),
+                    O.encode(img, n, step, bits=12), kind)
 
 
 @pytest.mark.parametrize("method", METHODS)
@@ -199,12 +217,12 @@ def test_planted_codes_12bit(method):
         assert gpu["err"][r] == 0.0 and gpu["domain"][r] == dy * nx + dx and gpu["iso"][r] == k
 
 
-def test_ct12_512_full_size_sampled_and_methods_agree():
-    # 512x512 12-bit, 8x8 ranges, 16x16 domains at stride 2 (4096 x 496,008 candidates)
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("method", METHODS)
+def test_ct12_512_every_range_matches_oracle(method, full):
+    # 512x512 12-bit, 8x8 ranges, 16x16 domains at stride 2 (4096 x 496,008
+    # candidates): all 4096 codes element by element
     img = gen_image(512, 512, 12, 3)
-    mf = gpu_encode(img, 8, 2, 12, F.METHOD_MFMA)
-    di = gpu_encode(img, 8, 2, 12, F.METHOD_DIRECT)
-    assert_same(mf, di, "12b mfma-vs-direct")
-    rs = _sample_ranges(4096, 2, 16)
-    ora = O.encode_ranges(img, 8, 2, rs, bits=12)
-    assert_same({k: mf[k][rs] for k in KEYS}, ora, "ct12_512 sampled")
+    got = gpu_encode(img, 8, 2, 12, method, full=full)
+    assert_same(got, oracle_table("ct12_512", img, 8, 2, bits=12),
+                f"ct12_512 method {method} full {full}")

@@ -1,0 +1,82 @@
+"""fic_encode_noalloc (scratch in the library's static device array) against
+fic_encode (scratch in a caller workspace): identical codes, element by
+element, on consecutive calls that reuse the same array with shrinking
+inputs."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1404_0774_amd as F
+from paper_1404_0774_amd import _lib
+from oracle import oracle as O
+from fic_inputs import gen_image
+
+pytestmark = pytest.mark.gpu
+KEYS = ("domain", "iso", "s_idx", "o_idx", "err")
+
+
+def new_codes(nr, dev):
+    return dict(domain=torch.full((nr,), -7, dtype=torch.int32, device=dev),
+                iso=torch.full((nr,), 99, dtype=torch.uint8, device=dev),
+                s_idx=torch.full((nr,), 99, dtype=torch.uint8, device=dev),
+                o_idx=torch.full((nr,), 99, dtype=torch.uint8, device=dev),
+                err=torch.full((nr,), -1.0, dtype=torch.float64, device=dev))
+
+
+def encode_noalloc(img, p):
+    """One fic_encode_noalloc call through the C ABI; returns device codes."""
+    dev = img.device
+    out = new_codes(F.query(p)[0], dev)
+    codes = _lib._Codes(*[out[k].data_ptr() for k in KEYS])
+    cp = p.c()
+    L = F.lib()
+    st = L.fic_encode_noalloc(ctypes.byref(cp), ctypes.c_void_p(img.data_ptr()), codes,
+                              _lib._stream(dev))
+    assert st == 0, L.fic_last_error().decode()
+    return out
+
+
+def host(out):
+    return {k: out[k].cpu().numpy() for k in KEYS}
+
+
+def device_image(H, W, bits, seed):
+    a = gen_image(H, W, bits, seed)
+    t = torch.from_numpy(a.astype(np.uint8 if bits == 8 else np.int16)).cuda()
+    return a, (t if bits == 8 else t.view(torch.uint16))
+
+
+def test_noalloc_matches_workspace_encode_on_consecutive_calls():
+    # largest first (512x512 12-bit at stride 2: 25.7 MiB of the 32 MiB),
+    # then smaller inputs that leave the first call's bytes in the array
+    cases = [(512, 512, 12, 8, 2, 0, 3), (512, 512, 8, 8, 4, 1, 2),
+             (512, 512, 8, 8, 4, 0, 2), (96, 80, 8, 4, 2, 0, 11)]
+    for (H, W, bits, n, step, full, seed) in cases:
+        a, img = device_image(H, W, bits, seed)
+        p = F.Params(H, W, bits, n, step, full_search=full)
+        got = host(encode_noalloc(img, p))
+        ref = host(F.encode(img, p))
+        torch.cuda.synchronize()
+        for k in KEYS:
+            assert np.array_equal(got[k], ref[k]), f"{H}x{W} {bits}-bit n={n}: {k}"
+        if H * W <= 96 * 80:
+            ora = O.encode(a, n, step, bits=bits)
+            for k in KEYS:
+                assert np.array_equal(got[k], ora[k]), f"{H}x{W} oracle: {k}"
+
+
+def test_noalloc_rejects_parameters_beyond_the_array():
+    p = F.Params(1024, 1024, 12, 8, 4)           # needs 50.6 MiB
+    assert F.query(p)[2] > (32 << 20)
+    img = torch.zeros((1024, 1024), dtype=torch.uint16, device="cuda")
+    out = new_codes(F.query(p)[0], img.device)
+    codes = _lib._Codes(*[out[k].data_ptr() for k in KEYS])
+    cp = p.c()
+    L = F.lib()
+    assert L.fic_encode_noalloc(ctypes.byref(cp), ctypes.c_void_p(img.data_ptr()), codes,
+                                _lib._stream(img.device)) == 3
+    assert b"static scratch" in L.fic_last_error()
+    torch.cuda.synchronize()
+    assert int(out["domain"].min()) == -7       # nothing was enqueued
