@@ -150,13 +150,15 @@ int fic_search_counts(const fic_params *p, const void *workspace,
  *   code arrays, as in fic_encode.  Call it whenever the slice shapes or
  *   pointers change, outside any stream capture.
  * fic_encode_batch -- enqueues the batch on `stream`: one launch per phase
- *   for all slices (operand preparation, seed pass, search, code
- *   extraction); the search runs as a persistent grid that takes work items
- *   from a device counter.  It performs no allocation and no host-device
- *   copy, so a stream capture of it can be replayed as a graph.  `ticks`
- *   (device, n_slices + 1 entries, may be NULL) receives the GPU's 100 MHz
- *   clock at the start of the search ([0]) and when each slice's search
- *   finished ([1 + s]).  Codes equal those of fic_encode per slice.
+ *   for all slices (operand preparation, list compaction, seed pass,
+ *   search); the search runs as a persistent grid that takes work items
+ *   from a device counter, and extracts each slice's codes as soon as that
+ *   slice's search is complete, while later slices are still searched.  It
+ *   performs no allocation and no host-device copy, so a stream capture of
+ *   it can be replayed as a graph.  `ticks` (device, n_slices + 1 entries,
+ *   may be NULL) receives the GPU's 100 MHz clock at the start of the search
+ *   ([0]) and when each slice's codes were written ([1 + s]).  Codes equal
+ *   those of fic_encode per slice.
  * Errors: FIC_E_INVALID, FIC_E_UNSUPPORTED (not 8-bit; slice geometry as in
  * fic_query), FIC_E_WORKSPACE, FIC_E_HIP.
  */
@@ -181,6 +183,20 @@ int fic_encode_batch(const fic_params *slices, int32_t n_slices,
 int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
                const float *s, const float *o, int32_t iters, float x0,
                float *traj, void *stream);
+
+/*
+ * fic_decode_batch -- fic_decode of n_images images that share `p` (size,
+ * range size, domain grid), each with its own codes, one launch per
+ * iteration for the whole batch.  Codes are packed image after image
+ * (domain[b * n_ranges + r], likewise iso, s, o); traj receives image b's
+ * trajectory at traj + b * (iters + 1) * height * width, laid out as
+ * fic_decode's.  Errors: FIC_E_INVALID (null pointers, iters < 0,
+ * n_images < 1), FIC_E_UNSUPPORTED (more than 2^31 pixels in one iterate).
+ */
+int fic_decode_batch(const fic_params *p, int32_t n_images,
+                     const int32_t *domain, const uint8_t *iso,
+                     const float *s, const float *o, int32_t iters, float x0,
+                     float *traj, void *stream);
 
 /*
  * fic_decode_scaled -- fic_decode at another resolution.  A range's code

@@ -93,6 +93,8 @@ def lib():
         L.fic_encode.argtypes = [P, vp, _Codes, vp, sz, vp]
         L.fic_decode.restype = ctypes.c_int
         L.fic_decode.argtypes = [P, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.fic_decode_batch.restype = ctypes.c_int
+        L.fic_decode_batch.argtypes = [P, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.fic_decode_scaled.restype = ctypes.c_int
         L.fic_decode_scaled.argtypes = [P, i32, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.fic_stream_query.restype = ctypes.c_int
@@ -361,6 +363,22 @@ def decode(domain, iso, s, o, p: Params, iters=12, x0=None):
                             _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
                             _dev_ptr(o, torch.float32, "o"), iters, ctypes.c_float(x0),
                             traj.data_ptr(), _stream(dev)))
+    return traj
+
+
+def decode_batch(domain, iso, s, o, p: Params, iters=12, x0=None):
+    """Decode B images of one geometry, each with its own codes (tensors of
+    shape (B, n_ranges)); returns the trajectories (B, iters+1, H, W)."""
+    if x0 is None:
+        x0 = float(2 ** (p.bit_depth - 1))
+    B = domain.shape[0]
+    dev = s.device
+    traj = torch.empty((B, iters + 1, p.height, p.width), dtype=torch.float32, device=dev)
+    cp = p.c()
+    _check(lib().fic_decode_batch(ctypes.byref(cp), B, _dev_ptr(domain, torch.int32, "domain"),
+                                  _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
+                                  _dev_ptr(o, torch.float32, "o"), iters, ctypes.c_float(x0),
+                                  traj.data_ptr(), _stream(dev)))
     return traj
 
 

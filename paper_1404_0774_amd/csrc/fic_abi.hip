@@ -376,6 +376,26 @@ int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   return ok();
 }
 
+int fic_decode_batch(const fic_params *p, int32_t n_images,
+                     const int32_t *domain, const uint8_t *iso,
+                     const float *s, const float *o, int32_t iters, float x0,
+                     float *traj, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !traj)
+    return fail(FIC_E_INVALID, "null code or trajectory pointer");
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  if (n_images < 1) return fail(FIC_E_INVALID, "n_images %d < 1", n_images);
+  if ((long long)g.H * g.W * n_images > (1ll << 31))
+    return fail(FIC_E_UNSUPPORTED, "%d images of %dx%d exceed 2^31 pixels",
+                n_images, g.H, g.W);
+  hipError_t e = launch_decode_batch(g, n_images, domain, iso, s, o, iters, x0,
+                                     traj, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_batch");
+  return ok();
+}
+
 int fic_decode_scaled(const fic_params *p, int32_t scale_num,
                       int32_t scale_den, const int32_t *domain,
                       const uint8_t *iso, const float *s, const float *o,

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "fic_internal.h"
@@ -15,15 +16,20 @@ namespace {
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// Code-extraction work items: this many workgroup passes of 256 lanes each
+// (a range per N lanes: 32 ranges a pass for 8x8 ranges).
+constexpr int kFinPasses = 4;
+
 struct BatchPlan {
   std::vector<Geo> geo;
   std::vector<Tune> tune;
   std::vector<int4> items;
   std::vector<int2> wg_map;          // [sum of phase_total]
-  std::vector<int> items_per_slice;  // [n]
+  std::vector<int> items_per_slice;  // [n] search items
+  std::vector<int> fin_per_slice;    // [n] code-extraction items
   std::vector<size_t> slice_off;     // workspace offset of each slice
-  size_t off_tab, off_items, off_map, off_ips, off_rem, off_counter,
-      off_ticks, total;
+  size_t off_tab, off_items, off_map, off_ips, off_fps, off_rem, off_frem,
+      off_counter, off_ticks, total;
   int phase_total[4], phase_base[4];
 };
 
@@ -58,18 +64,43 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return cost[a] > cost[b]; });
-  pl.items.clear();
+  std::vector<int4> search;
   pl.items_per_slice.assign(n, 0);
+  std::vector<int> last(n, 0);  // position of each slice's last search item
   for (int s : order) {
     const Geo &g = pl.geo[s];
     const Tune &t = pl.tune[s];
     const int rg = g.R_pad / kMfmaRangesPerWG;
     for (int c0 = 0; c0 < g.NCB; c0 += t.item_blocks)
       for (int r = 0; r < rg; ++r) {
-        pl.items.push_back(int4{s, r, c0, std::min(c0 + t.item_blocks, g.NCB)});
+        last[s] = (int)search.size();
+        search.push_back(int4{s, r, c0, std::min(c0 + t.item_blocks, g.NCB)});
         ++pl.items_per_slice[s];
       }
   }
+  // A slice's code-extraction items follow its last search item by one grid
+  // of items, so that the workgroup taking one rarely waits for the search
+  // items still running; they run while later slices are searched.
+  std::vector<std::pair<long long, int4>> ents;
+  for (size_t i = 0; i < search.size(); ++i)
+    ents.push_back({2ll * (long long)i, search[i]});
+  pl.fin_per_slice.assign(n, 0);
+  for (int s = 0; s < n; ++s) {
+    const Geo &g = pl.geo[s];
+    const int passes = (int)(((long long)g.R_pad * g.n + 255) / 256);
+    for (int f = 0; f < passes; f += kFinPasses) {
+      ents.push_back({2ll * (last[s] + kBatchSearchGrid) + 1,
+                      int4{s, -1, f, std::min(kFinPasses, passes - f)}});
+      ++pl.fin_per_slice[s];
+    }
+  }
+  std::stable_sort(ents.begin(), ents.end(),
+                   [](const std::pair<long long, int4> &a,
+                      const std::pair<long long, int4> &b) {
+                     return a.first < b.first;
+                   });
+  pl.items.clear();
+  for (const auto &e : ents) pl.items.push_back(e.second);
 
   pl.wg_map.clear();
   for (int ph = 0; ph < 4; ++ph) {
@@ -81,7 +112,7 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
       if (ph == 0) wg = g.n_dwg;
       if (ph == 1) wg = ((long long)g.R_pad * g.n + 255) / 256;
       if (ph == 2) wg = g.R_pad / 8;
-      if (ph == 3) wg = ((long long)g.R_pad * g.n + 255) / 256;
+      // phase 3 (code extraction) runs inside the search launch
       for (int i = 0; i < (int)wg; ++i) pl.wg_map.push_back(int2{s, i});
       acc += (int)wg;
     }
@@ -93,7 +124,9 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
   pl.off_items = o;   o = a256(o + sizeof(int4) * pl.items.size());
   pl.off_map = o;     o = a256(o + sizeof(int2) * pl.wg_map.size());
   pl.off_ips = o;     o = a256(o + sizeof(int) * n);
+  pl.off_fps = o;     o = a256(o + sizeof(int) * n);
   pl.off_rem = o;     o = a256(o + sizeof(int) * n);
+  pl.off_frem = o;    o = a256(o + sizeof(int) * n);
   pl.off_counter = o; o = a256(o + sizeof(int));
   pl.off_ticks = o;   o = a256(o + sizeof(unsigned long long) * (n + 1));
   pl.slice_off.resize(n);
@@ -112,7 +145,9 @@ BatchDev batch_dev(const BatchPlan &pl, void *ws, int n) {
   bd.items = (int4 *)(w + pl.off_items);
   bd.wg_map = (int2 *)(w + pl.off_map);
   bd.items_per_slice = (int *)(w + pl.off_ips);
+  bd.fin_per_slice = (int *)(w + pl.off_fps);
   bd.remaining = (int *)(w + pl.off_rem);
+  bd.fin_remaining = (int *)(w + pl.off_frem);
   bd.counter = (int *)(w + pl.off_counter);
   bd.ticks = (unsigned long long *)(w + pl.off_ticks);
   bd.n = n;
@@ -179,6 +214,9 @@ int fic_batch_prepare(const fic_params *slices, int32_t n_slices,
   if (e == hipSuccess)
     e = hipMemcpy(w + pl.off_ips, pl.items_per_slice.data(),
                   sizeof(int) * n_slices, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(w + pl.off_fps, pl.fin_per_slice.data(),
+                  sizeof(int) * n_slices, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     char msg[256];
     snprintf(msg, sizeof msg, "batch table upload: %s", hipGetErrorString(e));
@@ -207,7 +245,6 @@ int fic_encode_batch(const fic_params *slices, int32_t n_slices,
   for (const Tune &t : pl.tune) max_seed = std::max(max_seed, t.seed_blocks);
   if (e == hipSuccess) e = launch_seed_batch(bd, max_seed, s);
   if (e == hipSuccess) e = launch_search_batch(bd, s);
-  if (e == hipSuccess) e = launch_finalize_batch(bd, s);
   if (e != hipSuccess) {
     char msg[256];
     snprintf(msg, sizeof msg, "batch launch: %s", hipGetErrorString(e));

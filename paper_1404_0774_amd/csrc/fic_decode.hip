@@ -69,6 +69,40 @@ __global__ void k_decode_step_any(DecGeo d, const int32_t *domain,
   y[p] = fmaf(s[r], u, o[r]);
 }
 
+// Many images of one geometry, each with its own codes: one thread per
+// pixel of the whole batch.  Image b's codes start at entry b R; its
+// trajectory is traj[b][t][pixel] ((iters + 1) images of H W floats each).
+template <int N>
+__global__ __launch_bounds__(256) void k_decode_step_batch(
+    Geo g, long long total, const int32_t *domain, const uint8_t *iso,
+    const float *s, const float *o, float *traj, int t, int iters) {
+  const long long gp = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gp >= total) return;
+  const int HW = g.H * g.W;
+  const long long b = gp / HW;
+  const int p = (int)(gp - b * HW);
+  const int py = p / g.W, px = p % g.W;
+  const int ry = py / N, rx = px / N, i = py % N, j = px % N;
+  const long long r = b * g.R + ry * g.RW + rx;
+  const int d = clamp_dom(domain[r], g.ND);
+  int si, sj;
+  sigma(iso[r], i, j, N - 1, si, sj);
+  const int cy = (d / g.NX) * g.step + 2 * si, cx = (d % g.NX) * g.step + 2 * sj;
+  float *x = traj + (size_t)b * (iters + 1) * HW + (size_t)t * HW;
+  const float *c = x + (size_t)cy * g.W + cx;
+  const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
+  x[HW + p] = fmaf(s[r], u, o[r]);  // the image's iterate t + 1
+}
+
+// traj[b][0] = x0 for every image b.
+__global__ void k_fill_first_batch(float *traj, long long HW, int iters,
+                                   long long total, float v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const long long b = i / HW;
+  traj[b * (iters + 1) * HW + (i - b * HW)] = v;
+}
+
 __global__ void k_fill_f32(float *p, long long n, float v) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -519,6 +553,27 @@ hipError_t launch_decode(const Geo &g, const int32_t *domain,
     else
       hipLaunchKernelGGL(k_decode_step<4>, grid, dim3(bs), 0, st, g, domain,
                          iso, s, o, x, y);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_decode_batch(const Geo &g, int n_images,
+                               const int32_t *domain, const uint8_t *iso,
+                               const float *s, const float *o, int iters,
+                               float x0, float *traj, hipStream_t st) {
+  const long long HW = (long long)g.H * g.W;
+  const long long total = HW * n_images;
+  const int bs = 256;
+  const dim3 grid((unsigned)((total + bs - 1) / bs));
+  hipLaunchKernelGGL(k_fill_first_batch, grid, dim3(bs), 0, st, traj, HW,
+                     iters, total, x0);
+  for (int t = 0; t < iters; ++t) {
+    if (g.n == 8)
+      hipLaunchKernelGGL(k_decode_step_batch<8>, grid, dim3(bs), 0, st, g,
+                         total, domain, iso, s, o, traj, t, iters);
+    else
+      hipLaunchKernelGGL(k_decode_step_batch<4>, grid, dim3(bs), 0, st, g,
+                         total, domain, iso, s, o, traj, t, iters);
   }
   return hipGetLastError();
 }

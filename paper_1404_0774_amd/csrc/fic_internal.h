@@ -99,14 +99,19 @@ struct SliceDesc {
 // Device side of a batch (all pointers into the caller's workspace).
 struct BatchDev {
   SliceDesc *tab;             // [n]
-  int4 *items;                // [n_items]: slice, row group, first block, end
-  int2 *wg_map;               // per phase (domain prep, range prep, seed,
-                              //   finalize) and workgroup: slice and the
-                              //   workgroup's index within the slice
-  int *items_per_slice;       // [n]
+  int4 *items;                // [n_items] work list of the persistent search:
+                              //   search item (slice, row group, first
+                              //   block, end block) or code-extraction item
+                              //   (slice, -1, first workgroup, workgroups)
+  int2 *wg_map;               // per phase (domain prep, range prep, seed)
+                              //   and workgroup: slice and the workgroup's
+                              //   index within the slice
+  int *items_per_slice;       // [n] search items per slice
+  int *fin_per_slice;         // [n] code-extraction items per slice
   int *remaining;             // [n] unfinished search items per slice
-  int *counter;               // [1] next search item
-  unsigned long long *ticks;  // [n + 1] start tick, completion tick per slice
+  int *fin_remaining;         // [n] unfinished code-extraction items
+  int *counter;               // [1] next work item
+  unsigned long long *ticks;  // [n + 1] start tick, codes-ready tick per slice
   int n, n_items;
   int phase_total[4];         // workgroups per phase
   int phase_base[4];          // first entry of each phase in wg_map
@@ -150,6 +155,10 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
                                   const float *o, int iters, const float *traj,
                                   const float *grad_xT, float *grad_s,
                                   float *grad_o, void *ws, hipStream_t st);
+hipError_t launch_decode_batch(const Geo &g, int n_images,
+                               const int32_t *domain, const uint8_t *iso,
+                               const float *s, const float *o, int iters,
+                               float x0, float *traj, hipStream_t st);
 hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
                                 const uint8_t *iso, const float *s,
                                 const float *o, int iters, float x0,
@@ -167,7 +176,6 @@ hipError_t launch_compact(const Geo &g, const EncBufs &b, hipStream_t st);
 hipError_t launch_compact_batch(const BatchDev &bd, hipStream_t st);
 hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st);
 hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st);
-hipError_t launch_finalize_batch(const BatchDev &bd, hipStream_t st);
 size_t refine_ws_bytes(const Geo &g, int iters);
 hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso,
                          float *s, float *o, const void *image, int iters,
@@ -178,6 +186,9 @@ hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso
 constexpr int kMfmaRangesPerWG = 64;  // 4 waves x 4 row blocks x 4 ranges
 constexpr int kMfma12RangesPerWG = 16;
 constexpr int kDirectRangesPerWG = 32;
+// Workgroups of the batched search's persistent grid (about two per compute
+// unit); the work list places code extraction one grid of items behind.
+constexpr int kBatchSearchGrid = 512;
 
 // Launch shape of one encode, resolved from the tuning table (fic_tuning.hip)
 // with the library defaults for anything the table leaves open.  Always

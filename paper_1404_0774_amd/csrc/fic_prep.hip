@@ -5,93 +5,11 @@
 
 #include <type_traits>
 
-#include "fic_device.h"
+#include "fic_finalize.h"
 
 namespace fic {
 
 namespace {
-
-template <typename Pix>
-__device__ __forceinline__ int cell_sum(const Pix *img, int W, int y, int x) {
-  const Pix *p = img + (size_t)y * W + x;
-  return (int)p[0] + (int)p[1] + (int)p[W] + (int)p[W + 1];
-}
-
-// The value of a partner lane inside the lane's row of 16 (DPP, no LDS
-// traffic): CTRL 0xB1 = lane ^ 1, 0x4E = lane ^ 2, 0x141 = mirror within 8,
-// 0x140 = mirror within 16.  Every lane of the row must be active.
-template <int CTRL, typename T>
-__device__ __forceinline__ T dpp_partner(T v) {
-  static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values");
-  if constexpr (sizeof(T) == 4) {
-    const int x = __builtin_bit_cast(int, v);
-    return __builtin_bit_cast(
-        T, __builtin_amdgcn_update_dpp(0, x, CTRL, 0xF, 0xF, false));
-  } else {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, 0xF,
-                                               0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32),
-                                               CTRL, 0xF, 0xF, false);
-    return __builtin_bit_cast(
-        T, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-  }
-}
-
-// Sum over aligned groups of W lanes (W a power of two <= 64), the result in
-// every lane of the group.  Butterfly: after each step every lane holds the
-// sum of its aligned group of twice the size.  Every lane of a group must be
-// active (integer or exactly representable sums, so the order is free).
-template <int W, typename T>
-__device__ __forceinline__ T group_sum(T v) {
-  static_assert(W >= 1 && W <= 64 && (W & (W - 1)) == 0, "power of two");
-  if constexpr (W >= 2) v += dpp_partner<0xB1>(v);
-  if constexpr (W >= 4) v += dpp_partner<0x4E>(v);
-  if constexpr (W >= 8) v += dpp_partner<0x141>(v);
-  if constexpr (W >= 16) v += dpp_partner<0x140>(v);
-  if constexpr (W >= 32) v += __shfl_xor(v, 16);
-  if constexpr (W >= 64) v += __shfl_xor(v, 32);
-  return v;
-}
-
-// The C pixels p[0 .. C) of an image row (C sizeof(Pix) a multiple of 4).
-// wide: p is 4-byte aligned, so the run is read as 32-bit words (four 8-bit
-// or two 16-bit pixels each).
-template <typename Pix, int C>
-__device__ __forceinline__ void load_run(const Pix *p, bool wide, int (&v)[C]) {
-  constexpr int PW = 4 / sizeof(Pix);  // pixels per word
-  static_assert(C % PW == 0, "whole words");
-  if (wide) {
-    const unsigned *w = (const unsigned *)p;
-#pragma unroll
-    for (int q = 0; q < C / PW; ++q) {
-      const unsigned u = w[q];
-#pragma unroll
-      for (int e = 0; e < PW; ++e)
-        v[q * PW + e] = (int)((u >> (8 * sizeof(Pix) * e)) &
-                              ((1u << (8 * sizeof(Pix))) - 1u));
-    }
-  } else {
-#pragma unroll
-    for (int k = 0; k < C; ++k) v[k] = (int)p[k];
-  }
-}
-
-// The 2N pixels of one domain row.
-template <typename Pix, int N>
-__device__ __forceinline__ void load_row(const Pix *p, bool wide,
-                                         int (&v)[2 * N]) {
-  load_run<Pix, 2 * N>(p, wide, v);
-}
-
-// Whether every domain row starts on a 4-byte boundary: the image, its width
-// and the domain step allow it.
-template <typename Pix>
-__device__ __forceinline__ bool domain_rows_aligned(const Geo &g,
-                                                    const Pix *img) {
-  return ((uintptr_t)img & 3) == 0 &&
-         ((g.W | g.step) & (sizeof(Pix) == 1 ? 3 : 1)) == 0;
-}
 
 // One thread per (domain, cell row): N threads per domain, domains in
 // natural order so that the threads of a wave read neighbouring pixels.
@@ -286,100 +204,6 @@ __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
   }
 }
 
-// One group of L lanes per range (L = N or K = N^2), each lane holding K / L
-// consecutive pixels of the range: unpack the winning key and recompute its
-// fit from the image to produce the code (domain, transform, s index, o
-// index, residual).  K lanes suit one image (many short waves), N lanes a
-// batch (a quarter or an eighth of the waves).  Flat domains (no variance) all fit
-// a range with s = 0 and the range mean (eqs. 11-12), so they tie and only
-// the first of them can win; the search skips them and the first one is
-// compared here.
-template <typename Pix, int N, int L>
-__device__ __forceinline__ void finalize_body(const Geo &g, const Pix *img,
-                                              const EncBufs &b,
-                                              const fic_codes &out, int bid) {
-  constexpr int P = N * N / L;  // pixels per lane
-  static_assert(L == N || L == N * N, "a row or a pixel per lane");
-  __shared__ int s_wmin[8];  // per-wave minima of the flat-domain table
-  const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const int slot = (int)(t / L), q0 = (int)(t % L) * P, m = N - 1;
-  const bool live = slot < g.R_pad;
-  const int r = live ? range_of_slot(g, slot) : g.R;  // image range
-  // independent loads first: the key, the range sums, the flat-domain table
-  unsigned long long key = ~0ull;
-  double Sb0 = 0.0, Sbb0 = 0.0;
-  if (live && r < g.R) {
-    key = b.best[slot];
-    Sb0 = b.rng_sb[slot];
-    Sbb0 = b.rng_sbb[slot];
-  }
-  int mf = INT_MAX;
-  for (int w = threadIdx.x; w < g.n_dwg; w += blockDim.x)
-    mf = min(mf, b.flat_min[w]);
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) mf = min(mf, __shfl_xor(mf, o));
-  if ((threadIdx.x & 63) == 0) s_wmin[threadIdx.x >> 6] = mf;
-  __syncthreads();
-  int ff = s_wmin[0];
-  for (int wv = 1; wv < (int)(blockDim.x >> 6); ++wv) ff = min(ff, s_wmin[wv]);
-  if (!live || r >= g.R) return;  // padding: whole groups of L lanes leave
-  if (ff < g.ND) {
-    const Fit f0 = fit_exact(0.0, 0.0, 0.0, Sb0, Sbb0, g);
-    const unsigned long long kf = make_key(f0.err, 8ll * ff, g);
-    key = kf < key ? kf : key;
-  }
-  const long long c = (long long)(key & ((1ull << g.cbits) - 1));
-  const int d = (int)(c >> 3), k = (int)(c & 7);
-  const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
-  // The lane takes cells (ci, cj0 ..) of the domain in natural order and
-  // the range pixels they meet, sigma_k^-1 of each cell: G = sum_q
-  // A[sigma_k(q)] b[q] = sum_p A[p] b[sigma_k^-1(p)].  Integer sums (below
-  // 2^63 per lane and 2^53 in total): exact.
-  const int ci = q0 / N, cj0 = q0 % N;
-  int A[P];
-  if constexpr (P == N) {
-    // one cell row: two image rows, as words when they are aligned
-    int p0[2 * N], p1[2 * N];
-    const Pix *c0 = img + (size_t)(Y + 2 * ci) * g.W + X;
-    const bool wide = domain_rows_aligned(g, img);
-    load_row<Pix, N>(c0, wide, p0);
-    load_row<Pix, N>(c0 + g.W, wide, p1);
-#pragma unroll
-    for (int e = 0; e < P; ++e)
-      A[e] = p0[2 * e] + p0[2 * e + 1] + p1[2 * e] + p1[2 * e + 1];
-  } else {
-#pragma unroll
-    for (int e = 0; e < P; ++e)
-      A[e] = cell_sum(img, g.W, Y + 2 * ci, X + 2 * (cj0 + e));
-  }
-  const Pix *rb = img + (size_t)((r / g.RW) * N) * g.W + (r % g.RW) * N;
-  long long G = 0, SA = 0, SAA = 0, Sb = 0, Sbb = 0;
-#pragma unroll
-  for (int e = 0; e < P; ++e) {
-    int bi, bj;
-    sigma_inv(k, ci, cj0 + e, m, bi, bj);
-    const long long bv = (long long)rb[(size_t)bi * g.W + bj];
-    G += (long long)A[e] * bv;
-    SA += A[e];
-    SAA += (long long)A[e] * A[e];
-    Sb += bv;
-    Sbb += bv * bv;
-  }
-  G = group_sum<L>(G);
-  SA = group_sum<L>(SA);
-  SAA = group_sum<L>(SAA);
-  Sb = group_sum<L>(Sb);
-  Sbb = group_sum<L>(Sbb);
-  if (q0 != 0) return;
-  const Fit f = fit_exact((double)G, (double)SA, (double)SAA, (double)Sb,
-                          (double)Sbb, g);
-  out.domain[r] = d;
-  out.iso[r] = (uint8_t)k;
-  out.s_idx[r] = (uint8_t)f.j;
-  out.o_idx[r] = (uint8_t)f.m;
-  out.err[r] = f.err;
-}
-
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
                                                   EncBufs b, fic_codes out) {
@@ -502,6 +326,7 @@ __global__ void k_batch_init(BatchDev bd) {
   }
   if (i < bd.n) {
     bd.remaining[i] = bd.items_per_slice[i];
+    bd.fin_remaining[i] = bd.fin_per_slice[i];
     bd.ticks[1 + i] = 0;
   }
 }
@@ -520,16 +345,6 @@ __global__ __launch_bounds__(256) void k_prep_batch(BatchDev bd) {
     prep_domains_body<Pix, N>(g, img, b, m.y);
   else
     prep_ranges_body<Pix, N, N>(g, img, b, m.y);
-}
-
-template <typename Pix, int N>
-__global__ __launch_bounds__(256) void k_finalize_batch(BatchDev bd) {
-  const int2 m = load_uniform(&bd.wg_map[bd.phase_base[3] + blockIdx.x]);
-  const Geo g = load_uniform(&bd.tab[m.x].g);
-  const EncBufs b = load_uniform(&bd.tab[m.x].b);
-  const fic_codes out = load_uniform(&bd.tab[m.x].out);
-  const Pix *img = (const Pix *)load_uniform(&bd.tab[m.x].image);
-  finalize_body<Pix, N, N>(g, img, b, out, m.y);
 }
 
 // One workgroup per slice.
@@ -565,22 +380,6 @@ hipError_t launch_prep_batch(const BatchDev &bd, hipStream_t st) {
       hipLaunchKernelGGL((k_prep_batch<uint8_t, 8>), grid, dim3(256), 0, st, bd);
     else
       hipLaunchKernelGGL((k_prep_batch<uint8_t, 4>), grid, dim3(256), 0, st, bd);
-  }
-  return hipGetLastError();
-}
-
-hipError_t launch_finalize_batch(const BatchDev &bd, hipStream_t st) {
-  const dim3 grid(bd.phase_total[3]);
-  if (bd.bits == 12) {
-    if (bd.rsize == 8)
-      hipLaunchKernelGGL((k_finalize_batch<uint16_t, 8>), grid, dim3(256), 0, st, bd);
-    else
-      hipLaunchKernelGGL((k_finalize_batch<uint16_t, 4>), grid, dim3(256), 0, st, bd);
-  } else {
-    if (bd.rsize == 8)
-      hipLaunchKernelGGL((k_finalize_batch<uint8_t, 8>), grid, dim3(256), 0, st, bd);
-    else
-      hipLaunchKernelGGL((k_finalize_batch<uint8_t, 4>), grid, dim3(256), 0, st, bd);
   }
   return hipGetLastError();
 }

@@ -27,7 +27,7 @@
 // lexicographically, so the result does not depend on the order of the work.
 #include <math.h>
 
-#include "fic_search_common.h"
+#include "fic_finalize.h"
 
 namespace fic {
 
@@ -619,12 +619,23 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   search_rows<K>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0, c1);
 }
 
-// Many slices: a persistent grid whose workgroups take search items
-// (slice, row group, column blocks) from a shared counter, in the order of
-// the work list (largest slices first).  When a slice's last item is done,
-// the workgroup that finished it records the completion tick (100 MHz).
+// Spin limit of a code-extraction item's wait (about a second): the wait
+// always ends (every search item it waits for was taken earlier by a running
+// workgroup and never waits itself), the limit only bounds a broken launch.
+constexpr int kFinSpin = 1 << 24;
+
+// Many slices: a persistent grid whose workgroups take work items from a
+// shared counter, in the order of the work list (largest slices first).
+// A search item (slice, row group, column blocks) sweeps part of a slice's
+// candidate table; a code-extraction item (slice, -1, first pass, passes)
+// turns part of its best keys into codes once every search item of that
+// slice is done.  Such an item sits in the list after all of its slice's
+// search items, so the items it waits for are already running.  When a
+// slice's last code-extraction item is done, the workgroup that finished it
+// records the slice's codes-ready tick (100 MHz).
 template <int K>
 __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
+  constexpr int N = K == 64 ? 8 : 4;
   __shared__ SearchLds lds;
   __shared__ int s_item;
   if (threadIdx.x == 0)
@@ -639,23 +650,41 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const int4 w = load_uniform(&bd.items[it]);
     const Geo g = load_uniform(&bd.tab[w.x].g);
     const EncBufs b = load_uniform(&bd.tab[w.x].b);
-    const uint8_t *img =
-        g.pix_a ? (const uint8_t *)load_uniform(&bd.tab[w.x].image) : nullptr;
+    const uint8_t *img = (const uint8_t *)load_uniform(&bd.tab[w.x].image);
+    if (w.y < 0) {
+      // code extraction: wait until the slice's search is complete (the
+      // acquire pairs with the search items' release below)
+      if (threadIdx.x == 0) {
+        int spins = 0;
+        while (__hip_atomic_load(&bd.remaining[w.x], __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT) > 0 &&
+               ++spins < kFinSpin)
+          __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      }
+      __syncthreads();
+      const fic_codes out = load_uniform(&bd.tab[w.x].out);
+      for (int q = 0; q < w.w; ++q) {
+        finalize_body<uint8_t, N, N>(g, img, b, out, w.z + q);
+        __syncthreads();  // the next pass reuses the body's LDS table
+      }
+      if (threadIdx.x == 0 && atomicSub(&bd.fin_remaining[w.x], 1) == 1)
+        bd.ticks[1 + w.x] = (unsigned long long)wall_clock64();
+      continue;
+    }
     // the item's row and blocks within the slice's searched lists
     const int nA = __builtin_amdgcn_readfirstlane(gld(&b.n_act[0]));
     const int nD = __builtin_amdgcn_readfirstlane(gld(&b.n_act[1]));
     const int row0 = w.y * kMfmaRangesPerWG;
     const int c1 = min(w.w, (nD + 31) / 32);
     if (row0 < nA && w.z < c1)
-      search_rows<K>(g, b, img, lds, row0, nA, nD, w.z, c1);
-    // (no fence before the count: the completion tick is only a timestamp,
-    // and a device-wide fence compiles to an L2 write-back and invalidate,
-    // once per item)
+      search_rows<K>(g, b, g.pix_a ? img : nullptr, lds, row0, nA, nD, w.z,
+                     c1);
+    // every wave's key updates are complete and visible device-wide before
+    // the count that lets code extraction start
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) {
-      if (atomicSub(&bd.remaining[w.x], 1) == 1)
-        bd.ticks[1 + w.x] = (unsigned long long)wall_clock64();
-    }
+    if (threadIdx.x == 0) atomicSub(&bd.remaining[w.x], 1);
   }
 }
 
@@ -665,7 +694,7 @@ hipError_t launch_search_batch(const BatchDev &bd, hipStream_t st) {
   if (bd.bits != 8) return hipErrorInvalidValue;
   if (bd.n_items <= 0) return hipSuccess;
   // about two workgroups per compute unit (256 CUs)
-  const int grid = bd.n_items < 512 ? bd.n_items : 512;
+  const int grid = bd.n_items < kBatchSearchGrid ? bd.n_items : kBatchSearchGrid;
   auto kern = bd.rsize == 8 ? k_search_batch_u8<64> : k_search_batch_u8<16>;
   hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, st, bd);
   return hipGetLastError();

@@ -8,6 +8,7 @@
 // (bit depth, range size, method, lower bound on the domain count) to such
 // a choice; anything it leaves open takes the built-in default.
 #include <ctype.h>
+#include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -205,7 +206,9 @@ struct Reader {
       if (field) {
         double v;
         if (!number(v)) return false;
-        if (v != (double)(int32_t)v) return fail("tuning field is not an integer");
+        // range first: converting an out-of-range double to int is undefined
+        if (!(v >= -2147483648.0 && v <= 2147483647.0) || v != floor(v))
+          return fail("tuning field is not a 32-bit integer");
         *field = (int32_t)v;
       } else if (!value(out, depth + 1)) {
         return false;

@@ -88,6 +88,27 @@ def test_decode_scaled_matches_oracle(num, den):
         assert np.array_equal(traj, base)
 
 
+@pytest.mark.parametrize("H,W,n,step", [(64, 64, 4, 4), (96, 64, 8, 2)])
+def test_decode_batch_matches_single_decodes_and_oracle(H, W, n, step):
+    """Three images of one geometry with their own codes in one batched
+    decode: each trajectory equals fic_decode's bit for bit and the FP64
+    oracle's within 1e-3."""
+    T, B = 12, 3
+    cs = [codes_for(H, W, n, step, 50 + b) for b in range(B)]
+    p = F.Params(H, W, 8, n, step)
+    stack = lambda i, dt: dev(np.stack([c[i] for c in cs]), dt)
+    traj = F.decode_batch(stack(1, torch.int32), stack(2, torch.uint8), stack(3, torch.float32),
+                          stack(4, torch.float32), p, T, 128.0)
+    torch.cuda.synchronize()
+    assert traj.shape == (B, T + 1, H, W)
+    for b, (img, d, k, s, o) in enumerate(cs):
+        one = F.decode(dev(d, torch.int32), dev(k, torch.uint8), dev(s, torch.float32),
+                       dev(o, torch.float32), p, T, 128.0)
+        assert torch.equal(traj[b], one), b
+        ref = O.decode(H, W, n, step, d, k, s, o, T, 128.0)
+        assert np.abs(traj[b].cpu().numpy() - ref).max() <= 1e-3
+
+
 def test_decode_scaled_rejects_fractional_pixels():
     p = F.Params(64, 64, 8, 4, 4)
     z = torch.zeros(256, dtype=torch.int32, device="cuda")
