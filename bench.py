@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MFMA_FP16_PEAK = 2.5e15  # dense FP16 MFMA FLOP/s of MI355X (AMD published)
+MFMA_INT8_PEAK = 5.0e15  # dense int8 MFMA OP/s
 HBM_PEAK = 8.0e12        # bytes/s
 # hardware byte counters of the headline search kernel, from rocprofv3 --pmc
 # (written by --pmc-summary); used only while the kernel sources are unchanged
@@ -326,21 +327,50 @@ def main():
         o12, full12 = encode_line(F, torch, t12, p12, ws12, st12, 2, kf12)
         p12.full_search = 0
         o12s, skip12 = encode_line(F, torch, t12, p12, ws12, st12, 2, kf12)
+        # the same contraction on the int8 matrix cores (4 int8 products of
+        # K = 64 per candidate, against the 5.0 POP/s int8 peak)
+        p12.method, p12.full_search = F.METHOD_MFMA_I8, 1
+        ws12i = torch.empty(F.query(p12)[2] + 256, dtype=torch.uint8, device=dev)
+        o12i, full12i = encode_line(F, torch, t12, p12, ws12i, st12, 2, 0)
+        full12i["search_int8_tops"] = 4 * 2.0 * 64 * c12 / (full12i["phases_ms"]["search"] / 1e3) / 1e12
+        full12i["search_int8_frac"] = full12i["search_int8_tops"] * 1e12 / MFMA_INT8_PEAK
+        p12.full_search = 0
+        o12is, skip12i = encode_line(F, torch, t12, p12, ws12i, st12, 2, 0)
         p12.method, p12.full_search = F.METHOD_DIRECT, 1
         o12d, full12d = encode_line(F, torch, t12, p12, ws12, 2, 1, 0)
         p12.full_search = 0
         o12ds, skip12d = encode_line(F, torch, t12, p12, ws12, 2, 1, 0)
         ref12 = codes_np(o12)
-        same12 = all(np.array_equal(codes_np(o)[k], ref12[k]) for o in (o12s, o12d, o12ds)
-                     for k in ref12)
+        same12 = all(np.array_equal(codes_np(o)[k], ref12[k])
+                     for o in (o12s, o12d, o12ds, o12i, o12is) for k in ref12)
         result["ct12_512"] = {
             "workload": "512x512 12-bit slice, 8x8 ranges, 16x16 domains stride 2",
             "candidates": c12, "value": c12 / (full12["ms_per_step"] / 1e3),
             "unit": "comparisons/s", "full": full12, "skip_flat": skip12,
+            "int8": {"full": full12i, "skip_flat": skip12i,
+                     "over_fp16_full": full12["ms_per_step"] / full12i["ms_per_step"]},
             "direct": {"full": full12d, "skip_flat": skip12d},
             "mfma_over_direct": full12d["ms_per_step"] / full12["ms_per_step"],
             "mfma_over_direct_skip_flat": skip12d["ms_per_step"] / skip12["ms_per_step"],
             "codes_identical_all_modes_and_methods": bool(same12)}
+
+        # ---- quadtree ranges: 8x8 split into 4x4 where the residual is high ----
+        qt = []
+        for tau in (10.0, 40.0):
+            pq = F.Params(H, W, bits, 8, step, method=F.METHOD_MFMA, full_search=1)
+            qout = F.encode_quadtree(timg, pq, 4, tau)
+            nleaf = int(qout["y"].numel())
+            n4 = int((qout["size"] == 4).sum())
+            ms_q = mean_ms(torch, dev, lambda: F.encode_quadtree(timg, pq, 4, tau), 5, 1)
+            # candidates evaluated: all 8x8 ranges, then the 4x4 quadrants of
+            # the split ones, each against every domain of its side
+            ev = 8 * R * ND + 8 * n4 * F.query(F.Params(H, W, bits, 4, step))[1]
+            qt.append({"tau": tau, "leaves": nleaf, "leaves_4x4": n4, "ms": ms_q,
+                       "candidates_evaluated": ev, "evaluated_per_s": ev / (ms_q / 1e3)})
+        result["quadtree"] = {"workload": "512x512 uint8, 8x8 ranges split into 4x4 quadrants "
+                                          "when the residual exceeds tau * n^2, domains on the "
+                                          "4-pixel grid, full search per level",
+                              "rows": qt}
 
         # ---- the paper's own workload shape: 4x4 ranges, 8x8 domains stride 4 ---
         pw = []

@@ -59,8 +59,12 @@ enum fic_status {
 };
 
 enum fic_method {
-  FIC_METHOD_MFMA = 0,  /* search as an FP16 matrix-core contraction */
-  FIC_METHOD_DIRECT = 1 /* plain method: LDS-tiled per-candidate sums */
+  FIC_METHOD_MFMA = 0,    /* search as an FP16 matrix-core contraction */
+  FIC_METHOD_DIRECT = 1,  /* plain method: LDS-tiled per-candidate sums */
+  FIC_METHOD_MFMA_I8 = 2  /* 12-bit images with 8x8 ranges only: the same
+                             contraction on the int8 matrix cores (hi/lo
+                             pieces of 7 and 6 bits, exact int32 partial
+                             products) */
 };
 
 typedef struct {
@@ -70,7 +74,7 @@ typedef struct {
   int32_t domain_step;   /* STEP >= 1 */
   int32_t s_bits;        /* contrast bits, 1..8 (5 in the reference setup) */
   int32_t o_bits;        /* offset bits, 1..min(8, bit_depth+1) (7) */
-  int32_t method;        /* enum fic_method */
+  int32_t method;        /* enum fic_method (FIC_METHOD_MFMA_I8: 12-bit) */
   int32_t full_search;   /* 0: skip the candidates whose outcome is fixed
                             (below); 1: every range meets every domain in
                             the contraction.  The codes are identical. */
@@ -254,6 +258,43 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
 
 /* Workspace bytes fic_refine needs for these parameters and iters (host). */
 int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
+
+/*
+ * Quadtree (adaptive) ranges (Section V's quadtree method; Section II's
+ * adaptive fractal coding).  Every range of side p->range_size (the largest
+ * side, n_max) is encoded as by fic_encode; a range whose residual exceeds
+ * tau * n^2 (tau: a squared error per pixel) and whose side n is above
+ * min_range_size is split into its four quadrants, which are encoded the
+ * same way at side n / 2 (2n x 2n domains on the same STEP grid).  Sides
+ * are 8 and 4 (so n_max / min_range_size is 1 or 2).  The leaves are
+ * written top-level range by top-level range (row-major), each one's leaves
+ * in Z order (top-left, top-right, bottom-left, bottom-right, recursively).
+ * A leaf's domain index refers to the domain grid of its own side.
+ *
+ * fic_quadtree_query -- host only: workspace bytes and the largest leaf
+ *   count, (height / min_range_size) (width / min_range_size), which the
+ *   output arrays must hold.
+ * fic_encode_quadtree -- enqueues the levels' searches and the leaf layout
+ *   on `stream`.  out: device arrays of at least the largest leaf count
+ *   (y, x: the leaf's top-left pixel; size: its side; codes as fic_encode);
+ *   *out.n_leaves (device) receives the leaf count.
+ * Errors: FIC_E_INVALID (null pointers, tau NaN, min_range_size not a
+ * power-of-two fraction of range_size, workspace misaligned),
+ * FIC_E_UNSUPPORTED (sides other than 4 and 8, parameters as fic_query),
+ * FIC_E_WORKSPACE, FIC_E_HIP.
+ */
+typedef struct {
+  int32_t *y, *x;     /* top-left pixel of each leaf */
+  uint8_t *size;      /* side of each leaf */
+  fic_codes codes;    /* the leaf's code (domain index on its side's grid) */
+  int32_t *n_leaves;  /* [1]: number of leaves written */
+} fic_quadtree_out;
+
+int fic_quadtree_query(const fic_params *p, int32_t min_range_size,
+                       size_t *ws_bytes, int64_t *max_leaves);
+int fic_encode_quadtree(const fic_params *p, int32_t min_range_size,
+                        double tau, const void *image, fic_quadtree_out out,
+                        void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Code stream: the codes written compactly for the encoding file (Section

@@ -141,6 +141,78 @@ def encode_ranges(img, n, step, ranges, bits=8, s_bits=5, o_bits=7, threads=0):
     return out
 
 
+def quadtree_sizes(n_max, n_min):
+    """Range sides of the levels: n_max, n_max / 2, ..., n_min."""
+    sizes = [n_max]
+    while sizes[-1] > n_min:
+        sizes.append(sizes[-1] // 2)
+    if sizes[-1] != n_min:
+        raise ValueError("n_min must be n_max divided by a power of two")
+    return sizes
+
+
+def encode_quadtree(img, n_max, n_min, step, tau, bits=8, s_bits=5, o_bits=7):
+    """Adaptive partition of the range blocks (Section V's quadtree method;
+    Section II's adaptive fractal coding).  Reading used here: every range
+    of side n_max is encoded by the full search (domains of side 2 n on the
+    STEP grid, the same for every level); a range whose residual (eq. 8 with
+    the quantised s, o) exceeds tau * n^2, tau a squared error per pixel,
+    and whose side is above n_min is split into its four quadrants, which
+    are encoded the same way at side n / 2.  The leaves are listed top-level
+    range by top-level range (row-major), each one's leaves in Z order
+    (top-left, top-right, bottom-left, bottom-right, recursively).
+
+    Returns a dict of leaf arrays (y, x, size, domain, iso, s_idx, o_idx,
+    err) and `split`, per level above n_min, the split flag of every range
+    of that level's grid (0 for ranges that were not encoded)."""
+    img = np.ascontiguousarray(img, dtype=np.uint16)
+    H, W = img.shape
+    sizes = quadtree_sizes(n_max, n_min)
+    if H % n_max or W % n_max:
+        raise ValueError("image sides must be multiples of n_max")
+    codes = {}      # (y, x, n) -> (domain, iso, s_idx, o_idx, err)
+    split = []
+    active = [(ry * n_max, rx * n_max) for ry in range(H // n_max) for rx in range(W // n_max)]
+    for n in sizes:
+        rw = W // n
+        idx = np.array([(y // n) * rw + x // n for (y, x) in active], np.int64)
+        c = encode_ranges(img, n, step, idx, bits, s_bits, o_bits)
+        for i, (y, x) in enumerate(active):
+            codes[(y, x, n)] = (int(c["domain"][i]), int(c["iso"][i]), int(c["s_idx"][i]),
+                                int(c["o_idx"][i]), float(c["err"][i]))
+        if n == n_min:
+            break
+        flags = np.zeros((H // n) * rw, np.uint8)
+        nxt = []
+        for i, (y, x) in enumerate(active):
+            if c["err"][i] > tau * (n * n):
+                flags[(y // n) * rw + x // n] = 1
+                h = n // 2
+                nxt += [(y, x), (y, x + h), (y + h, x), (y + h, x + h)]
+        split.append(flags)
+        active = nxt
+    leaves = []
+
+    def walk(y, x, n, level):
+        if level < len(split) and split[level][(y // n) * (W // n) + x // n]:
+            h = n // 2
+            for (dy, dx) in ((0, 0), (0, h), (h, 0), (h, h)):
+                walk(y + dy, x + dx, h, level + 1)
+        else:
+            leaves.append((y, x, n) + codes[(y, x, n)])
+
+    for ry in range(H // n_max):
+        for rx in range(W // n_max):
+            walk(ry * n_max, rx * n_max, n_max, 0)
+    cols = list(zip(*leaves))
+    out = dict(y=np.array(cols[0], np.int32), x=np.array(cols[1], np.int32),
+               size=np.array(cols[2], np.uint8), domain=np.array(cols[3], np.int32),
+               iso=np.array(cols[4], np.uint8), s_idx=np.array(cols[5], np.uint8),
+               o_idx=np.array(cols[6], np.uint8), err=np.array(cols[7], np.float64))
+    out["split"] = split
+    return out
+
+
 def dequantize(s_idx, o_idx, bits=8, s_bits=5, o_bits=7):
     """Grid values of the quantised codes (same grid definition as the oracle's fit)."""
     s = np.asarray(s_idx, np.float64) / 2.0 ** (s_bits - 1) - 1.0

@@ -7,13 +7,17 @@ ABI.  PyTorch provides device memory and streams.
 from ._lib import (FicError, Params, encode, decode, decode_batch, decode_scaled, decode_backward,
                    query,
                    dequantize, FicDecode, lib, METHOD_MFMA, METHOD_DIRECT,
+                   METHOD_MFMA_I8,
                    timing_begin, timing_end, refine, Batch, Tuning, set_tuning,
                    load_tuning, get_tuning, search_counts, stream_query,
-                   stream_pack, stream_header, stream_unpack)
+                   stream_pack, stream_header, stream_unpack, quadtree_query,
+                   encode_quadtree)
 
 __all__ = ["FicError", "Params", "encode", "decode", "decode_batch", "decode_scaled", "decode_backward",
            "query",
            "dequantize", "FicDecode", "lib", "METHOD_MFMA", "METHOD_DIRECT",
+           "METHOD_MFMA_I8",
            "timing_begin", "timing_end", "refine", "Batch", "Tuning", "set_tuning",
            "load_tuning", "get_tuning", "search_counts", "stream_query",
-           "stream_pack", "stream_header", "stream_unpack"]
+           "stream_pack", "stream_header", "stream_unpack", "quadtree_query",
+           "encode_quadtree"]

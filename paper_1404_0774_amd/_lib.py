@@ -17,6 +17,7 @@ TUNING_PATH = os.path.join(HERE, "tuning.json")
 
 METHOD_MFMA = 0
 METHOD_DIRECT = 1
+METHOD_MFMA_I8 = 2   # 12-bit images, 8x8 ranges: the int8 matrix cores
 
 _STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported parameters",
            3: "workspace too small", 4: "HIP runtime error"}
@@ -40,6 +41,11 @@ class _Codes(ctypes.Structure):
     _fields_ = [("domain", ctypes.c_void_p), ("iso", ctypes.c_void_p),
                 ("s_idx", ctypes.c_void_p), ("o_idx", ctypes.c_void_p),
                 ("err", ctypes.c_void_p)]
+
+
+class _QtOut(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_void_p), ("x", ctypes.c_void_p), ("size", ctypes.c_void_p),
+                ("codes", _Codes), ("n_leaves", ctypes.c_void_p)]
 
 
 class Tuning(ctypes.Structure):
@@ -97,6 +103,10 @@ def lib():
         L.fic_decode_batch.argtypes = [P, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.fic_decode_scaled.restype = ctypes.c_int
         L.fic_decode_scaled.argtypes = [P, i32, i32, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
+        L.fic_quadtree_query.restype = ctypes.c_int
+        L.fic_quadtree_query.argtypes = [P, i32, ctypes.POINTER(sz), ctypes.POINTER(ctypes.c_int64)]
+        L.fic_encode_quadtree.restype = ctypes.c_int
+        L.fic_encode_quadtree.argtypes = [P, i32, ctypes.c_double, vp, _QtOut, vp, sz, vp]
         L.fic_stream_query.restype = ctypes.c_int
         L.fic_stream_query.argtypes = [P, ctypes.POINTER(sz), ctypes.POINTER(i32)]
         L.fic_stream_pack.restype = ctypes.c_int
@@ -230,6 +240,48 @@ def encode(image: torch.Tensor, p: Params, workspace=None):
     out["_ws"] = keep
     out["_ws_ptr"] = (ws, ew)
     return out
+
+
+def quadtree_query(p: Params, min_range_size: int):
+    """Host-only: (workspace bytes, largest leaf count)."""
+    nb, ml = ctypes.c_size_t(), ctypes.c_int64()
+    cp = p.c()
+    _check(lib().fic_quadtree_query(ctypes.byref(cp), min_range_size, ctypes.byref(nb),
+                                    ctypes.byref(ml)))
+    return nb.value, ml.value
+
+
+def encode_quadtree(image: torch.Tensor, p: Params, min_range_size: int, tau: float):
+    """Quadtree encode: ranges of side p.range_size whose residual exceeds
+    tau * n^2 are split into quadrants down to min_range_size.  Returns a
+    dict of device leaf arrays (y, x, size, domain, iso, s_idx, o_idx, err)
+    trimmed to the leaf count (this synchronises the device)."""
+    exp = torch.uint8 if p.bit_depth == 8 else torch.uint16
+    if image.dtype == torch.int16 and p.bit_depth == 12:
+        image = image.view(torch.uint16)
+    img_ptr = _dev_ptr(image, exp, "image")
+    wsb, ml = quadtree_query(p, min_range_size)
+    dev = image.device
+    out = dict(y=torch.empty(ml, dtype=torch.int32, device=dev),
+               x=torch.empty(ml, dtype=torch.int32, device=dev),
+               size=torch.empty(ml, dtype=torch.uint8, device=dev),
+               domain=torch.empty(ml, dtype=torch.int32, device=dev),
+               iso=torch.empty(ml, dtype=torch.uint8, device=dev),
+               s_idx=torch.empty(ml, dtype=torch.uint8, device=dev),
+               o_idx=torch.empty(ml, dtype=torch.uint8, device=dev),
+               err=torch.empty(ml, dtype=torch.float64, device=dev))
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    keep, ws = _workspace(wsb, dev)
+    q = _QtOut(out["y"].data_ptr(), out["x"].data_ptr(), out["size"].data_ptr(),
+               _Codes(out["domain"].data_ptr(), out["iso"].data_ptr(), out["s_idx"].data_ptr(),
+                      out["o_idx"].data_ptr(), out["err"].data_ptr()), count.data_ptr())
+    cp = p.c()
+    _check(lib().fic_encode_quadtree(ctypes.byref(cp), min_range_size, ctypes.c_double(tau),
+                                     ctypes.c_void_p(img_ptr), q, ctypes.c_void_p(ws),
+                                     ctypes.c_size_t(wsb), _stream(dev)))
+    n = int(count.item())
+    del keep
+    return {k: v[:n] for k, v in out.items()}
 
 
 def search_counts(out, p: Params):

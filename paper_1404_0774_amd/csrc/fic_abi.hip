@@ -94,8 +94,13 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   if (p->full_search != 0 && p->full_search != 1)
     return fail(FIC_E_INVALID, "full_search %d (0 or 1)", p->full_search);
   if (for_encode && p->method != FIC_METHOD_MFMA &&
-      p->method != FIC_METHOD_DIRECT)
+      p->method != FIC_METHOD_DIRECT && p->method != FIC_METHOD_MFMA_I8)
     return fail(FIC_E_INVALID, "method %d", p->method);
+  if (for_encode && p->method == FIC_METHOD_MFMA_I8 &&
+      (p->bit_depth != 12 || p->range_size != 8))
+    return fail(FIC_E_UNSUPPORTED,
+                "the int8 matrix-core search takes 12-bit images with 8x8 "
+                "ranges");
   if ((long long)p->height * p->width > (1ll << 30))
     return fail(FIC_E_UNSUPPORTED, "image larger than 2^30 pixels");
 
@@ -146,6 +151,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.rng_stride = (int)rs;
   g.pix_a = 0;
   g.full = p->full_search;
+  g.i8 = p->method == FIC_METHOD_MFMA_I8 && g.bits == 12;
   return FIC_OK;
 }
 
@@ -168,6 +174,9 @@ EncLayout enc_layout(const Geo &g) {
   L.off_n_act = o;    o = align256(o + 2 * 4);
   L.off_rng_flag = o; o = align256(o + (size_t)g.R_pad);
   L.off_col_flag = o; o = align256(o + (size_t)g.NC_pad);
+  const size_t i8 = g.i8 ? 1 : 0;
+  L.off_bop8 = o;     o = align256(o + i8 * 2 * (size_t)g.NC_pad * g.K);
+  L.off_aop8 = o;     o = align256(o + i8 * 2 * (size_t)g.R_pad * 8 * g.K);
   L.total = o;
   return L;
 }
@@ -190,6 +199,9 @@ EncBufs enc_bufs(const EncLayout &L, void *ws) {
   b.n_act = (int32_t *)(w + L.off_n_act);
   b.rng_flag = (uint8_t *)(w + L.off_rng_flag);
   b.col_flag = (uint8_t *)(w + L.off_col_flag);
+  b.rmask = nullptr;
+  b.bop8 = (int8_t *)(w + L.off_bop8);
+  b.aop8 = (int8_t *)(w + L.off_aop8);
   return b;
 }
 
@@ -241,7 +253,8 @@ void timing_mark(int phase, hipStream_t s) {
 }
 
 int encode_launch(const fic_params *p, Geo g, const void *image,
-                  fic_codes out, void *workspace, void *stream);
+                  fic_codes out, void *workspace, void *stream,
+                  const uint8_t *rmask = nullptr);
 
 }  // namespace
 
@@ -299,8 +312,10 @@ namespace {
 // The launches of one encode on a validated workspace of at least
 // enc_layout(g).total bytes.
 int encode_launch(const fic_params *p, Geo g, const void *image,
-                  fic_codes out, void *workspace, void *stream) {
-  const EncBufs b = enc_bufs(enc_layout(g), workspace);
+                  fic_codes out, void *workspace, void *stream,
+                  const uint8_t *rmask) {
+  EncBufs b = enc_bufs(enc_layout(g), workspace);
+  b.rmask = rmask;
   hipStream_t s = (hipStream_t)stream;
   // 8x8 ranges on the matrix cores take their range fragments straight from
   // the (8-byte aligned) image
@@ -322,6 +337,9 @@ int encode_launch(const fic_params *p, Geo g, const void *image,
   timing_mark(2, s);
   if (p->method == FIC_METHOD_DIRECT)
     e = launch_search_direct(g, b, t.chunks, s);
+  else if (p->method == FIC_METHOD_MFMA_I8)
+    e = launch_search_mfma12_i8(
+        g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
   else if (g.bits == 12)
     e = launch_search_mfma12(
         g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
@@ -494,6 +512,145 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   hipError_t e = launch_refine(g, domain, iso, s, o, image, iters, x0, steps,
                                lr_s, lr_o, loss, workspace, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(e, "refine");
+  return ok();
+}
+
+}  // extern "C"
+
+namespace fic {
+namespace {
+
+// Levels and workspace of a quadtree encode.
+struct QtPlan {
+  int L;
+  fic_params lp[3];
+  Geo g[3];
+  size_t off_enc, off_codes[3], off_split[3], off_mask[3], off_cnt[3], off_off,
+      total;
+};
+
+int qt_plan(const fic_params *p, int n_min, QtPlan &q) {
+  Geo g0;
+  int st = make_geo(p, g0, /*for_encode=*/true);
+  if (st) return st;
+  if (n_min != 4 && n_min != 8)
+    return fail(FIC_E_UNSUPPORTED, "min_range_size %d (4 or 8)", n_min);
+  if (n_min > p->range_size)
+    return fail(FIC_E_INVALID, "min_range_size %d above range_size %d", n_min,
+                p->range_size);
+  q.L = 0;
+  size_t enc = 0;
+  for (int n = p->range_size; n >= n_min; n /= 2) {
+    q.lp[q.L] = *p;
+    q.lp[q.L].range_size = n;
+    st = make_geo(&q.lp[q.L], q.g[q.L], /*for_encode=*/true);
+    if (st) return st;
+    enc = enc > enc_layout(q.g[q.L]).total ? enc : enc_layout(q.g[q.L]).total;
+    ++q.L;
+  }
+  size_t o = 0;
+  q.off_enc = o;
+  o = align256(o + enc);
+  for (int l = 0; l < q.L; ++l) {
+    const size_t R = (size_t)q.g[l].R;
+    q.off_codes[l] = o;
+    o = align256(o + R * (4 + 1 + 1 + 1));
+    o = align256(o + R * 8);  // residuals (8-byte aligned after the bytes)
+    q.off_split[l] = o;
+    o = align256(o + R);
+    q.off_mask[l] = o;
+    o = align256(o + R);
+    q.off_cnt[l] = o;
+    o = align256(o + R * 4);
+  }
+  q.off_off = o;
+  o = align256(o + ((size_t)q.g[0].R + 1) * 4);
+  q.total = o;
+  return FIC_OK;
+}
+
+fic_codes qt_codes(const QtPlan &q, int l, char *w) {
+  const size_t R = (size_t)q.g[l].R;
+  char *c = w + q.off_codes[l];
+  fic_codes k;
+  k.domain = (int32_t *)c;
+  k.iso = (uint8_t *)(c + 4 * R);
+  k.s_idx = (uint8_t *)(c + 5 * R);
+  k.o_idx = (uint8_t *)(c + 6 * R);
+  k.err = (double *)(c + align256(7 * R));
+  return k;
+}
+
+}  // namespace
+}  // namespace fic
+
+extern "C" {
+
+int fic_quadtree_query(const fic_params *p, int32_t min_range_size,
+                       size_t *ws_bytes, int64_t *max_leaves) {
+  QtPlan q;
+  const int st = qt_plan(p, min_range_size, q);
+  if (st) return st;
+  if (ws_bytes) *ws_bytes = q.total;
+  if (max_leaves) *max_leaves = q.g[q.L - 1].R;
+  return ok();
+}
+
+int fic_encode_quadtree(const fic_params *p, int32_t min_range_size,
+                        double tau, const void *image, fic_quadtree_out out,
+                        void *workspace, size_t ws_bytes, void *stream) {
+  QtPlan q;
+  int st = qt_plan(p, min_range_size, q);
+  if (st) return st;
+  if (tau != tau) return fail(FIC_E_INVALID, "tau is NaN");
+  if (!image || !workspace || !out.y || !out.x || !out.size ||
+      !out.n_leaves || !out.codes.domain || !out.codes.iso ||
+      !out.codes.s_idx || !out.codes.o_idx || !out.codes.err)
+    return fail(FIC_E_INVALID, "null image, workspace or output pointer");
+  if (((uintptr_t)workspace) & 255)
+    return fail(FIC_E_INVALID, "workspace is not 256-byte aligned");
+  if (ws_bytes < q.total)
+    return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                q.total);
+  char *w = (char *)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  QtLevels lv;
+  lv.L = q.L;
+  lv.R0 = q.g[0].R;
+  for (int l = 0; l < q.L; ++l) {
+    const fic_codes c = qt_codes(q, l, w);
+    const uint8_t *mask = l ? (const uint8_t *)(w + q.off_mask[l]) : nullptr;
+    st = encode_launch(&q.lp[l], q.g[l], image, c, w + q.off_enc, stream, mask);
+    if (st) return st;
+    uint8_t *split = (uint8_t *)(w + q.off_split[l]);
+    if (l + 1 < q.L) {
+      const double lim = tau * (double)q.g[l].K;
+      const hipError_t e =
+          launch_qt_split(q.g[l].RW, q.g[l].R, mask, c.err, lim, split,
+                          (uint8_t *)(w + q.off_mask[l + 1]), s);
+      if (e != hipSuccess) return hip_fail(e, "quadtree split");
+    }
+    lv.lv[l].codes = c;
+    lv.lv[l].split = split;
+    lv.lv[l].RW = q.g[l].RW;
+    lv.lv[l].n = q.g[l].n;
+  }
+  // leaves under each top-level range: counted from the finest level that
+  // can split upwards (a level with one level below it has one leaf per
+  // quadrant); a single level has one leaf per range
+  int32_t *cnt0 = (int32_t *)(w + q.off_cnt[0]);
+  for (int l = q.L > 1 ? q.L - 2 : 0; l >= 0; --l) {
+    const bool splits = l + 1 < q.L;
+    const bool deeper = l + 2 < q.L;
+    const hipError_t e = launch_qt_count(
+        q.g[l].RW, q.g[l].R, splits ? lv.lv[l].split : nullptr,
+        deeper ? (const int32_t *)(w + q.off_cnt[l + 1]) : nullptr,
+        (int32_t *)(w + q.off_cnt[l]), s);
+    if (e != hipSuccess) return hip_fail(e, "quadtree count");
+  }
+  const hipError_t e =
+      launch_qt_leaves(lv, cnt0, (int32_t *)(w + q.off_off), out, s);
+  if (e != hipSuccess) return hip_fail(e, "quadtree leaves");
   return ok();
 }
 

@@ -31,6 +31,8 @@ struct Geo {
                      //   fragments from the image; no range operand is written
   int full;          // 1: ranges and domains without variance are searched
                      //   too (0: they are left out; their outcome is fixed)
+  int i8;            // 1: 12-bit operands also as int8 hi/lo planes (the
+                     //   int8 matrix-core search)
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step
@@ -77,13 +79,19 @@ struct EncBufs {
   int32_t *n_act;     // [2] counts of the two lists
   uint8_t *rng_flag;  // [R_pad] 1: slot holds a range with variance
   uint8_t *col_flag;  // [NC_pad] 1: column holds a domain with variance
+  int8_t *bop8;      // 12-bit int8 search only: [2][NC_pad][K] A_hi, A_lo
+  int8_t *aop8;      // 12-bit int8 search only: [2][R_pad * 8][K] b_hi, b_lo
+  // Optional, per image range (not slot): 0 leaves the range out of the
+  // search (its code is then candidate 0's); null searches every range.
+  // The quadtree encode searches only the quadrants of split ranges.
+  const uint8_t *rmask;
 };
 
 // Byte layout of the encode workspace.
 struct EncLayout {
   size_t off_bop, off_aop, off_col_dom, off_col_sadp, off_col_saa, off_col_rec;
   size_t off_rng_sb, off_rng_sbb, off_best, off_flat, off_act_slot,
-      off_act_col, off_n_act, off_rng_flag, off_col_flag;
+      off_act_col, off_n_act, off_rng_flag, off_col_flag, off_bop8, off_aop8;
   size_t total;
 };
 
@@ -133,6 +141,19 @@ struct StreamGeo {
   uint32_t header[8];
 };
 
+// One level of a quadtree encode: its codes (every range of its grid),
+// split flags, ranges per row and range side.
+struct QtLevel {
+  fic_codes codes;
+  const uint8_t *split;
+  int RW, n;
+};
+struct QtLevels {
+  QtLevel lv[3];
+  int L;   // levels (1..3)
+  int R0;  // ranges of the top level
+};
+
 // Launchers (one per kernel file).  All return hipError_t of the launch.
 hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
                        hipStream_t st);
@@ -143,6 +164,8 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
                               hipStream_t st);
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
                                 int workgroups, hipStream_t st);
+hipError_t launch_search_mfma12_i8(const Geo &g, const EncBufs &b,
+                                   int workgroups, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,
                                 hipStream_t st);
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
@@ -164,6 +187,15 @@ hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
                                 const float *o, int iters, float x0,
                                 float *traj, hipStream_t st);
 size_t decode_backward_ws_bytes(const Geo &g);
+hipError_t launch_qt_split(int RW, int R, const uint8_t *mask,
+                           const double *err, double lim, uint8_t *split,
+                           uint8_t *mask_next, hipStream_t st);
+hipError_t launch_qt_count(int RW, int R, const uint8_t *split,
+                           const int32_t *cnt_next, int32_t *cnt,
+                           hipStream_t st);
+hipError_t launch_qt_leaves(const QtLevels &q, const int32_t *cnt0,
+                            int32_t *off, const fic_quadtree_out &out,
+                            hipStream_t st);
 hipError_t launch_stream_pack(const StreamGeo &sg, const int32_t *domain,
                               const uint8_t *iso, const uint8_t *s_idx,
                               const uint8_t *o_idx, void *out,

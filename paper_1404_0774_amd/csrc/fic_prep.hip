@@ -69,6 +69,16 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     *(halfN *)(b.bop + (size_t)col * K + i * N) = vh;
     if (g.bits == 12)
       *(halfN *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + i * N) = vl;
+    if (g.i8) {
+      // the same pieces as int8 (both <= 127) for the int8 search
+      int8_t *dh = b.bop8 + (size_t)col * K + i * N;
+      int8_t *dl = dh + (size_t)g.NC_pad * K;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        dh[j] = (int8_t)(float)vh[j];
+        dl[j] = (int8_t)(float)vl[j];
+      }
+    }
   }
   // the column's statistics over its N adjacent threads
   SA = group_sum<N>(SA);
@@ -157,6 +167,11 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
         if (sizeof(Pix) == 2) {
           row_hi[k * K + pp] = (_Float16)(float)(v[e] >> 6);
           row_lo[k * K + pp] = (_Float16)(float)(v[e] & 63);
+          if (g.i8) {
+            int8_t *r8 = b.aop8 + (size_t)r * 8 * K;
+            r8[k * K + pp] = (int8_t)(v[e] >> 6);
+            r8[(size_t)g.R_pad * 8 * K + k * K + pp] = (int8_t)(v[e] & 63);
+          }
         } else {
           row_hi[k * K + pp] = (_Float16)(float)v[e];
         }
@@ -177,8 +192,11 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;
   // searched: a real range with variance (K Sbb - Sb^2 != 0, exact), or
-  // any real range in a full search
-  b.rng_flag[r] = ri < g.R && (g.full || (Acc)K * Sbb - Sb * Sb != 0) ? 1 : 0;
+  // any real range in a full search; never one the range mask leaves out
+  b.rng_flag[r] = ri < g.R && (!b.rmask || b.rmask[ri]) &&
+                         (g.full || (Acc)K * Sbb - Sb * Sb != 0)
+                     ? 1
+                     : 0;
   if (ri >= g.R) {
     b.best[r] = ~0ull;
     return;

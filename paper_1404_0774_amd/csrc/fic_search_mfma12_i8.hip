@@ -1,0 +1,369 @@
+// fic_search_mfma12_i8.hip -- the matrix-core search for 12-bit images on
+// the int8 matrix cores.
+//
+// Both operands are split as in the FP16 kernel, b = 64 b_hi + b_lo (6 + 6
+// bits) and A = 128 A_hi + A_lo (7 + 7 bits); every piece fits a signed int8
+// and 2 b_lo <= 126 does too, so
+//     G = 8192 G_hh + 64 M + G_ll,
+//     G_hh = sum A_hi b_hi,  G_ll = sum A_lo b_lo,
+//     M    = sum (A_hi * 2 b_lo + A_lo * b_hi),
+// with three int32 accumulators of v_mfma_i32_32x32x32_i8 (four instructions
+// per 32-deep k-step, two k-steps for 8x8 ranges).  Integer accumulation is
+// exact whatever the size of the sums; the int8 rate is twice the FP16 rate
+// and each instruction is twice as deep, so the contraction takes a quarter
+// of the FP16 kernel's matrix-core instructions.  Everything after the
+// contraction (prune with a margin, queue of exact FP64 G, drains, key
+// updates) is the FP16 kernel's.  The doubling of b_lo is a shift of each
+// packed byte (no carries: bytes <= 63).
+#include <math.h>
+
+#include "fic_search_common.h"
+
+namespace fic {
+
+namespace {
+
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kWR = 4;      // ranges per wave (one row block)
+constexpr int kSync = 4;    // column blocks between global syncs
+constexpr int kQueue = 128; // pairs; >= 63 + 64 lanes
+
+struct __attribute__((aligned(16))) QEntry12 {
+  double g[8];  // exact G of the 8 transforms
+  double saa;
+  float sa, dp;
+  int dom, lr;
+  int pad[2];
+};
+
+
+// Exact-safe test of one candidate in FP64: G - SA Sb/K is exact in double,
+// t = W' D' is rounded down.
+__device__ __forceinline__ bool passes_exact(double G, double sa, double Sb,
+                                             double invK, float t) {
+  const double a = G - sa * Sb * invK;  // K is a power of two
+  return a * a >= (double)t;
+}
+
+// Surviving transforms are listed as pair index << 3 | transform.
+__device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
+                                        int &qn, int n,
+                                        unsigned long long *best,
+                                        const double2 *rstat, const Geo &g) {
+  const int lane = threadIdx.x & 63;
+  const double K = (double)g.K;
+  for (int base = 0; base < n; base += 64) {
+    const int i = base + lane;
+    int nc = 0;
+    {
+      double gv[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      unsigned pass = 0;
+      if (i < n) {
+        const QEntry12 &q = queue[i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) gv[k] = q.g[k];
+        const double2 rs = rstat[q.lr];
+        const float t =
+            weight_from_key(best[q.lr], K * rs.y - rs.x * rs.x, g) * q.dp;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+          pass |= passes_exact(gv[k], (double)q.sa, rs.x, g.invK, t) ? (1u << k) : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bool f = (pass >> k) & 1u;
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(f);
+        if (f) {
+          const int off = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          cands[nc + off] = ((unsigned)i << 3) | k;
+        }
+        nc += __popcll(m);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int c = lane; c < nc; c += 64) {
+      const unsigned pk = cands[c];
+      const QEntry12 &q = queue[pk >> 3];
+      const double2 rs = rstat[q.lr];
+      const Fit f = fit_exact(q.g[pk & 7], (double)q.sa, q.saa, rs.x, rs.y, g);
+      atomicMin(&best[q.lr], make_key(f.err, 8ll * q.dom + (pk & 7), g));
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  const int rem = qn - n;
+  static_assert(sizeof(QEntry12) == 96, "entry is six 16-byte words");
+  uint4 t[6];
+#pragma unroll
+  for (int w = 0; w < 6; ++w) t[w] = uint4{0, 0, 0, 0};
+  if (lane < rem) {
+    const uint4 *src = (const uint4 *)&queue[n + lane];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) t[w] = src[w];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rem) {
+    uint4 *dst = (uint4 *)&queue[lane];
+#pragma unroll
+    for (int w = 0; w < 6; ++w) dst[w] = t[w];
+  }
+  qn = rem;
+}
+
+// Column ci of the searched list for block cb and lane column cl (-1 past
+// the list).
+__device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
+                                        int cl) {
+  const int j = cb * 32 + cl;
+  return j < nD ? b.act_col[j] : -1;
+}
+
+// A 1-D grid of G workgroups over the searched lists (ranges and domains
+// with variance, built by the compaction; the lengths are read on the
+// device): rows of 16 searched ranges, each split into G / rows chunks of
+// 32-column blocks (at least one).  Block: 4 waves of 4 ranges each.  Same
+// lane layout as the 8-bit kernel: accumulator v of lane l holds transform
+// v mod 8 of range 2 (l / 32) + v / 8 of the wave, for domain column
+// l mod 32.
+template <int K>
+__global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) {
+  constexpr int KS = K / 16;
+  __shared__ unsigned long long s_best[4][kWR];
+  __shared__ double2 s_rstat[4][kWR];
+  __shared__ int s_slot[4][kWR];
+  __shared__ QEntry12 s_queue[4][kQueue];
+  __shared__ unsigned s_cands[4][8 * 64];
+  const int nA = __builtin_amdgcn_readfirstlane(b.n_act[0]);
+  const int nD = __builtin_amdgcn_readfirstlane(b.n_act[1]);
+  const int rows = (nA + 4 * kWR - 1) / (4 * kWR);
+  const int ncb = (nD + 31) / 32;
+  if (rows == 0 || ncb == 0) return;
+  const int chunks = max(1, min((int)gridDim.x / rows, ncb));
+  const int rg = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+  if (rg >= rows) return;
+  const int cbpc = (ncb + chunks - 1) / chunks;
+  const int c0 = chunk * cbpc, c1 = min(c0 + cbpc, ncb);
+  if (c0 >= c1) return;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int h = lane >> 5;
+  const int cl = lane & 31;
+  const int wr0 = rg * (4 * kWR) + wave * kWR;  // entries of the range list
+  unsigned long long *my_best = s_best[wave];
+  double2 *rstat = s_rstat[wave];
+  int *slots = s_slot[wave];
+  QEntry12 *queue = s_queue[wave];
+  unsigned *cands = s_cands[wave];
+  int qn = 0;
+  const double Kd = (double)g.K;
+
+  // the wave's range slots (-1: none), their keys and sums
+  unsigned long long gsnap = ~0ull;
+  int my_slot = -1;
+  if (lane < kWR) {
+    my_slot = wr0 + lane < nA ? b.act_slot[wr0 + lane] : -1;
+    slots[lane] = my_slot;
+    double sb = 0.0, sbb = 0.0;
+    if (my_slot >= 0) {
+      gsnap = load_best(&b.best[my_slot]);
+      sb = b.rng_sb[my_slot];
+      sbb = b.rng_sbb[my_slot];
+    }
+    my_best[lane] = gsnap;
+    rstat[lane] = double2{sb, sbb};
+  }
+  __builtin_amdgcn_wave_barrier();
+
+  const size_t aplane = (size_t)g.R_pad * 8 * K;
+  const size_t bplane = (size_t)g.NC_pad * K;
+  // lane l holds 16 consecutive pieces of k-step kk: pixels 32 kk + 16 h ..
+  // (the same element order for both operands, so every product pairs a
+  // range piece with the cell piece of the same pixel)
+  i32x4 ah[KS], al[KS], al2[KS];
+  {
+    const int rho = lane & 31;
+    const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
+    const int rl = 2 * hh + (gg >> 1), iso = 4 * (gg & 1) + q;
+    const int sl = slots[rl];
+    const int8_t *src =
+        b.aop8 + ((size_t)(sl >= 0 ? sl : 0) * 8 + iso) * K + 16 * h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      ah[kk] = sl >= 0 ? *(const i32x4 *)(src + 32 * kk) : i32x4{};
+      al[kk] = sl >= 0 ? *(const i32x4 *)(src + aplane + 32 * kk) : i32x4{};
+      al2[kk] = al[kk] << 1;  // 2 b_lo in every byte
+    }
+  }
+
+  float wp[2], bbar[2];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const double2 rs = rstat[2 * h + e];
+    bbar[e] = (float)(rs.x * g.invK);
+    wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+  }
+
+  // a column past the searched list reads column 0 and is marked flat
+  // (D' = +inf), so it never passes the prune
+  i32x4 bh[KS], bl[KS];
+  float csa, cdp;
+  int cdom;
+  double csaa;
+  {
+    const int ci = column12(b, nD, c0, cl);
+    const int col = ci >= 0 ? ci : 0;
+    const int8_t *bsrc = b.bop8 + (size_t)col * K + 16 * h;
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      bh[kk] = *(const i32x4 *)(bsrc + 32 * kk);
+      bl[kk] = *(const i32x4 *)(bsrc + bplane + 32 * kk);
+    }
+    const float2 sadp = b.col_sadp[col];
+    csa = sadp.x;
+    cdp = ci >= 0 ? sadp.y : __builtin_inff();
+    cdom = b.col_dom[col];
+    csaa = b.col_saa[col];
+  }
+  // column index of the next block, read a block ahead
+  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl) : -1;
+
+  for (int cb = c0; cb < c1; ++cb) {
+    const int slot = (cb - c0) % kSync;
+    i32x4 bhn[KS], bln[KS];
+    const int ncol = ci_next >= 0 ? ci_next : 0;
+    const bool nlive = ci_next >= 0;
+    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl) : -1;
+    {
+      const int8_t *bsrc = b.bop8 + (size_t)ncol * K + 16 * h;
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        bhn[kk] = *(const i32x4 *)(bsrc + 32 * kk);
+        bln[kk] = *(const i32x4 *)(bsrc + bplane + 32 * kk);
+      }
+    }
+    const float2 nsadp = b.col_sadp[ncol];
+    const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
+    const int ndom = b.col_dom[ncol];
+    const double nsaa = b.col_saa[ncol];
+
+    i32x16 ghh = i32x16{}, gmid = i32x16{}, gll = i32x16{};
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      ghh = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah[kk], bh[kk], ghh, 0, 0, 0);
+      gll = __builtin_amdgcn_mfma_i32_32x32x32_i8(al[kk], bl[kk], gll, 0, 0, 0);
+      gmid = __builtin_amdgcn_mfma_i32_32x32x32_i8(al2[kk], bh[kk], gmid, 0, 0, 0);
+      gmid = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah[kk], bl[kk], gmid, 0, 0, 0);
+    }
+
+    // G in FP32 (non-negative), max/min over the 8 transforms on bit patterns
+    float gap[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v)
+      gap[v] = fmaf(8192.0f, (float)ghh[v], fmaf(64.0f, (float)gmid[v], (float)gll[v]));
+    float gmx[2], gmn[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      unsigned ux = __float_as_uint(gap[8 * e]), un = ux;
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        const unsigned u = __float_as_uint(gap[8 * e + k]);
+        ux = max(ux, u);
+        un = min(un, u);
+      }
+      gmx[e] = __uint_as_float(ux);
+      gmn[e] = __uint_as_float(un);
+    }
+    bool ps[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const float a0 = fmaf(-csa, bbar[e], gmx[e]);
+      const float a1 = fmaf(-csa, bbar[e], gmn[e]);
+      // margin for the FP32 rebuild of G and the rounding of a
+      const float mm = fmaf(fmaxf(fabsf(a0), fabsf(a1)), 1.0f + 0x1p-20f,
+                            gmx[e] * 0x1p-20f);
+      ps[e] = mm * mm >= wp[e] * cdp;
+    }
+
+    if (__any(ps[0] || ps[1])) {
+      bool drained = false;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const unsigned long long m = __builtin_amdgcn_ballot_w64(ps[e]);
+        if (m == 0) continue;
+        if (ps[e]) {
+          const int off = __builtin_amdgcn_mbcnt_hi(
+              (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+          QEntry12 *q = &queue[qn + off];
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            q->g[k] = (double)(8192ll * ghh[8 * e + k] +
+                               64ll * gmid[8 * e + k] + gll[8 * e + k]);
+          q->saa = csaa;
+          q->sa = csa;
+          q->dp = cdp;
+          q->dom = cdom;
+          q->lr = 2 * h + e;
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+          drain12(queue, cands, qn, qn & ~63, my_best, rstat, g);
+          drained = true;
+        }
+      }
+      if (drained) {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const double2 rs = rstat[2 * h + e];
+          wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+        }
+      }
+    }
+
+    const int jn = cb - c0 + 1;
+    if (jn == 1 || jn == 2 || slot == kSync - 1 || cb + 1 == c1) {
+      if (cb + 1 == c1 && qn > 0)
+        drain12(queue, cands, qn, qn, my_best, rstat, g);
+      // publish, then read the global keys and use them at once
+      if (lane < kWR && my_slot >= 0) {
+        const unsigned long long m = my_best[lane];
+        if (m < gsnap) atomicMin(&b.best[my_slot], m);
+        gsnap = load_best(&b.best[my_slot]);
+        my_best[lane] = min(m, gsnap);
+      }
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const double2 rs = rstat[2 * h + e];
+        wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
+      }
+    }
+
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      bh[kk] = bhn[kk];
+      bl[kk] = bln[kk];
+    }
+    csa = nsa;
+    cdp = ndp;
+    cdom = ndom;
+    csaa = nsaa;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_search_mfma12_i8(const Geo &g, const EncBufs &b,
+                                   int workgroups, hipStream_t st) {
+  // 32-deep k-steps: 8x8 ranges (K = 64) only
+  if (g.bits != 12 || !g.i8 || g.K != 64) return hipErrorInvalidValue;
+  static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
+  if (workgroups < 1) workgroups = 1;
+  auto kern = k_search_mfma_12_i8<64>;
+  hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b);
+  return hipGetLastError();
+}
+
+}  // namespace fic

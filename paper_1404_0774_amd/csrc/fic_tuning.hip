@@ -34,7 +34,7 @@ constexpr int kMaxItemBlocks = 4096;
 // search launch, one seed block (ranked for a starting bound) once there are
 // 16 or more column blocks, 16 column blocks per batched work item.
 Tune default_tune(const Geo &g, int method) {
-  const int per_wg = (g.bits == 12 && method == FIC_METHOD_MFMA)
+  const int per_wg = (g.bits == 12 && method != FIC_METHOD_DIRECT)
                          ? kMfma12RangesPerWG
                          : kMfmaRangesPerWG;
   const int row_groups = std::max(1, g.R_pad / per_wg);
@@ -54,7 +54,8 @@ bool valid_entry(const fic_tuning &e, char *msg, size_t len) {
     snprintf(msg, len, "tuning entry: range_size %d (4 or 8)", e.range_size);
     return false;
   }
-  if (e.method != FIC_METHOD_MFMA && e.method != FIC_METHOD_DIRECT) {
+  if (e.method != FIC_METHOD_MFMA && e.method != FIC_METHOD_DIRECT &&
+      e.method != FIC_METHOD_MFMA_I8) {
     snprintf(msg, len, "tuning entry: method %d", e.method);
     return false;
   }

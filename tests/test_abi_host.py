@@ -300,3 +300,28 @@ def test_stream_pack_and_unpack_validate_before_gpu_work():
     assert L.fic_stream_pack(ctypes.byref(p), fake, fake, fake, fake, fake, nb - 4, None) == 3
     assert L.fic_stream_unpack(ctypes.byref(p), fake, nb - 4, fake, fake, fake, fake, None) == 1
     assert L.fic_stream_unpack(ctypes.byref(p), None, nb, fake, fake, fake, fake, None) == 1
+
+
+def test_quadtree_validates_before_gpu_work():
+    L = F.lib()
+    p = F.Params(256, 256, 8, 8, 4)
+    nb, ml = F.quadtree_query(p, 4)
+    assert ml == 4096 and nb > 0
+    assert F.quadtree_query(p, 8)[1] == 1024
+    for n_min, status in [(2, 2), (16, 2), (0, 2)]:
+        with pytest.raises(F.FicError) as e:
+            F.quadtree_query(p, n_min)
+        assert e.value.status == status
+    with pytest.raises(F.FicError) as e:
+        F.quadtree_query(F.Params(256, 256, 8, 4, 4), 8)   # min above max
+    assert e.value.status == 1
+    fake = ctypes.c_void_p(1 << 20)
+    codes = _lib._Codes(fake, fake, fake, fake, fake)
+    out = _lib._QtOut(fake, fake, fake, codes, fake)
+    cp = p.c()
+    assert L.fic_encode_quadtree(ctypes.byref(cp), 4, ctypes.c_double(float("nan")), fake, out,
+                                 fake, nb, None) == 1
+    assert L.fic_encode_quadtree(ctypes.byref(cp), 4, ctypes.c_double(1.0), fake, out, fake,
+                                 nb - 256, None) == 3
+    assert L.fic_encode_quadtree(ctypes.byref(cp), 4, ctypes.c_double(1.0), None, out, fake,
+                                 nb, None) == 1

@@ -60,12 +60,14 @@ def test_parity_small_images(method, H, W, n, step, seed, full):
 
 
 @pytest.mark.parametrize("full", [0, 1])
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", METHODS + [F.METHOD_MFMA_I8])
 @pytest.mark.parametrize("bits", [8, 12])
 def test_search_visits_exactly_the_ranges_and_domains_with_variance(bits, method, full):
     """Without full_search both searches skip flat ranges and flat domains
     (their outcome is fixed); with it they visit every range and domain.  The
     counts they report match a direct count."""
+    if method == F.METHOD_MFMA_I8 and bits == 8:
+        pytest.skip("the int8 search takes 12-bit images")
     H, W, n, step = 128, 96, 8, 4
     img = gen_image(H, W, bits, 19)
     p = F.Params(H, W, bits, n, step, method=method, full_search=full)
@@ -176,21 +178,27 @@ def test_deterministic_repeat():
 
 # --- 12-bit images: hi/lo split contraction ---------------------------------
 
+METHODS12 = METHODS + [F.METHOD_MFMA_I8]
+
+
 @pytest.mark.parametrize("full", [0, 1])
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", METHODS12)
 @pytest.mark.parametrize("H,W,n,step,seed", [
     (48, 64, 4, 2, 41),     # 192 ranges, ragged tiles
     (64, 64, 8, 4, 42),
     (40, 56, 4, 3, 43),
+    (96, 80, 8, 2, 44),     # 120 ranges (ragged tile), 1,161 domains
 ])
 def test_parity_12bit_small(method, H, W, n, step, seed, full):
+    if method == F.METHOD_MFMA_I8 and n != 8:
+        pytest.skip("the int8 search takes 8x8 ranges")
     img = gen_image(H, W, 12, seed)
     assert_same(gpu_encode(img, n, step, 12, method, full=full), O.encode(img, n, step, bits=12),
                 f"12b {H}x{W}")
 
 
 @pytest.mark.parametrize("full", [0, 1])
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", METHODS12)
 @pytest.mark.parametrize("kind", ["zeros", "max", "noise", "checker"])
 def test_parity_12bit_degenerate(method, kind, full):
     H = W = 48
@@ -199,6 +207,8 @@ def test_parity_12bit_degenerate(method, kind, full):
            "noise": rng.integers(0, 4096, (H, W)),
            "checker": (np.indices((H, W)).sum(0) % 2) * 4095}[kind].astype(np.uint16)
     for (n, step) in [(4, 4), (8, 2)]:
+        if method == F.METHOD_MFMA_I8 and n != 8:
+            continue
         assert_same(gpu_encode(img, n, step, 12, method, full=full),
                     O.encode(img, n, step, bits=12), kind)
 
@@ -218,7 +228,7 @@ def test_planted_codes_12bit(method):
 
 
 @pytest.mark.parametrize("full", [0, 1])
-@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("method", METHODS12)
 def test_ct12_512_every_range_matches_oracle(method, full):
     # 512x512 12-bit, 8x8 ranges, 16x16 domains at stride 2 (4096 x 496,008
     # candidates): all 4096 codes element by element
@@ -226,3 +236,29 @@ def test_ct12_512_every_range_matches_oracle(method, full):
     got = gpu_encode(img, 8, 2, 12, method, full=full)
     assert_same(got, oracle_table("ct12_512", img, 8, 2, bits=12),
                 f"ct12_512 method {method} full {full}")
+
+
+@pytest.mark.parametrize("method", [F.METHOD_MFMA, F.METHOD_MFMA_I8])
+def test_planted_codes_12bit_n8(method):
+    """Planted exact 8x8 ranges in a 12-bit image: residual 0 and the planted
+    code, on both matrix-core searches."""
+    H = W = 64
+    n, step = 8, 4
+    P = 4096
+    plants = [(56, (0, 0), 5, 0.5, 64.0 * 8), (63, (1, 2), 2, -0.25, P / 2.0)]
+    img = planted_image(H, W, n, step, 12, 31, plants)
+    gpu = gpu_encode(img, n, step, 12, method)
+    assert_same(gpu, O.encode(img, n, step, bits=12), "planted12 n8")
+    nx = (W - 2 * n) // step + 1
+    for (r, (dy, dx), k, s, o) in plants:
+        assert gpu["err"][r] == 0.0 and gpu["domain"][r] == dy * nx + dx and gpu["iso"][r] == k
+
+
+def test_int8_search_refuses_8bit_and_4x4():
+    for p in (F.Params(64, 64, 8, 8, 4, method=F.METHOD_MFMA_I8),
+              F.Params(64, 64, 12, 4, 4, method=F.METHOD_MFMA_I8)):
+        img = torch.zeros((64, 64), dtype=torch.uint8 if p.bit_depth == 8 else torch.uint16,
+                          device="cuda")
+        with pytest.raises(F.FicError) as e:
+            F.encode(img, p)
+        assert e.value.status == 2

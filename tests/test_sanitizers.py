@@ -14,9 +14,9 @@ HERE = os.path.join(ROOT, "tests", "sanitize")
 CSRC = os.path.join(ROOT, "paper_1404_0774_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 CLANG = "/opt/rocm/llvm/bin/clang++"
-SOURCES = ["fic_abi", "fic_batch", "fic_prep", "fic_seed", "fic_search_mfma",
-           "fic_search_mfma12", "fic_search_direct", "fic_decode", "fic_tuning",
-           "fic_stream"]
+# the library's own source list
+from paper_1404_0774_amd.build import SOURCES as _LIB_SOURCES  # noqa: E402
+SOURCES = [os.path.splitext(f)[0] for f in _LIB_SOURCES]
 SAN_ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0",
                UBSAN_OPTIONS="print_stacktrace=1")
 
