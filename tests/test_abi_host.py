@@ -200,7 +200,7 @@ def test_tuning_table_selection(clean_tuning):
     assert F.get_tuning(F.Params(512, 512, 8, 8, 4))["col_chunks"] == 8
 
 
-@pytest.mark.parametrize("field,value", [("bit_depth", 10), ("range_size", 6), ("method", 2),
+@pytest.mark.parametrize("field,value", [("bit_depth", 10), ("range_size", 6), ("method", 3),
                                          ("min_domains", -1), ("col_chunks", -1),
                                          ("col_chunks", 5000), ("seed_blocks", -2),
                                          ("seed_blocks", 65), ("item_blocks", -3)])
