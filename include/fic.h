@@ -70,7 +70,8 @@ enum fic_method {
 typedef struct {
   int32_t height, width; /* pixels; multiples of range_size */
   int32_t bit_depth;     /* 8 or 12 */
-  int32_t range_size;    /* n: 4 or 8 */
+  int32_t range_size;    /* n: 4, 8 or 16 (16: 8-bit images, matrix-core
+                            method; no adjoint, refinement or batch) */
   int32_t domain_step;   /* STEP >= 1 */
   int32_t s_bits;        /* contrast bits, 1..8 (5 in the reference setup) */
   int32_t o_bits;        /* offset bits, 1..min(8, bit_depth+1) (7) */
@@ -107,8 +108,8 @@ typedef struct {
  * NULL.  Errors: FIC_E_INVALID (null p, height or width not a multiple of n,
  * 2n larger than a side, STEP < 1, full_search not 0 or 1),
  * FIC_E_UNSUPPORTED (bit_depth not 8 or 12,
- * n not 4 or 8, s_bits/o_bits out of range, more candidates than the packed
- * 64-bit search key can index).
+ * n not 4, 8 or 16, s_bits/o_bits out of range, more candidates than the
+ * packed 64-bit search key can index).
  */
 int fic_query(const fic_params *p, int64_t *n_ranges, int64_t *n_domains,
               size_t *encode_ws_bytes, size_t *backward_ws_bytes);
@@ -266,7 +267,7 @@ int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
  * tau * n^2 (tau: a squared error per pixel) and whose side n is above
  * min_range_size is split into its four quadrants, which are encoded the
  * same way at side n / 2 (2n x 2n domains on the same STEP grid).  Sides
- * are 8 and 4 (so n_max / min_range_size is 1 or 2).  The leaves are
+ * are 16 (8-bit images), 8 and 4: up to three levels.  The leaves are
  * written top-level range by top-level range (row-major), each one's leaves
  * in Z order (top-left, top-right, bottom-left, bottom-right, recursively).
  * A leaf's domain index refers to the domain grid of its own side.
@@ -355,7 +356,7 @@ int fic_stream_unpack(const fic_params *p, const void *in, size_t in_bytes,
  *
  * fic_set_tuning -- replaces the table with n_entries entries (0 clears it).
  *   Errors: FIC_E_INVALID (NULL entries with n > 0, a field out of range:
- *   bit_depth 8|12, range_size 4|8, method, min_domains >= 0,
+ *   bit_depth 8|12, range_size 4|8|16, method, min_domains >= 0,
  *   col_chunks 0..4096, seed_blocks -1..64, item_blocks 0..4096).
  * fic_load_tuning -- replaces the table with the entries of a JSON file:
  *   every object holding a "bit_depth" key is one entry, read from the

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfic.so")
 SOURCES = ["fic_abi.hip", "fic_batch.hip", "fic_prep.hip", "fic_seed.hip",
-           "fic_search_mfma.hip", "fic_search_mfma12.hip", "fic_search_mfma12_i8.hip", "fic_search_direct.hip",
+           "fic_search_mfma.hip", "fic_search_mfma12.hip", "fic_search_mfma12_i8.hip",
+           "fic_search_mfma16.hip", "fic_search_direct.hip",
            "fic_decode.hip", "fic_tuning.hip", "fic_stream.hip",
            "fic_quadtree.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -83,8 +83,13 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
     return fail(FIC_E_INVALID, "domain_step %d < 1", p->domain_step);
   if (p->bit_depth != 8 && p->bit_depth != 12)
     return fail(FIC_E_UNSUPPORTED, "bit_depth %d (8 or 12)", p->bit_depth);
-  if (n != 4 && n != 8)
-    return fail(FIC_E_UNSUPPORTED, "range_size %d (4 or 8)", n);
+  if (n != 4 && n != 8 && n != 16)
+    return fail(FIC_E_UNSUPPORTED, "range_size %d (4, 8 or 16)", n);
+  // 16x16 ranges: the matrix-core search on 8-bit images (centred operands)
+  if (for_encode && n == 16 &&
+      (p->bit_depth != 8 || p->method != FIC_METHOD_MFMA))
+    return fail(FIC_E_UNSUPPORTED,
+                "16x16 ranges take 8-bit images and the matrix-core method");
   if (p->s_bits < 1 || p->s_bits > 8)
     return fail(FIC_E_UNSUPPORTED, "s_bits %d (1..8)", p->s_bits);
   // the code arrays hold one byte per index
@@ -337,6 +342,9 @@ int encode_launch(const fic_params *p, Geo g, const void *image,
   timing_mark(2, s);
   if (p->method == FIC_METHOD_DIRECT)
     e = launch_search_direct(g, b, t.chunks, s);
+  else if (g.n == 16)
+    e = launch_search_mfma16(
+        g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
   else if (p->method == FIC_METHOD_MFMA_I8)
     e = launch_search_mfma12_i8(
         g, b, t.chunks * (g.R_pad / kMfma12RangesPerWG), s);
@@ -405,6 +413,8 @@ int fic_decode_batch(const fic_params *p, int32_t n_images,
     return fail(FIC_E_INVALID, "null code or trajectory pointer");
   if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
   if (n_images < 1) return fail(FIC_E_INVALID, "n_images %d < 1", n_images);
+  if (g.n == 16)
+    return fail(FIC_E_UNSUPPORTED, "the batched decode takes 4x4 or 8x8 ranges");
   if ((long long)g.H * g.W * n_images > (1ll << 31))
     return fail(FIC_E_UNSUPPORTED, "%d images of %dx%d exceed 2^31 pixels",
                 n_images, g.H, g.W);
@@ -463,6 +473,8 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
   Geo g;
   int st = make_geo(p, g, /*for_encode=*/false);
   if (st) return st;
+  if (g.n == 16)
+    return fail(FIC_E_UNSUPPORTED, "the adjoint takes 4x4 or 8x8 ranges");
   if (!domain || !iso || !s || !o || !traj || !grad_xT || !grad_s || !grad_o ||
       !workspace)
     return fail(FIC_E_INVALID, "null pointer argument");
@@ -497,6 +509,8 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   Geo g;
   int st = make_geo(p, g, /*for_encode=*/false);
   if (st) return st;
+  if (g.n == 16)
+    return fail(FIC_E_UNSUPPORTED, "refinement takes 4x4 or 8x8 ranges");
   if (!domain || !iso || !s || !o || !image || !loss || !workspace)
     return fail(FIC_E_INVALID, "null pointer argument");
   if (iters < 0 || steps < 0)
@@ -533,8 +547,8 @@ int qt_plan(const fic_params *p, int n_min, QtPlan &q) {
   Geo g0;
   int st = make_geo(p, g0, /*for_encode=*/true);
   if (st) return st;
-  if (n_min != 4 && n_min != 8)
-    return fail(FIC_E_UNSUPPORTED, "min_range_size %d (4 or 8)", n_min);
+  if (n_min != 4 && n_min != 8 && n_min != 16)
+    return fail(FIC_E_UNSUPPORTED, "min_range_size %d (4, 8 or 16)", n_min);
   if (n_min > p->range_size)
     return fail(FIC_E_INVALID, "min_range_size %d above range_size %d", n_min,
                 p->range_size);

@@ -54,6 +54,9 @@ int plan_batch(const fic_params *slices, int n, BatchPlan &pl) {
   }
   if (slices[0].bit_depth != 8)
     return abi_fail(FIC_E_UNSUPPORTED, "batched search takes 8-bit slices");
+  if (slices[0].range_size == 16 || slices[0].method != FIC_METHOD_MFMA)
+    return abi_fail(FIC_E_UNSUPPORTED,
+                    "batched search takes 4x4 or 8x8 ranges, matrix cores");
 
   // work list: slices largest first; within a slice, column chunks outer
   // and row groups inner so that workgroups running together share domains

@@ -537,9 +537,24 @@ size_t decode_backward_ws_bytes(const Geo &g) {
   return adj_layout(g, nullptr).total;
 }
 
+DecGeo dec_geo(const Geo &g) {
+  DecGeo d;
+  d.H = g.H;
+  d.W = g.W;
+  d.n = g.n;
+  d.step = g.step;
+  d.RW = g.RW;
+  d.NX = g.NX;
+  d.ND = g.ND;
+  return d;
+}
+
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
                          const uint8_t *iso, const float *s, const float *o,
                          int iters, float x0, float *traj, hipStream_t st) {
+  if (g.n != 4 && g.n != 8)  // other range sizes: the generic step
+    return launch_decode_scaled(dec_geo(g), domain, iso, s, o, iters, x0, traj,
+                                st);
   const long long HW = (long long)g.H * g.W;
   const int bs = 256;
   const dim3 grid((unsigned)((HW + bs - 1) / bs));

@@ -164,6 +164,8 @@ hipError_t launch_search_mfma(const Geo &g, const EncBufs &b,
                               hipStream_t st);
 hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
                                 int workgroups, hipStream_t st);
+hipError_t launch_search_mfma16(const Geo &g, const EncBufs &b,
+                                int workgroups, hipStream_t st);
 hipError_t launch_search_mfma12_i8(const Geo &g, const EncBufs &b,
                                    int workgroups, hipStream_t st);
 hipError_t launch_search_direct(const Geo &g, const EncBufs &b, int chunks,

@@ -60,6 +60,8 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
       if (g.bits == 12) {
         vh[j] = (_Float16)(float)(A >> 7);
         vl[j] = (_Float16)(float)(A & 127);
+      } else if (N == 16) {
+        vh[j] = (_Float16)(float)(A - 510);  // centred: |A - 510| <= 510
       } else {
         vh[j] = (_Float16)(float)A;
       }
@@ -172,6 +174,8 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
             r8[k * K + pp] = (int8_t)(v[e] >> 6);
             r8[(size_t)g.R_pad * 8 * K + k * K + pp] = (int8_t)(v[e] & 63);
           }
+        } else if (N == 16) {
+          row_hi[k * K + pp] = (_Float16)(float)(v[e] - 128);  // centred
         } else {
           row_hi[k * K + pp] = (_Float16)(float)v[e];
         }
@@ -213,28 +217,33 @@ __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
                                               EncBufs b) {
   if ((int)blockIdx.x < g.n_dwg) {
     prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
-  } else if (g.pix_a) {
+  } else if (g.pix_a || N == 16) {
+    // (16x16 ranges: a row of 16 pixels per lane, 16 lanes per range)
     // a row per lane when only statistics are needed, a pixel per lane when
     // the range operand is written as well (its scattered stores spread)
     prep_ranges_body<Pix, N, N>(g, img, b, blockIdx.x - g.n_dwg);
   } else {
-    prep_ranges_body<Pix, N, N * N>(g, img, b, blockIdx.x - g.n_dwg);
+    if constexpr (N != 16)
+      prep_ranges_body<Pix, N, N * N>(g, img, b, blockIdx.x - g.n_dwg);
   }
 }
 
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_finalize(Geo g, const Pix *img,
                                                   EncBufs b, fic_codes out) {
-  finalize_body<Pix, N, N * N>(g, img, b, out, blockIdx.x);
+  // a pixel per lane; 16x16 ranges a row per lane (a range spans 16 lanes)
+  finalize_body<Pix, N, (N == 16 ? N : N * N)>(g, img, b, out, blockIdx.x);
 }
 
 template <typename Pix>
 hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
                      hipStream_t st) {
-  const long long lanes = g.pix_a ? g.n : g.K;  // per range, as k_prep
+  const long long lanes = (g.pix_a || g.n == 16) ? g.n : g.K;  // as k_prep
   const long long rwg = ((long long)g.R_pad * lanes + 255) / 256;
   const dim3 grid((unsigned)(g.n_dwg + rwg));
-  if (g.n == 8)
+  if (g.n == 16)
+    hipLaunchKernelGGL((k_prep<Pix, 16>), grid, dim3(256), 0, st, g, img, b);
+  else if (g.n == 8)
     hipLaunchKernelGGL((k_prep<Pix, 8>), grid, dim3(256), 0, st, g, img, b);
   else
     hipLaunchKernelGGL((k_prep<Pix, 4>), grid, dim3(256), 0, st, g, img, b);
@@ -411,7 +420,14 @@ hipError_t launch_prep(const Geo &g, const void *image, const EncBufs &b,
 hipError_t launch_finalize(const Geo &g, const void *image, const EncBufs &b,
                            fic_codes out, hipStream_t st) {
   const int bs = 256;
-  const dim3 grid((unsigned)(((long long)g.R_pad * g.K + bs - 1) / bs));
+  const long long lanes = g.n == 16 ? g.n : g.K;  // per range, as k_finalize
+  const dim3 grid((unsigned)(((long long)g.R_pad * lanes + bs - 1) / bs));
+  if (g.n == 16) {
+    if (g.bits != 8) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_finalize<uint8_t, 16>), grid, dim3(bs), 0, st, g,
+                       (const uint8_t *)image, b, out);
+    return hipGetLastError();
+  }
   if (g.bits == 12) {
     if (g.n == 8)
       hipLaunchKernelGGL((k_finalize<uint16_t, 8>), grid, dim3(bs), 0, st, g,

@@ -185,7 +185,7 @@ hipError_t launch_seed_batch(const BatchDev &bd, int nblocks, hipStream_t st) {
 
 hipError_t launch_seed_dense(const Geo &g, const EncBufs &b, int nblocks,
                              hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
+  if (nblocks <= 0 || g.K > 64) return hipSuccess;
   const dim3 grid(g.R_pad / 8);
   auto kern = g.bits == 12 ? (g.K == 64 ? k_seed_dense<64, true>
                                         : k_seed_dense<16, true>)

@@ -34,9 +34,10 @@ constexpr int kMaxItemBlocks = 4096;
 // search launch, one seed block (ranked for a starting bound) once there are
 // 16 or more column blocks, 16 column blocks per batched work item.
 Tune default_tune(const Geo &g, int method) {
-  const int per_wg = (g.bits == 12 && method != FIC_METHOD_DIRECT)
-                         ? kMfma12RangesPerWG
-                         : kMfmaRangesPerWG;
+  const int per_wg =
+      ((g.bits == 12 && method != FIC_METHOD_DIRECT) || g.n == 16)
+          ? kMfma12RangesPerWG
+          : kMfmaRangesPerWG;
   const int row_groups = std::max(1, g.R_pad / per_wg);
   Tune t;
   t.seed_blocks = g.NCB >= 16 ? 1 : 0;
@@ -50,8 +51,9 @@ bool valid_entry(const fic_tuning &e, char *msg, size_t len) {
     snprintf(msg, len, "tuning entry: bit_depth %d (8 or 12)", e.bit_depth);
     return false;
   }
-  if (e.range_size != 4 && e.range_size != 8) {
-    snprintf(msg, len, "tuning entry: range_size %d (4 or 8)", e.range_size);
+  if (e.range_size != 4 && e.range_size != 8 && e.range_size != 16) {
+    snprintf(msg, len, "tuning entry: range_size %d (4, 8 or 16)",
+             e.range_size);
     return false;
   }
   if (e.method != FIC_METHOD_MFMA && e.method != FIC_METHOD_DIRECT &&
@@ -253,6 +255,8 @@ Tune resolve_tune(const Geo &g, int method) {
   // the 8-bit, n = 8 matrix-core search seeds itself and has no range
   // operand for the seed pass to read
   if (method == FIC_METHOD_MFMA && g.bits == 8 && g.n == 8) t.seed_blocks = 0;
+  // 16x16 ranges keep centred operands, which the seed pass does not read
+  if (g.n == 16) t.seed_blocks = 0;
   t.chunks = std::max(1, std::min(t.chunks, g.NCB));
   t.item_blocks = std::max(1, t.item_blocks);
   return t;

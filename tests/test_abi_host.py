@@ -308,7 +308,7 @@ def test_quadtree_validates_before_gpu_work():
     nb, ml = F.quadtree_query(p, 4)
     assert ml == 4096 and nb > 0
     assert F.quadtree_query(p, 8)[1] == 1024
-    for n_min, status in [(2, 2), (16, 2), (0, 2)]:
+    for n_min, status in [(2, 2), (16, 1), (0, 2), (32, 2)]:
         with pytest.raises(F.FicError) as e:
             F.quadtree_query(p, n_min)
         assert e.value.status == status

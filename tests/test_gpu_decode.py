@@ -109,6 +109,18 @@ def test_decode_batch_matches_single_decodes_and_oracle(H, W, n, step):
         assert np.abs(traj[b].cpu().numpy() - ref).max() <= 1e-3
 
 
+def test_decode_16x16_ranges_matches_oracle():
+    H, W, n, step, T = 128, 96, 16, 8, 12
+    img = gen_image(H, W, 8, 52)
+    c = O.encode(img, n, step)
+    s, o = O.dequantize(c["s_idx"], c["o_idx"])
+    p = F.Params(H, W, 8, n, step)
+    traj = F.decode(dev(c["domain"], torch.int32), dev(c["iso"], torch.uint8),
+                    dev(s, torch.float32), dev(o, torch.float32), p, T, 128.0).cpu().numpy()
+    ref = O.decode(H, W, n, step, c["domain"], c["iso"], s, o, T, 128.0)
+    assert np.abs(traj - ref).max() <= 1e-3
+
+
 def test_decode_scaled_rejects_fractional_pixels():
     p = F.Params(64, 64, 8, 4, 4)
     z = torch.zeros(256, dtype=torch.int32, device="cuda")

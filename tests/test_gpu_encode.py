@@ -262,3 +262,36 @@ def test_int8_search_refuses_8bit_and_4x4():
         with pytest.raises(F.FicError) as e:
             F.encode(img, p)
         assert e.value.status == 2
+
+
+# --- 16x16 ranges (8-bit, centred FP16 operands) ------------------------------
+
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("H,W,step,seed", [(64, 64, 8, 71), (128, 96, 4, 72), (96, 160, 2, 73)])
+def test_16x16_ranges_match_oracle(H, W, step, seed, full):
+    img = gen_image(H, W, 8, seed)
+    assert_same(gpu_encode(img, 16, step, 8, F.METHOD_MFMA, full=full), O.encode(img, 16, step),
+                f"n16 {H}x{W}")
+
+
+@pytest.mark.parametrize("kind", ["zeros", "max", "checker", "noise", "halves"])
+def test_16x16_ranges_degenerate_and_extreme_images(kind):
+    # "max" and "checker" put the centred sums at their bounds
+    H = W = 64
+    rng = np.random.default_rng(8)
+    img = {"zeros": np.zeros((H, W)), "max": np.full((H, W), 255),
+           "checker": (np.indices((H, W)).sum(0) % 2) * 255,
+           "noise": rng.integers(0, 256, (H, W)),
+           "halves": np.where(np.arange(W)[None, :] < W // 2, 255, 0) * np.ones((H, 1))
+           }[kind].astype(np.uint8)
+    for full in (0, 1):
+        assert_same(gpu_encode(img, 16, 8, 8, F.METHOD_MFMA, full=full), O.encode(img, 16, 8), kind)
+
+
+def test_16x16_ranges_refuse_the_plain_method_and_12bit():
+    for bits, method in ((8, F.METHOD_DIRECT), (12, F.METHOD_MFMA)):
+        p = F.Params(64, 64, bits, 16, 8, method=method)
+        img = torch.zeros((64, 64), dtype=torch.uint8 if bits == 8 else torch.uint16, device="cuda")
+        with pytest.raises(F.FicError) as e:
+            F.encode(img, p)
+        assert e.value.status == 2

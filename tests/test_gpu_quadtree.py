@@ -63,3 +63,18 @@ def test_single_level_is_the_plain_encode():
     for k in ("domain", "iso", "s_idx", "o_idx", "err"):
         assert np.array_equal(got[k], ref[k]), k
     assert np.all(got["size"] == 8)
+
+
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("tau", [5.0, 40.0, -1.0])
+def test_three_level_quadtree_matches_oracle(tau, full):
+    # 16x16 ranges split into 8x8 and then 4x4
+    img = gen_image(128, 128, 8, 66)
+    assert_leaves(gpu_quadtree(img, 8, 16, 4, 4, tau, full=full),
+                  O.encode_quadtree(img, 16, 4, 4, tau), f"16->4 tau {tau}")
+
+
+def test_decode_workload_three_level_quadtree():
+    img = gen_image(256, 256, 8, 5)
+    assert_leaves(gpu_quadtree(img, 8, 16, 4, 4, 20.0), O.encode_quadtree(img, 16, 4, 4, 20.0),
+                  "256 16->4")
