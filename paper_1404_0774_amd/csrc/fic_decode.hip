@@ -18,6 +18,9 @@
 // domain shared by thousands of ranges (flat background) thus costs a short
 // sum per pixel, and every sum has a fixed order, so the result is bitwise
 // reproducible.
+#include <hip/hip_cooperative_groups.h>
+
+#include <algorithm>
 #include <utility>
 
 #include "fic_device.h"
@@ -48,6 +51,53 @@ __global__ void k_decode_step(Geo g, const int32_t *domain, const uint8_t *iso,
   const float *c = x + (size_t)cy * g.W + cx;
   const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
   y[p] = fmaf(s[r], u, o[r]);
+}
+
+// All iterations in one cooperative launch: every thread keeps the source
+// cell offset, s and o of up to PPT pixels (p = thread + i * threads) in
+// registers and the grid synchronises once per iteration, instead of one
+// launch per iteration that looks the codes up again.  The arithmetic is
+// k_decode_step's, so the iterates are identical.
+template <int N, int PPT>
+__global__ __launch_bounds__(256) void k_decode_persist(
+    Geo g, const int32_t *domain, const uint8_t *iso, const float *s,
+    const float *o, int iters, float x0, float *traj) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const int HW = g.H * g.W;
+  const int nth = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  int src[PPT];
+  float sv[PPT], ov[PPT];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int p = tid + q * nth;
+    src[q] = -1;
+    sv[q] = ov[q] = 0.0f;
+    if (p < HW) {
+      const int py = p / g.W, px = p % g.W;
+      const int r = (py / N) * g.RW + px / N;
+      const int d = clamp_dom(domain[r], g.ND);
+      int si, sj;
+      sigma(iso[r], py % N, px % N, N - 1, si, sj);
+      src[q] = ((d / g.NX) * g.step + 2 * si) * g.W + (d % g.NX) * g.step +
+               2 * sj;
+      sv[q] = s[r];
+      ov[q] = o[r];
+      traj[p] = x0;
+    }
+  }
+  for (int t = 0; t < iters; ++t) {
+    grid.sync();  // iterate t is complete everywhere
+    const float *x = traj + (size_t)t * HW;
+    float *y = traj + (size_t)(t + 1) * HW;
+#pragma unroll
+    for (int q = 0; q < PPT; ++q) {
+      if (src[q] < 0) continue;
+      const float *c = x + src[q];
+      const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
+      y[tid + q * nth] = fmaf(sv[q], u, ov[q]);
+    }
+  }
 }
 
 // Any range size n (a decode at another scale): one thread per output pixel.
@@ -109,6 +159,9 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 }
 
 // --- the domain -> ranges table --------------------------------------------
+
+// Decode in one cooperative launch when the image fits the resident grid.
+constexpr bool kDecodePersistent = true;
 
 constexpr int kSeg = 16;     // ranges per list segment
 constexpr int kGather = 32;  // segment partials loaded per round
@@ -331,11 +384,12 @@ __global__ __launch_bounds__(256) void k_adj_step(
 // kGather: a domain shared by a thousand flat ranges has ~100 segments, and
 // the pixels it covers would otherwise wait for ~13 rounds of loads).
 template <int N>
-__global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
-                                                const float *partial,
-                                                float *gout) {
+__device__ __forceinline__ void grad_x_body(const Geo &g,
+                                            const int32_t *segoff,
+                                            const float *partial, float *gout,
+                                            int bid) {
   constexpr int K = N * N;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int q = bid * blockDim.x + threadIdx.x;
   if (q >= g.H * g.W) return;
   const int qy = q / g.W, qx = q % g.W;
   const int span = 2 * N;
@@ -361,6 +415,67 @@ __global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
       }
     }
   gout[q] = acc;
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
+                                                const float *partial,
+                                                float *gout) {
+  grad_x_body<N>(g, segoff, partial, gout, blockIdx.x);
+}
+
+// Device pointers of the adjoint table and per-step buffers.
+struct AdjDev {
+  const int32_t *nseg, *segoff, *list;
+  const int2 *seg;
+  float *partial, *gbuf0, *gbuf1;
+};
+
+// All reverse steps in one cooperative launch: each step's two parts are
+// the per-step kernels' bodies run over virtual workgroups, with a grid
+// synchronisation after the segment partials and after the gradient image,
+// so every sum keeps its order and the result equals the per-step launches.
+template <int N>
+__global__ __launch_bounds__(256) void k_adj_persist(
+    Geo g, const int32_t *domain, const uint8_t *iso, const float *s,
+    int iters, const float *traj, const float *grad_xT, float *grad_s,
+    float *grad_o, AdjDev a, int nb_so, int nb_sp, int nb_gx) {
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  const size_t HW = (size_t)g.H * g.W;
+  const float *gnext = grad_xT;
+  for (int t = iters - 1; t >= 0; --t) {
+    const float *x = traj + (size_t)t * HW;
+    for (int vb = blockIdx.x; vb < nb_so; vb += gridDim.x)
+      grad_so_body<N>(g, domain, iso, x, gnext, grad_s, grad_o,
+                      t == iters - 1 ? 1 : 0, vb);
+    if (t == 0) break;
+    for (int vb = blockIdx.x; vb < nb_sp; vb += gridDim.x)
+      seg_partial_body<N>(g, a.nseg, a.seg, a.list, iso, s, gnext, a.partial,
+                          vb);
+    grid.sync();  // the step's segment partials are complete
+    float *gout = (t & 1) ? a.gbuf1 : a.gbuf0;
+    for (int vb = blockIdx.x; vb < nb_gx; vb += gridDim.x)
+      grad_x_body<N>(g, a.segoff, a.partial, gout, vb);
+    grid.sync();  // g_t is complete
+    gnext = gout;
+  }
+}
+
+constexpr int kMaxDevices = 64;
+
+// Workgroups of 256 threads that can be resident at once for a kernel on
+// the current device (0 if unknown).
+template <typename Kern>
+int resident_groups(Kern kern) {
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+      !prop.cooperativeLaunch ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) !=
+          hipSuccess)
+    return 0;
+  return per_cu * prop.multiProcessorCount;
 }
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -435,10 +550,56 @@ void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
 
 // The reverse steps, with the table already built.
 template <int N>
+bool adjoint_persist(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                     const float *s, int iters, const float *traj,
+                     const float *grad_xT, float *grad_s, float *grad_o,
+                     const AdjWs &a, hipStream_t st) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone)
+    return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return false;
+  static int groups_max[kMaxDevices];
+  static bool known[kMaxDevices];
+  if (!known[dev]) {
+    groups_max[dev] = resident_groups(k_adj_persist<N>);
+    known[dev] = true;
+  }
+  const long long HW = (long long)g.H * g.W;
+  int nb_so = (int)(((long long)g.R * N * N + 255) / 256);
+  int nb_sp = (int)(((long long)a.max_seg * N * N + 255) / 256);
+  int nb_gx = (int)((HW + 255) / 256);
+  int groups = std::max(nb_so, std::max(nb_sp, nb_gx));
+  groups = std::min(groups, groups_max[dev]);
+  if (groups < 1) return false;
+  AdjDev d;
+  d.nseg = a.segoff + g.ND;
+  d.segoff = a.segoff;
+  d.list = a.list;
+  d.seg = a.seg;
+  d.partial = a.partial;
+  d.gbuf0 = a.gbuf0;
+  d.gbuf1 = a.gbuf1;
+  Geo gg = g;
+  void *args[] = {&gg,         (void *)&domain, (void *)&iso,   (void *)&s,
+                  &iters,      (void *)&traj,   (void *)&grad_xT,
+                  (void *)&grad_s, (void *)&grad_o, &d, &nb_so, &nb_sp, &nb_gx};
+  return hipLaunchCooperativeKernel((const void *)k_adj_persist<N>,
+                                    dim3((unsigned)groups), dim3(256), args, 0,
+                                    st) == hipSuccess;
+}
+
+template <int N>
 void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
                    const float *s, int iters, const float *traj,
                    const float *grad_xT, float *grad_s, float *grad_o,
                    const AdjWs &a, hipStream_t st) {
+  if (kDecodePersistent && iters > 0 &&
+      adjoint_persist<N>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
+                         grad_o, a, st))
+    return;
   const size_t HW = (size_t)g.H * g.W;
   const int bs = 256;
   const float *gnext = grad_xT;
@@ -549,12 +710,64 @@ DecGeo dec_geo(const Geo &g) {
   return d;
 }
 
+// One cooperative launch for the whole decode when the image fits the
+// resident grid at up to kPersistPixels pixels per thread; returns false
+// (nothing enqueued) when it does not or the device cannot launch it.
+constexpr int kPersistPixels = 4;
+
+template <int N, int PPT>
+bool decode_persist_try(const Geo &g, const int32_t *domain,
+                        const uint8_t *iso, const float *s, const float *o,
+                        int iters, float x0, float *traj, hipStream_t st,
+                        int groups_max) {
+  const long long HW = (long long)g.H * g.W;
+  const long long groups = (HW + 256LL * PPT - 1) / (256LL * PPT);
+  if (groups > groups_max) return false;
+  Geo gg = g;
+  void *args[] = {&gg,    (void *)&domain, (void *)&iso, (void *)&s,
+                  (void *)&o, &iters,      &x0,          &traj};
+  return hipLaunchCooperativeKernel((const void *)k_decode_persist<N, PPT>,
+                                    dim3((unsigned)groups), dim3(256), args, 0,
+                                    st) == hipSuccess;
+}
+
+template <int N>
+bool decode_persist(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                    const float *s, const float *o, int iters, float x0,
+                    float *traj, hipStream_t st) {
+  // a stream under capture takes the per-iteration launches instead
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess ||
+      cap != hipStreamCaptureStatusNone)
+    return false;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+    return false;
+  // resident workgroups per device and pixels-per-thread choice (computed
+  // once; concurrent first calls compute the same values)
+  static int groups_max[kMaxDevices][2];
+  static bool known[kMaxDevices];
+  if (!known[dev]) {
+    groups_max[dev][0] = resident_groups(k_decode_persist<N, 1>);
+    groups_max[dev][1] = resident_groups(k_decode_persist<N, kPersistPixels>);
+    known[dev] = true;
+  }
+  return decode_persist_try<N, 1>(g, domain, iso, s, o, iters, x0, traj, st,
+                                  groups_max[dev][0]) ||
+         decode_persist_try<N, kPersistPixels>(g, domain, iso, s, o, iters, x0,
+                                               traj, st, groups_max[dev][1]);
+}
+
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
                          const uint8_t *iso, const float *s, const float *o,
                          int iters, float x0, float *traj, hipStream_t st) {
   if (g.n != 4 && g.n != 8)  // other range sizes: the generic step
     return launch_decode_scaled(dec_geo(g), domain, iso, s, o, iters, x0, traj,
                                 st);
+  if (kDecodePersistent && iters > 0 &&
+      (g.n == 8 ? decode_persist<8>(g, domain, iso, s, o, iters, x0, traj, st)
+                : decode_persist<4>(g, domain, iso, s, o, iters, x0, traj, st)))
+    return hipGetLastError();
   const long long HW = (long long)g.H * g.W;
   const int bs = 256;
   const dim3 grid((unsigned)((HW + bs - 1) / bs));
