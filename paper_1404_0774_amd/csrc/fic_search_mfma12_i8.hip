@@ -129,7 +129,8 @@ __device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
 // l mod 32.
 template <int K>
 __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) {
-  constexpr int KS = K / 16;
+  static_assert(K % 32 == 0, "32-deep k-steps");
+  constexpr int KS = K / 32;  // k-steps of v_mfma_i32_32x32x32_i8
   __shared__ unsigned long long s_best[4][kWR];
   __shared__ double2 s_rstat[4][kWR];
   __shared__ int s_slot[4][kWR];
