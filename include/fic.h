@@ -130,6 +130,25 @@ int fic_encode(const fic_params *p, const void *image, fic_codes out,
                void *workspace, size_t ws_bytes, void *stream);
 
 /*
+ * fic_encode_noalloc -- fic_encode for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid allocation).  Same search, same codes; the workspace is a static
+ * 32 MiB device array inside the library (one per device, held from module
+ * load until the process ends) instead of a caller buffer.
+ *   image, out  as for fic_encode
+ * The first call on a device looks up that device's copy of the array
+ * (hipGetSymbolAddress); no call allocates or frees memory.  Every call on
+ * one device shares its array, which keeps the last call's contents: calls
+ * that overlap on one device (two streams, two threads) race and must be
+ * serialised by the caller.  fic_search_counts does not apply.
+ * Errors: those of fic_encode's validation; FIC_E_WORKSPACE when
+ * fic_query's encode_ws_bytes exceeds 32 MiB (nothing is enqueued);
+ * FIC_E_HIP.
+ */
+int fic_encode_noalloc(const fic_params *p, const void *image, fic_codes out,
+                       void *stream);
+
+/*
  * fic_search_counts -- host, synchronous.  After an fic_encode of `p` has
  * completed on `workspace`, reports how many ranges and how many domains the
  * search kernel visited (either method): with full_search = 0 those with

@@ -97,6 +97,8 @@ def lib():
                                         ctypes.POINTER(ctypes.c_int64)]
         L.fic_encode.restype = ctypes.c_int
         L.fic_encode.argtypes = [P, vp, _Codes, vp, sz, vp]
+        L.fic_encode_noalloc.restype = ctypes.c_int
+        L.fic_encode_noalloc.argtypes = [P, vp, _Codes, vp]
         L.fic_decode.restype = ctypes.c_int
         L.fic_decode.argtypes = [P, vp, vp, vp, vp, i32, ctypes.c_float, vp, vp]
         L.fic_decode_batch.restype = ctypes.c_int

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "fic_internal.h"
@@ -363,10 +364,66 @@ int encode_launch(const fic_params *p, Geo g, const void *image,
   return ok();
 }
 
+// --- encode without allocation: scratch in a static device array ----------
+
+// Encode workspace of fic_encode_noalloc.  Each device the library runs on
+// holds its own copy from module load until the process ends.  In host code
+// this name is a host-side stand-in, never a device address: kernels get the
+// address that hipGetSymbolAddress returns for the current device.
+constexpr size_t kScratchBytes = 32ull << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices];
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int scratch_address(void **ptr) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(FIC_E_UNSUPPORTED, "device %d beyond the %d the static scratch "
+                "table covers", dev, kScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *a = nullptr;
+    e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!a || ((uintptr_t)a & 255))
+      return fail(FIC_E_HIP, "static scratch address %p is not 256-byte "
+                  "aligned", a);
+    g_scratch_ptr[dev] = a;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return FIC_OK;
+}
+
 }  // namespace
 }  // namespace fic
 
 extern "C" {
+
+int fic_encode_noalloc(const fic_params *p, const void *image, fic_codes out,
+                       void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/true);
+  if (st) return st;
+  if (!image || !out.domain || !out.iso || !out.s_idx || !out.o_idx ||
+      !out.err)
+    return fail(FIC_E_INVALID, "null image or code pointer");
+  const EncLayout L = enc_layout(g);
+  if (L.total > kScratchBytes)
+    return fail(FIC_E_WORKSPACE, "encode needs %zu bytes, the static scratch "
+                "array holds %zu", L.total, kScratchBytes);
+  void *ws = nullptr;
+  st = scratch_address(&ws);
+  if (st) return st;
+  // every buffer the launches read is written earlier in the same encode,
+  // so the previous call's bytes need no clearing
+  return encode_launch(p, g, image, out, ws, stream);
+}
 
 int fic_search_counts(const fic_params *p, const void *workspace,
                       size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains) {
