@@ -215,7 +215,8 @@ int fic_decode(const fic_params *p, const int32_t *domain, const uint8_t *iso,
  * (domain[b * n_ranges + r], likewise iso, s, o); traj receives image b's
  * trajectory at traj + b * (iters + 1) * height * width, laid out as
  * fic_decode's.  Errors: FIC_E_INVALID (null pointers, iters < 0,
- * n_images < 1), FIC_E_UNSUPPORTED (more than 2^31 pixels in one iterate).
+ * n_images < 1), FIC_E_UNSUPPORTED (more than 2^31 pixels in one iterate,
+ * more than 65535 images, 16x16 ranges).
  */
 int fic_decode_batch(const fic_params *p, int32_t n_images,
                      const int32_t *domain, const uint8_t *iso,

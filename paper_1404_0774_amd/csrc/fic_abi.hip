@@ -470,6 +470,8 @@ int fic_decode_batch(const fic_params *p, int32_t n_images,
     return fail(FIC_E_INVALID, "null code or trajectory pointer");
   if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
   if (n_images < 1) return fail(FIC_E_INVALID, "n_images %d < 1", n_images);
+  if (n_images > 65535)
+    return fail(FIC_E_UNSUPPORTED, "n_images %d > 65535", n_images);
   if (g.n == 16)
     return fail(FIC_E_UNSUPPORTED, "the batched decode takes 4x4 or 8x8 ranges");
   if ((long long)g.H * g.W * n_images > (1ll << 31))

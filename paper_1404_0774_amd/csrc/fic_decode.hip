@@ -1,10 +1,12 @@
 // fic_decode.hip -- iterating the partitioned IFS map (eq. 6) and its
 // reverse-mode derivative with respect to the contrast s and offset o.
 //
-// Forward: one launch per iteration, one thread per output pixel:
+// Forward: one thread per output pixel,
 //   x_{t+1}[p] = s_r * ((x00 + x01) + (x10 + x11)) * 0.25 + o_r
 // where p is pixel (i, j) of range r and x.. is the 2x2 cell sigma_k(i, j)
-// of the range's domain in x_t.
+// of the range's domain in x_t; one launch per iteration, or for small
+// images one launch per three iterations with the intermediate values a
+// pixel needs recomputed.
 //
 // Reverse: with g_{t+1} = dL/dx_{t+1} and u_t[p] the cell mean read by p,
 //   dL/ds_r += sum_{p in r} g_{t+1}[p] u_t[p],  dL/do_r += sum_{p in r} g_{t+1}[p]
@@ -18,8 +20,6 @@
 // domain shared by thousands of ranges (flat background) thus costs a short
 // sum per pixel, and every sum has a fixed order, so the result is bitwise
 // reproducible.
-#include <hip/hip_cooperative_groups.h>
-
 #include <algorithm>
 #include <utility>
 
@@ -35,67 +35,105 @@ __device__ __forceinline__ int clamp_dom(int d, int nd) {
   return d < 0 ? 0 : (d >= nd ? nd - 1 : d);
 }
 
-template <int N>
-__global__ void k_decode_step(Geo g, const int32_t *domain, const uint8_t *iso,
-                              const float *s, const float *o, const float *x,
-                              float *y) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= g.H * g.W) return;
-  const int py = p / g.W, px = p % g.W;
-  const int ry = py / N, rx = px / N, i = py % N, j = px % N;
-  const int r = ry * g.RW + rx;
-  const int d = clamp_dom(domain[r], g.ND);
-  int si, sj;
-  sigma(iso[r], i, j, N - 1, si, sj);
-  const int cy = (d / g.NX) * g.step + 2 * si, cx = (d % g.NX) * g.step + 2 * sj;
-  const float *c = x + (size_t)cy * g.W + cx;
-  const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
-  y[p] = fmaf(s[r], u, o[r]);
-}
-
-// All iterations in one cooperative launch: every thread keeps the source
-// cell offset, s and o of up to PPT pixels (p = thread + i * threads) in
-// registers and the grid synchronises once per iteration, instead of one
-// launch per iteration that looks the codes up again.  The arithmetic is
-// k_decode_step's, so the iterates are identical.
-template <int N, int PPT>
-__global__ __launch_bounds__(256) void k_decode_persist(
-    Geo g, const int32_t *domain, const uint8_t *iso, const float *s,
-    const float *o, int iters, float x0, float *traj) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  const int HW = g.H * g.W;
-  const int nth = gridDim.x * blockDim.x;
-  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-  int src[PPT];
-  float sv[PPT], ov[PPT];
+// One iteration for ranges of side N (4 or 8), a workgroup per RPW = 256 / N
+// consecutive ranges of one image.  Phase 1: thread (range, a) pools cell row
+// a of the range's domain, reading two image rows of 2N floats (16-byte loads
+// when V = 4), into LDS.  Phase 2: thread (row i, range) writes row i of the
+// range, pixel (i, j) = s * pooled[sigma_k(i, j)] + o, adjacent threads
+// writing adjacent ranges.  Pooling and the affine step are the expressions
+//   u = ((x00 + x01) + (x10 + x11)) * 0.25,  x' = fma(s, u, o)
+// for every pixel, whatever the launch shape.
+//
+// Batches: image b (of gridDim.x / wpi) has its codes at entry b R and its
+// iterates t and t + 1 at xs + b xstride and ys + b xstride.  With xcd_map,
+// workgroup L takes virtual workgroup (L mod 8) G/8 + L/8 (G a multiple of
+// 8): workgroups go to the 8 XCDs in turn, so each XCD then holds a run of
+// whole images and reads iterate t from the L2 that wrote it.
+//
+// FIRST: the first iteration from the constant start x0, with no reads of an
+// iterate: every cell pools to u0 (the same expression on four x0), and the
+// launch writes both x_0 = x0 (at xs) and x_1 (at ys) over its ranges.
+template <int N, int V, bool FIRST>
+__global__ __launch_bounds__(256) void k_decode_pool(
+    Geo g, int wpi, int xcd_map, const int32_t *domain, const uint8_t *iso,
+    const float *s, const float *o, const float *xs, float *ys,
+    long long xstride, float x0) {
+  constexpr int RPW = 256 / N;
+  constexpr int PS = N * N + 1;  // padded: phase 2 reads at stride PS
+  __shared__ float pool[RPW * PS];
+  const int L = blockIdx.x;
+  const int v = xcd_map ? (L & 7) * (int)(gridDim.x >> 3) + (L >> 3) : L;
+  const int b = v / wpi;
+  const int r0 = (v - b * wpi) * RPW;
+  const size_t cb = (size_t)b * g.R;
+  const float *x = xs + (size_t)b * xstride;
+  float *y = ys + (size_t)b * xstride;
+  if constexpr (!FIRST) {
+    const int rl = threadIdx.x / N, a = threadIdx.x % N;
+    const int r = r0 + rl;
+    if (r < g.R) {
+      const int d = clamp_dom(domain[cb + r], g.ND);
+      const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
+      const float *p0 = x + (size_t)(Y + 2 * a) * g.W + X;
+      const float *p1 = p0 + g.W;
+      float u0[2 * N], u1[2 * N];
+      if constexpr (V == 4) {
 #pragma unroll
-  for (int q = 0; q < PPT; ++q) {
-    const int p = tid + q * nth;
-    src[q] = -1;
-    sv[q] = ov[q] = 0.0f;
-    if (p < HW) {
-      const int py = p / g.W, px = p % g.W;
-      const int r = (py / N) * g.RW + px / N;
-      const int d = clamp_dom(domain[r], g.ND);
-      int si, sj;
-      sigma(iso[r], py % N, px % N, N - 1, si, sj);
-      src[q] = ((d / g.NX) * g.step + 2 * si) * g.W + (d % g.NX) * g.step +
-               2 * sj;
-      sv[q] = s[r];
-      ov[q] = o[r];
-      traj[p] = x0;
+        for (int q = 0; q < 2 * N; q += 4) {
+          const float4 e = *(const float4 *)(p0 + q);
+          const float4 f = *(const float4 *)(p1 + q);
+          u0[q] = e.x; u0[q + 1] = e.y; u0[q + 2] = e.z; u0[q + 3] = e.w;
+          u1[q] = f.x; u1[q + 1] = f.y; u1[q + 2] = f.z; u1[q + 3] = f.w;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 2 * N; ++q) {
+          u0[q] = p0[q];
+          u1[q] = p1[q];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c)
+        pool[rl * PS + a * N + c] =
+            ((u0[2 * c] + u0[2 * c + 1]) + (u1[2 * c] + u1[2 * c + 1])) * 0.25f;
     }
   }
-  for (int t = 0; t < iters; ++t) {
-    grid.sync();  // iterate t is complete everywhere
-    const float *x = traj + (size_t)t * HW;
-    float *y = traj + (size_t)(t + 1) * HW;
+  if constexpr (!FIRST) __syncthreads();
+  {
+    const int i = threadIdx.x / RPW, rl = threadIdx.x % RPW;
+    const int r = r0 + rl;
+    if (r < g.R) {
+      const int k = iso[cb + r];
+      const float sv = s[cb + r], ov = o[cb + r];
+      const int ry = r / g.RW, rx = r - ry * g.RW;
+      const float u0 = ((x0 + x0) + (x0 + x0)) * 0.25f;
+      float out[N];
 #pragma unroll
-    for (int q = 0; q < PPT; ++q) {
-      if (src[q] < 0) continue;
-      const float *c = x + src[q];
-      const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
-      y[tid + q * nth] = fmaf(sv[q], u, ov[q]);
+      for (int j = 0; j < N; ++j) {
+        if constexpr (FIRST) {
+          out[j] = fmaf(sv, u0, ov);
+        } else {
+          int si, sj;
+          sigma(k, i, j, N - 1, si, sj);
+          out[j] = fmaf(sv, pool[rl * PS + si * N + sj], ov);
+        }
+      }
+      const size_t off = (size_t)(ry * N + i) * g.W + rx * N;
+      float *q = y + off;
+      float *q0 = (float *)x + off;  // FIRST: x_0 is written, never read
+      if constexpr (V == 4) {
+#pragma unroll
+        for (int j = 0; j < N; j += 4) {
+          *(float4 *)(q + j) = float4{out[j], out[j + 1], out[j + 2], out[j + 3]};
+          if constexpr (FIRST) *(float4 *)(q0 + j) = float4{x0, x0, x0, x0};
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          q[j] = out[j];
+          if constexpr (FIRST) q0[j] = x0;
+        }
+      }
     }
   }
 }
@@ -119,38 +157,11 @@ __global__ void k_decode_step_any(DecGeo d, const int32_t *domain,
   y[p] = fmaf(s[r], u, o[r]);
 }
 
-// Many images of one geometry, each with its own codes: one thread per
-// pixel of the whole batch.  Image b's codes start at entry b R; its
-// trajectory is traj[b][t][pixel] ((iters + 1) images of H W floats each).
-template <int N>
-__global__ __launch_bounds__(256) void k_decode_step_batch(
-    Geo g, long long total, const int32_t *domain, const uint8_t *iso,
-    const float *s, const float *o, float *traj, int t, int iters) {
-  const long long gp = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gp >= total) return;
-  const int HW = g.H * g.W;
-  const long long b = gp / HW;
-  const int p = (int)(gp - b * HW);
-  const int py = p / g.W, px = p % g.W;
-  const int ry = py / N, rx = px / N, i = py % N, j = px % N;
-  const long long r = b * g.R + ry * g.RW + rx;
-  const int d = clamp_dom(domain[r], g.ND);
-  int si, sj;
-  sigma(iso[r], i, j, N - 1, si, sj);
-  const int cy = (d / g.NX) * g.step + 2 * si, cx = (d % g.NX) * g.step + 2 * sj;
-  float *x = traj + (size_t)b * (iters + 1) * HW + (size_t)t * HW;
-  const float *c = x + (size_t)cy * g.W + cx;
-  const float u = ((c[0] + c[1]) + (c[g.W] + c[g.W + 1])) * 0.25f;
-  x[HW + p] = fmaf(s[r], u, o[r]);  // the image's iterate t + 1
-}
-
-// traj[b][0] = x0 for every image b.
-__global__ void k_fill_first_batch(float *traj, long long HW, int iters,
-                                   long long total, float v) {
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const long long b = i / HW;
-  traj[b * (iters + 1) * HW + (i - b * HW)] = v;
+// traj[b][0] = x0 for every image b: blockIdx.y is the image.
+__global__ void k_fill_first_batch(float *traj, int HW, long long stride,
+                                   float v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < HW) traj[(size_t)blockIdx.y * stride + i] = v;
 }
 
 __global__ void k_fill_f32(float *p, long long n, float v) {
@@ -159,9 +170,6 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 }
 
 // --- the domain -> ranges table --------------------------------------------
-
-// Decode in one cooperative launch when the image fits the resident grid.
-constexpr bool kDecodePersistent = true;
 
 constexpr int kSeg = 16;     // ranges per list segment
 constexpr int kGather = 32;  // segment partials loaded per round
@@ -424,60 +432,6 @@ __global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
   grad_x_body<N>(g, segoff, partial, gout, blockIdx.x);
 }
 
-// Device pointers of the adjoint table and per-step buffers.
-struct AdjDev {
-  const int32_t *nseg, *segoff, *list;
-  const int2 *seg;
-  float *partial, *gbuf0, *gbuf1;
-};
-
-// All reverse steps in one cooperative launch: each step's two parts are
-// the per-step kernels' bodies run over virtual workgroups, with a grid
-// synchronisation after the segment partials and after the gradient image,
-// so every sum keeps its order and the result equals the per-step launches.
-template <int N>
-__global__ __launch_bounds__(256) void k_adj_persist(
-    Geo g, const int32_t *domain, const uint8_t *iso, const float *s,
-    int iters, const float *traj, const float *grad_xT, float *grad_s,
-    float *grad_o, AdjDev a, int nb_so, int nb_sp, int nb_gx) {
-  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
-  const size_t HW = (size_t)g.H * g.W;
-  const float *gnext = grad_xT;
-  for (int t = iters - 1; t >= 0; --t) {
-    const float *x = traj + (size_t)t * HW;
-    for (int vb = blockIdx.x; vb < nb_so; vb += gridDim.x)
-      grad_so_body<N>(g, domain, iso, x, gnext, grad_s, grad_o,
-                      t == iters - 1 ? 1 : 0, vb);
-    if (t == 0) break;
-    for (int vb = blockIdx.x; vb < nb_sp; vb += gridDim.x)
-      seg_partial_body<N>(g, a.nseg, a.seg, a.list, iso, s, gnext, a.partial,
-                          vb);
-    grid.sync();  // the step's segment partials are complete
-    float *gout = (t & 1) ? a.gbuf1 : a.gbuf0;
-    for (int vb = blockIdx.x; vb < nb_gx; vb += gridDim.x)
-      grad_x_body<N>(g, a.segoff, a.partial, gout, vb);
-    grid.sync();  // g_t is complete
-    gnext = gout;
-  }
-}
-
-constexpr int kMaxDevices = 64;
-
-// Workgroups of 256 threads that can be resident at once for a kernel on
-// the current device (0 if unknown).
-template <typename Kern>
-int resident_groups(Kern kern) {
-  int dev = 0, per_cu = 0;
-  hipDeviceProp_t prop;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipGetDeviceProperties(&prop, dev) != hipSuccess ||
-      !prop.cooperativeLaunch ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 256, 0) !=
-          hipSuccess)
-    return 0;
-  return per_cu * prop.multiProcessorCount;
-}
-
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Workspace of the adjoint: the table (built once per code set) and the
@@ -550,56 +504,10 @@ void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
 
 // The reverse steps, with the table already built.
 template <int N>
-bool adjoint_persist(const Geo &g, const int32_t *domain, const uint8_t *iso,
-                     const float *s, int iters, const float *traj,
-                     const float *grad_xT, float *grad_s, float *grad_o,
-                     const AdjWs &a, hipStream_t st) {
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cap) != hipSuccess ||
-      cap != hipStreamCaptureStatusNone)
-    return false;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
-    return false;
-  static int groups_max[kMaxDevices];
-  static bool known[kMaxDevices];
-  if (!known[dev]) {
-    groups_max[dev] = resident_groups(k_adj_persist<N>);
-    known[dev] = true;
-  }
-  const long long HW = (long long)g.H * g.W;
-  int nb_so = (int)(((long long)g.R * N * N + 255) / 256);
-  int nb_sp = (int)(((long long)a.max_seg * N * N + 255) / 256);
-  int nb_gx = (int)((HW + 255) / 256);
-  int groups = std::max(nb_so, std::max(nb_sp, nb_gx));
-  groups = std::min(groups, groups_max[dev]);
-  if (groups < 1) return false;
-  AdjDev d;
-  d.nseg = a.segoff + g.ND;
-  d.segoff = a.segoff;
-  d.list = a.list;
-  d.seg = a.seg;
-  d.partial = a.partial;
-  d.gbuf0 = a.gbuf0;
-  d.gbuf1 = a.gbuf1;
-  Geo gg = g;
-  void *args[] = {&gg,         (void *)&domain, (void *)&iso,   (void *)&s,
-                  &iters,      (void *)&traj,   (void *)&grad_xT,
-                  (void *)&grad_s, (void *)&grad_o, &d, &nb_so, &nb_sp, &nb_gx};
-  return hipLaunchCooperativeKernel((const void *)k_adj_persist<N>,
-                                    dim3((unsigned)groups), dim3(256), args, 0,
-                                    st) == hipSuccess;
-}
-
-template <int N>
 void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
                    const float *s, int iters, const float *traj,
                    const float *grad_xT, float *grad_s, float *grad_o,
                    const AdjWs &a, hipStream_t st) {
-  if (kDecodePersistent && iters > 0 &&
-      adjoint_persist<N>(g, domain, iso, s, iters, traj, grad_xT, grad_s,
-                         grad_o, a, st))
-    return;
   const size_t HW = (size_t)g.H * g.W;
   const int bs = 256;
   const float *gnext = grad_xT;
@@ -710,52 +618,60 @@ DecGeo dec_geo(const Geo &g) {
   return d;
 }
 
-// One cooperative launch for the whole decode when the image fits the
-// resident grid at up to kPersistPixels pixels per thread; returns false
-// (nothing enqueued) when it does not or the device cannot launch it.
-constexpr int kPersistPixels = 4;
-
-template <int N, int PPT>
-bool decode_persist_try(const Geo &g, const int32_t *domain,
-                        const uint8_t *iso, const float *s, const float *o,
-                        int iters, float x0, float *traj, hipStream_t st,
-                        int groups_max) {
-  const long long HW = (long long)g.H * g.W;
-  const long long groups = (HW + 256LL * PPT - 1) / (256LL * PPT);
-  if (groups > groups_max) return false;
-  Geo gg = g;
-  void *args[] = {&gg,    (void *)&domain, (void *)&iso, (void *)&s,
-                  (void *)&o, &iters,      &x0,          &traj};
-  return hipLaunchCooperativeKernel((const void *)k_decode_persist<N, PPT>,
-                                    dim3((unsigned)groups), dim3(256), args, 0,
-                                    st) == hipSuccess;
+// One iteration of n_img images (iterates at xs, ys; image stride xstride
+// floats) with the pooled range kernel.
+template <int N, bool FIRST>
+void decode_pool_step(const Geo &g, int n_img, const int32_t *domain,
+                      const uint8_t *iso, const float *s, const float *o,
+                      const float *xs, float *ys, long long xstride, bool vec,
+                      float x0, hipStream_t st) {
+  constexpr int RPW = 256 / N;
+  const int wpi = (g.R + RPW - 1) / RPW;
+  const long long nwg = (long long)wpi * n_img;
+  const int xcd_map = n_img > 1 && nwg % 8 == 0 ? 1 : 0;
+  if (vec)
+    hipLaunchKernelGGL((k_decode_pool<N, 4, FIRST>), dim3((unsigned)nwg),
+                       dim3(256), 0, st, g, wpi, xcd_map, domain, iso, s, o, xs,
+                       ys, xstride, x0);
+  else
+    hipLaunchKernelGGL((k_decode_pool<N, 1, FIRST>), dim3((unsigned)nwg),
+                       dim3(256), 0, st, g, wpi, xcd_map, domain, iso, s, o, xs,
+                       ys, xstride, x0);
 }
 
-template <int N>
-bool decode_persist(const Geo &g, const int32_t *domain, const uint8_t *iso,
-                    const float *s, const float *o, int iters, float x0,
-                    float *traj, hipStream_t st) {
-  // a stream under capture takes the per-iteration launches instead
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(st, &cap) != hipSuccess ||
-      cap != hipStreamCaptureStatusNone)
-    return false;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
-    return false;
-  // resident workgroups per device and pixels-per-thread choice (computed
-  // once; concurrent first calls compute the same values)
-  static int groups_max[kMaxDevices][2];
-  static bool known[kMaxDevices];
-  if (!known[dev]) {
-    groups_max[dev][0] = resident_groups(k_decode_persist<N, 1>);
-    groups_max[dev][1] = resident_groups(k_decode_persist<N, kPersistPixels>);
-    known[dev] = true;
+// 16-byte loads and stores need image rows, domain corners and range rows
+// on 4-float boundaries, and a 16-byte aligned trajectory.
+bool decode_vec_ok(const Geo &g, const float *traj) {
+  return g.W % 4 == 0 && g.step % 4 == 0 && g.n % 4 == 0 &&
+         ((uintptr_t)traj & 15) == 0;
+}
+
+// All iterations, iters >= 1: the first writes x_0 and x_1.
+void decode_steps(const Geo &g, int n_img, const int32_t *domain,
+                  const uint8_t *iso, const float *s, const float *o,
+                  int iters, float x0, float *traj, long long img_stride,
+                  hipStream_t st) {
+  const long long HW = (long long)g.H * g.W;
+  const bool vec = decode_vec_ok(g, traj);
+  for (int t = 0; t < iters; ++t) {
+    float *x = traj + (size_t)t * HW;
+    float *y = traj + (size_t)(t + 1) * HW;
+    if (g.n == 8) {
+      if (t == 0)
+        decode_pool_step<8, true>(g, n_img, domain, iso, s, o, x, y,
+                                  img_stride, vec, x0, st);
+      else
+        decode_pool_step<8, false>(g, n_img, domain, iso, s, o, x, y,
+                                   img_stride, vec, x0, st);
+    } else {
+      if (t == 0)
+        decode_pool_step<4, true>(g, n_img, domain, iso, s, o, x, y,
+                                  img_stride, vec, x0, st);
+      else
+        decode_pool_step<4, false>(g, n_img, domain, iso, s, o, x, y,
+                                   img_stride, vec, x0, st);
+    }
   }
-  return decode_persist_try<N, 1>(g, domain, iso, s, o, iters, x0, traj, st,
-                                  groups_max[dev][0]) ||
-         decode_persist_try<N, kPersistPixels>(g, domain, iso, s, o, iters, x0,
-                                               traj, st, groups_max[dev][1]);
 }
 
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
@@ -764,24 +680,13 @@ hipError_t launch_decode(const Geo &g, const int32_t *domain,
   if (g.n != 4 && g.n != 8)  // other range sizes: the generic step
     return launch_decode_scaled(dec_geo(g), domain, iso, s, o, iters, x0, traj,
                                 st);
-  if (kDecodePersistent && iters > 0 &&
-      (g.n == 8 ? decode_persist<8>(g, domain, iso, s, o, iters, x0, traj, st)
-                : decode_persist<4>(g, domain, iso, s, o, iters, x0, traj, st)))
-    return hipGetLastError();
   const long long HW = (long long)g.H * g.W;
   const int bs = 256;
   const dim3 grid((unsigned)((HW + bs - 1) / bs));
-  hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
-  for (int t = 0; t < iters; ++t) {
-    const float *x = traj + (size_t)t * HW;
-    float *y = traj + (size_t)(t + 1) * HW;
-    if (g.n == 8)
-      hipLaunchKernelGGL(k_decode_step<8>, grid, dim3(bs), 0, st, g, domain,
-                         iso, s, o, x, y);
-    else
-      hipLaunchKernelGGL(k_decode_step<4>, grid, dim3(bs), 0, st, g, domain,
-                         iso, s, o, x, y);
-  }
+  if (iters == 0)
+    hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
+  else
+    decode_steps(g, 1, domain, iso, s, o, iters, x0, traj, 0, st);
   return hipGetLastError();
 }
 
@@ -790,19 +695,14 @@ hipError_t launch_decode_batch(const Geo &g, int n_images,
                                const float *s, const float *o, int iters,
                                float x0, float *traj, hipStream_t st) {
   const long long HW = (long long)g.H * g.W;
-  const long long total = HW * n_images;
+  const long long stride = HW * (iters + 1);  // floats per trajectory
   const int bs = 256;
-  const dim3 grid((unsigned)((total + bs - 1) / bs));
-  hipLaunchKernelGGL(k_fill_first_batch, grid, dim3(bs), 0, st, traj, HW,
-                     iters, total, x0);
-  for (int t = 0; t < iters; ++t) {
-    if (g.n == 8)
-      hipLaunchKernelGGL(k_decode_step_batch<8>, grid, dim3(bs), 0, st, g,
-                         total, domain, iso, s, o, traj, t, iters);
-    else
-      hipLaunchKernelGGL(k_decode_step_batch<4>, grid, dim3(bs), 0, st, g,
-                         total, domain, iso, s, o, traj, t, iters);
-  }
+  if (iters == 0)
+    hipLaunchKernelGGL(k_fill_first_batch,
+                       dim3((unsigned)((HW + bs - 1) / bs), (unsigned)n_images),
+                       dim3(bs), 0, st, traj, (int)HW, stride, x0);
+  else
+    decode_steps(g, n_images, domain, iso, s, o, iters, x0, traj, stride, st);
   return hipGetLastError();
 }
 

@@ -88,12 +88,31 @@ def test_decode_scaled_matches_oracle(num, den):
         assert np.array_equal(traj, base)
 
 
+@pytest.mark.parametrize("T", [1, 2, 5])
+@pytest.mark.parametrize("H,W,n,step", [(64, 64, 4, 4), (96, 64, 8, 4), (96, 64, 8, 2),
+                                        (40, 56, 4, 3), (36, 44, 4, 2)])
+def test_range_pooled_decode_equals_per_pixel_decode(H, W, n, step, T):
+    """fic_decode pools each range's domain cells once (16-byte accesses when
+    rows, domain corners and range rows sit on 4-float boundaries, single
+    floats otherwise); every iterate equals the generic per-pixel decode
+    (fic_decode_scaled at 1/1) bit for bit."""
+    img, d, k, s, o = codes_for(H, W, n, step, 33)
+    p = F.Params(H, W, 8, n, step)
+    args = (dev(d, torch.int32), dev(k, torch.uint8), dev(s, torch.float32),
+            dev(o, torch.float32))
+    a = F.decode(*args, p, T, 128.0)
+    b = F.decode_scaled(*args, p, (1, 1), T, 128.0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("B", [3, 8])
 @pytest.mark.parametrize("H,W,n,step", [(64, 64, 4, 4), (96, 64, 8, 2)])
-def test_decode_batch_matches_single_decodes_and_oracle(H, W, n, step):
-    """Three images of one geometry with their own codes in one batched
-    decode: each trajectory equals fic_decode's bit for bit and the FP64
-    oracle's within 1e-3."""
-    T, B = 12, 3
+def test_decode_batch_matches_single_decodes_and_oracle(H, W, n, step, B):
+    """B images of one geometry with their own codes in one batched decode
+    (B = 8 takes the XCD-grouped workgroup order): each trajectory equals
+    fic_decode's bit for bit and the FP64 oracle's within 1e-3."""
+    T = 12
     cs = [codes_for(H, W, n, step, 50 + b) for b in range(B)]
     p = F.Params(H, W, 8, n, step)
     stack = lambda i, dt: dev(np.stack([c[i] for c in cs]), dt)
