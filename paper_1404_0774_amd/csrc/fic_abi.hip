@@ -158,6 +158,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.pix_a = 0;
   g.full = p->full_search;
   g.i8 = p->method == FIC_METHOD_MFMA_I8 && g.bits == 12;
+  g.ctr = p->method == FIC_METHOD_MFMA && g.bits == 8 && n != 16;
   return FIC_OK;
 }
 

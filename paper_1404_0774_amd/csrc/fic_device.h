@@ -39,6 +39,27 @@ __host__ __device__ inline void sigma_inv(int k, int ci, int cj, int m, int &i,
   }
 }
 
+// Rounded mean of a non-negative block sum: the integer nearest sum / K
+// (halves up).  8-bit matrix-core operands are centred on it.
+__host__ __device__ inline int centre_of(long long sum, int K) {
+  return (int)((sum + K / 2) / K);
+}
+
+// The same rounded mean of a sum below 2^24 held in FP32, with invK = 1/K:
+// the scaling, the added half and the floor are all exact.
+__device__ __forceinline__ float centre_f(float sum, float invK) {
+  return floorf(fmaf(sum, invK, 0.5f));
+}
+
+// Exact G = sum A b of a candidate from the product h of its centred
+// operands (A - m_d and b - m_r, m_d and m_r the rounded means of SA and Sb):
+// G = h + m_r SA + m_d Sb - K m_d m_r, every term an integer held exactly.
+__device__ __forceinline__ double g_from_centred(double h, double sa,
+                                                 double sb, const Geo &g) {
+  const double md = floor(fma(sa, g.invK, 0.5)), mr = floor(fma(sb, g.invK, 0.5));
+  return h + mr * sa + md * sb - (double)g.K * md * mr;
+}
+
 // Result of the exact fit of one candidate.
 struct Fit {
   double err;  // eq. (8) with quantised s, o

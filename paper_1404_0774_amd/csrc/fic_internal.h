@@ -33,6 +33,9 @@ struct Geo {
                      //   too (0: they are left out; their outcome is fixed)
   int i8;            // 1: 12-bit operands also as int8 hi/lo planes (the
                      //   int8 matrix-core search)
+  int ctr;           // 1: 8-bit matrix-core operands (4x4, 8x8 ranges) are
+                     //   centred on each block's rounded mean:
+                     //   A - round(SA/K) and b - round(Sb/K), exact FP16
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step
@@ -44,10 +47,11 @@ struct Geo {
 
 // Device buffers carved out of the caller's workspace.
 // One column's statistics in a single 16-byte record (8-bit search): SA,
-// the prune denominator D' (as in col_sadp), the domain index and the sum of
-// squared cell sums, exact in 32 bits for 8-bit images (<= 64 * 1020^2).
+// sqrt(D') rounded down (+inf for flat domains and padding), the domain
+// index and the sum of squared cell sums, exact in 32 bits for 8-bit images
+// (<= 64 * 1020^2).
 struct __attribute__((aligned(16))) ColRec {
-  float sa, dp;
+  float sa, sc;
   int dom;
   unsigned saa;
 };

@@ -37,8 +37,12 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   long long SA = 0, SAA = 0;
   int d = -1;
   halfN vh, vl;
+  int Av[N];
 #pragma unroll
-  for (int j = 0; j < N; ++j) vh[j] = vl[j] = (_Float16)0.0f;
+  for (int j = 0; j < N; ++j) {
+    vh[j] = vl[j] = (_Float16)0.0f;
+    Av[j] = 0;
+  }
   if (live && e < g.ND) {
     d = (int)e;
     // 32-bit arithmetic whenever d * stride_inv < ND^2 fits
@@ -55,6 +59,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       const int A = p0[2 * j] + p0[2 * j + 1] + p1[2 * j] + p1[2 * j + 1];
+      Av[j] = A;
       SA += A;
       SAA += (long long)A * A;
       if (g.bits == 12) {
@@ -66,6 +71,15 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
         vh[j] = (_Float16)(float)A;
       }
     }
+  }
+  // the column's statistics over its N adjacent threads
+  SA = group_sum<N>(SA);
+  SAA = group_sum<N>(SAA);
+  if (g.ctr && N != 16) {
+    // centred on the rounded mean: |A - m| <= 1020, exact in FP16
+    const int m = d >= 0 ? centre_of(SA, K) : 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) vh[j] = (_Float16)(float)(Av[j] - m);
   }
   if (live) {
     *(halfN *)(b.bop + (size_t)col * K + i * N) = vh;
@@ -82,9 +96,6 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
       }
     }
   }
-  // the column's statistics over its N adjacent threads
-  SA = group_sum<N>(SA);
-  SAA = group_sum<N>(SAA);
   if (live && i == 0) {
     b.col_dom[col] = d;
     b.col_saa[col] = (double)SAA;
@@ -99,7 +110,10 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     b.col_sadp[col] = float2{(float)SA, dp};
     ColRec rec;
     rec.sa = (float)SA;
-    rec.dp = dp;
+    rec.sc = dp == __builtin_inff()
+                 ? dp
+                 : round_down_f(sqrt((double)K * (double)SAA -
+                                     (double)SA * (double)SA));
     rec.dom = d;
     rec.saa = g.bits == 8 ? (unsigned)SAA : 0u;
     b.col_rec[col] = rec;
@@ -160,7 +174,22 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
   Acc Sb = 0, Sbb = 0, G0 = 0, SA0 = 0, SAA0 = 0;
 #pragma unroll
   for (int e = 0; e < P; ++e) {
-    if (!g.pix_a) {
+    Sb += v[e];
+    Sbb += (Acc)v[e] * v[e];
+    G0 += (Acc)A0[e] * v[e];
+    SA0 += A0[e];
+    SAA0 += (Acc)A0[e] * A0[e];
+  }
+  Sb = group_sum<L>(Sb);
+  Sbb = group_sum<L>(Sbb);
+  G0 = group_sum<L>(G0);
+  SA0 = group_sum<L>(SA0);
+  SAA0 = group_sum<L>(SAA0);
+  if (!g.pix_a) {
+    // 8-bit matrix-core operands are centred on the range's rounded mean
+    const int mr = g.ctr ? centre_of((long long)Sb, K) : 0;
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
 #pragma unroll
       for (int k = 0; k < 8; ++k) {
         int si, sj;
@@ -177,21 +206,11 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
         } else if (N == 16) {
           row_hi[k * K + pp] = (_Float16)(float)(v[e] - 128);  // centred
         } else {
-          row_hi[k * K + pp] = (_Float16)(float)v[e];
+          row_hi[k * K + pp] = (_Float16)(float)(v[e] - mr);
         }
       }
     }
-    Sb += v[e];
-    Sbb += (Acc)v[e] * v[e];
-    G0 += (Acc)A0[e] * v[e];
-    SA0 += A0[e];
-    SAA0 += (Acc)A0[e] * A0[e];
   }
-  Sb = group_sum<L>(Sb);
-  Sbb = group_sum<L>(Sbb);
-  G0 = group_sum<L>(G0);
-  SA0 = group_sum<L>(SA0);
-  SAA0 = group_sum<L>(SAA0);
   if (q0 != 0) return;
   b.rng_sb[r] = (double)Sb;
   b.rng_sbb[r] = (double)Sbb;

@@ -7,17 +7,30 @@
 // eight transforms on the range side (row 8 r + k of the range operand holds
 // b_r scattered by sigma_k), all G form one product
 //       G[(r, k), d] = sum_p Rop[(r, k), p] * Bop[d, p]
-// of an (8 R) x K by K x ND pair of integer matrices.  Pixels (<= 255) and
-// 2x2 cell sums (<= 1020) are exact in FP16 and every partial sum stays below
-// 2^24, so v_mfma_f32_32x32x16_f16 with FP32 accumulation produces G exactly.
+// of an (8 R) x K by K x ND pair of integer matrices.
+//
+// Both operands are centred on their block's rounded mean: the domain
+// operand holds A - m_d (m_d = round(SA/K), |A - m_d| <= 1020) and the range
+// operand b - m_r (m_r = round(Sb/K), |b - m_r| <= 255), integers exact in
+// FP16.  With the centred sums bounded by Cauchy-Schwarz (norms <= 510.1
+// sqrt(K) and 127.6 sqrt(K)), every partial sum of
+//       H = sum_q (A[sigma_k(q)] - m_d)(b[q] - m_r)
+// stays below 2^22 in magnitude, so v_mfma_f32_32x32x16_f16 with FP32
+// accumulation produces H exactly, and
+//       G = H + m_r SA + m_d Sb - K m_d m_r            (exact in FP64),
+//       G - SA Sb / K = H - K delta_d delta_r,
+// with delta_d = SA/K - m_d and delta_r = Sb/K - m_r in [-1/2, 1/2], so the
+// least-squares quantity of the prune differs from H by at most K/4.
 //
 // The output is never stored.  Each 32x32 MFMA tile holds, per lane, one
 // domain column and the 8 transforms of two ranges (the row order of the
 // range operand is chosen for that), and the epilogue prunes with an
 // exact-safe least-squares bound shared by the 8 transforms: a candidate can
 // only tie or beat the range's best residual if
-//       (G - SA Sb / K)^2 >= W' D'.
-// Pairs that pass are appended, with their 8 G values and the column's
+//       |G - SA Sb / K| >= sqrt(W' D'),
+// so a (range, domain) pair can be skipped when max_k |H_k| + K/4 is below
+// that threshold: one max-of-absolute-values and one fused compare per pair.
+// Pairs that pass are appended, with their 8 H values and the column's
 // statistics, to a per-wave LDS queue; 64 at a time they are re-tested per
 // transform, the surviving transforms are compacted into a list and fitted
 // exactly in FP64, one per lane.
@@ -42,34 +55,36 @@ constexpr int kWaveRanges = 4 * kRB;
 constexpr int kSync = 4;            // column blocks between global syncs
 constexpr int kQueue = 128;         // pairs; >= 63 + 64 lanes
 
-// A queued (range, domain) pair: the 8 transforms' G, the column's
-// statistics and dl = domain << 4 | wave-local range index.
+// A queued (range, domain) pair: the 8 transforms' centred products H, the
+// column's statistics and dl = domain << 4 | wave-local range index.
 struct __attribute__((aligned(16))) QEntry {
   float4 g0, g1;
-  float sa, dp;
+  float sa, sc;
   unsigned saa;
   int dl;
 };
 
-// A surviving transform of a queued pair: G, and pair index << 3 | k.
+// A surviving transform of a queued pair: H, and pair index << 3 | k.
 struct Cand {
   float g;
   unsigned pk;
 };
 
-// The least-squares test shared by the 8 transforms of one (range, domain)
-// pair: max_k |G_k - SA Sb/K| >= sqrt(W' D').
-__device__ __forceinline__ bool pair_passes(float gmx, float gmn, float csa,
-                                            float bbar, float wp, float cdp) {
-  const float a0 = fmaf(-csa, bbar, gmx);
-  const float a1 = fmaf(-csa, bbar, gmn);
-  const float mm = fmaxf(fabsf(a0), fabsf(a1));
-  return mm * mm >= wp * cdp;
+// max_k |H_k| over the 8 transforms of a pair (exact integers in FP32).
+__device__ __forceinline__ float abs_max8(const f32x16 &a, int e) {
+  // starting from 0 (a canonical value) lets every step fold into v_max3
+  float m = 0.0f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m = fmaxf(m, fabsf(a[8 * e + k]));
+  return m;
 }
 
-// Recompute the prune weights: lane l < 16 computes the weight of wave
+// Recompute the prune thresholds: lane l < 16 computes sqrt(W') of wave
 // range l once and stores it at wtab[h][s] (range 4 (s / 2) + 2 h + s mod 2,
-// the layout of a lane's 8 slots); the sweep reads its 8 from LDS.
+// the layout of a lane's 8 slots); the sweep reads its 8 from LDS.  W' is
+// rounded down by 2^-20 (weight_from_key); the hardware square root (within
+// 1 ulp) is scaled down by 2^-22, so the threshold stays below the exact
+// root with room for the FP32 rounding of the test.
 __device__ __forceinline__ void refresh_weights(const unsigned long long *best,
                                                 const double2 *rstat,
                                                 float *wtab, int lane,
@@ -78,7 +93,8 @@ __device__ __forceinline__ void refresh_weights(const unsigned long long *best,
     const double2 rs = rstat[lane];
     const float wv =
         weight_from_key(best[lane], (double)g.K * rs.y - rs.x * rs.x, g);
-    wtab[((lane >> 1) & 1) * kSlots + 2 * (lane >> 2) + (lane & 1)] = wv;
+    const float sw = __builtin_amdgcn_sqrtf(wv) * (1.0f - 0x1p-22f);
+    wtab[((lane >> 1) & 1) * kSlots + 2 * (lane >> 2) + (lane & 1)] = sw;
   }
   __builtin_amdgcn_wave_barrier();
 }
@@ -113,14 +129,20 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
         const float4 g0 = q.g0, g1 = q.g1;
         gv[0] = g0.x; gv[1] = g0.y; gv[2] = g0.z; gv[3] = g0.w;
         gv[4] = g1.x; gv[5] = g1.y; gv[6] = g1.z; gv[7] = g1.w;
-        const float sa = q.sa, dp = q.dp;
+        const float sa = q.sa, sc = q.sc;
         const int lr = q.dl & 15;
         const double2 rs = rstat[lr];
-        const float bbar = (float)(rs.x * g.invK);
-        const float t = weight_from_key(best[lr], K * rs.y - rs.x * rs.x, g) * dp;
+        // G - SA Sb/K = H - c with c = (SA - K m_d)(Sb - K m_r)/K, exact
+        const float kf = (float)g.K, ik = (float)g.invK;
+        const float sbf = (float)rs.x;
+        const float dd = fmaf(-kf, centre_f(sa, ik), sa);
+        const float dr = fmaf(-kf, centre_f(sbf, ik), sbf);
+        const float c = dd * dr * ik;
+        const float t =
+            weight_from_key(best[lr], K * rs.y - rs.x * rs.x, g) * sc * sc;
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-          const float a = fmaf(-sa, bbar, gv[k]);
+          const float a = gv[k] - c;
           pass |= (a * a >= t) ? (1u << k) : 0u;
         }
       }
@@ -142,8 +164,8 @@ __device__ __forceinline__ void drain(QEntry *queue, Cand *cands, int &qn,
       const QEntry &q = queue[cd.pk >> 3];
       const int lr = q.dl & 15;
       const double2 rs = rstat[lr];
-      const Fit f =
-          fit_exact((double)cd.g, (double)q.sa, (double)q.saa, rs.x, rs.y, g);
+      const Fit f = fit_exact(g_from_centred((double)cd.g, (double)q.sa, rs.x, g),
+                              (double)q.sa, (double)q.saa, rs.x, rs.y, g);
       atomicMin(&best[lr], make_key(f.err, 8ll * (q.dl >> 4) + (cd.pk & 7), g));
     }
     __builtin_amdgcn_wave_barrier();
@@ -174,7 +196,6 @@ struct WaveState {
   QEntry *queue;             // LDS: queued pairs
   Cand *cands;               // LDS: drain candidates
   float *wtab;               // LDS: prune weights [2][kSlots]
-  float *btab;               // LDS: range means Sb / K [2][kSlots]
   int *slots;                // LDS: range slot of each wave range (-1: none)
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
@@ -194,7 +215,7 @@ __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
   for (int kk = 0; kk < K / 16; ++kk) bn[kk] = gld((const half8 *)(bsrc + 16 * kk));
   // as one 16-byte vector: a struct copy would go through a generic reference
   nsd = __builtin_bit_cast(ColRec, gld((const u32x4 *)&b.col_rec[c]));
-  if (ci < 0) nsd.dp = __builtin_inff();
+  if (ci < 0) nsd.sc = __builtin_inff();
 }
 
 // Column of searched block cb for lane column cl (-1 past the list).
@@ -213,10 +234,9 @@ __device__ __forceinline__ void sweep_block(
     const half8 (&bf)[K / 16], const ColRec &sd, half8 (&bn)[K / 16],
     ColRec &nsd, int cb, int c0, int c1) {
   constexpr int KS = K / 16;
-  // the lane's 8 prune weights and range means, kept in LDS between blocks
-  float wp[kSlots], bbar[kSlots];
-  read_slots(w.wtab, w.h, wp);
-  read_slots(w.btab, w.h, bbar);
+  // the lane's 8 prune thresholds sqrt(W'), kept in LDS between blocks
+  float sw[kSlots];
+  read_slots(w.wtab, w.h, sw);
   const int slot = (cb - c0) % kSync;
   {
     // the next block (its column index came a block earlier) and the index
@@ -236,34 +256,25 @@ __device__ __forceinline__ void sweep_block(
       acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
                                                        acc[rb], 0, 0, 0);
   }
-  const float csa = sd.sa, cdp = sd.dp;
+  const float csa = sd.sa, csc = sd.sc;
 
-  // Per (range, domain) pair: the 8 transforms' G are non-negative integers
-  // in FP32, so their bit patterns order like unsigned integers and max/min
-  // need no float canonicalisation.
-  float gmx[kSlots], gmn[kSlots];
+  // Per (range, domain) pair: max_k |H_k| + K/4 bounds |G_k - SA Sb/K| for
+  // all 8 transforms, so the pair can only matter if max_k |H_k| >=
+  // sqrt(W') sqrt(D') - K/4 (both roots rounded down; +inf for a flat
+  // domain or range, and 0 * inf = NaN for a flat domain against a useless
+  // bound: the compare fails both times).  Wave masks of the passing pairs,
+  // one per slot, in scalar registers.
+  constexpr float kq = 0.25f * K;
+  unsigned long long pm[kSlots], anym = 0;
 #pragma unroll
   for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      unsigned ux = __float_as_uint(acc[rb][8 * e]), un = ux;
-#pragma unroll
-      for (int k = 1; k < 8; ++k) {
-        const unsigned u = __float_as_uint(acc[rb][8 * e + k]);
-        ux = max(ux, u);
-        un = min(un, u);
-      }
-      gmx[2 * rb + e] = __uint_as_float(ux);
-      gmn[2 * rb + e] = __uint_as_float(un);
+      const int s = 2 * rb + e;
+      pm[s] = __builtin_amdgcn_ballot_w64(abs_max8(acc[rb], e) >=
+                                          fmaf(sw[s], csc, -kq));
+      anym |= pm[s];
     }
-  // wave masks of the passing pairs, one per slot (scalar registers)
-  unsigned long long pm[kSlots], anym = 0;
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    pm[s] = __builtin_amdgcn_ballot_w64(
-        pair_passes(gmx[s], gmn[s], csa, bbar[s], wp[s], cdp));
-    anym |= pm[s];
-  }
 
   if (anym != 0) {
     // append every passing pair, with its 8 G values, to the wave's queue
@@ -287,7 +298,7 @@ __device__ __forceinline__ void sweep_block(
           q->g1 = float4{acc[rb][8 * e + 4], acc[rb][8 * e + 5],
                          acc[rb][8 * e + 6], acc[rb][8 * e + 7]};
           *(uint4 *)&q->sa =
-              uint4{__float_as_uint(csa), __float_as_uint(cdp), sd.saa,
+              uint4{__float_as_uint(csa), __float_as_uint(csc), sd.saa,
                     (unsigned)(cdl | (4 * rb + 2 * w.h + e))};
         }
         w.qn += __popcll(m);
@@ -323,27 +334,28 @@ __device__ __forceinline__ void sweep_block(
 
 // Starting bound from the workgroup's first nb column blocks (nb <=
 // kSeedBlocks).  Each lane ranks the 8 transforms of each of its ranges
-// against its column of every block by the least-squares score
-// (G - SA Sb/K)^2 / D' and keeps the best; the bests are posted through LDS
-// (the empty candidate and queue buffers) and lane l < 16 picks range l's
-// best and fits that one candidate exactly.  Any candidate's exact residual
-// is a valid bound; the sweep then covers these blocks as usual.
+// against its column of every block by the least-squares score H^2 / D'
+// (H the centred product, which differs from G - SA Sb/K by at most K/4) and
+// keeps the best; the bests are posted through LDS (the empty candidate and
+// queue buffers) and lane l < 16 picks range l's best and fits that one
+// candidate exactly.  Any candidate's exact residual is a valid bound; the
+// sweep then covers these blocks as usual.
 constexpr int kSeedBlocks = 1;
+constexpr int kHBias = 1 << 22;  // |H| < 2^22: H + 2^22 fits 23 bits
 
 template <int K>
 __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
                                             WaveState &w,
                                             const half8 (&af)[kRB][K / 16],
-                                            const float (&bbar)[kSlots],
                                             const half8 (&b0)[K / 16],
                                             const ColRec &sd0, int c0,
                                             int nb) {
   constexpr int KS = K / 16;
-  // per (half, slot, column): score, and block << 27 | G << 3 | transform
+  // per (half, slot, column): score, and block << 27 | (H + 2^22) << 3 | k
   float *sc_tab = (float *)w.cands;
   unsigned *gk_tab = (unsigned *)w.cands + 2 * kSlots * 32;
   ColRec *col_tab = (ColRec *)w.queue;  // [kSeedBlocks][32]
-  // per slot: best score (0: none), its G and block * 8 + transform
+  // per slot: best score (0: none), its H and block * 8 + transform
   float best[kSlots], bestg[kSlots];
   unsigned bestk[kSlots];
 #pragma unroll
@@ -370,20 +382,19 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
     if (blk + 1 < nb)
       load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, bf, sd);
-    // flat domains and padding columns (D' = +inf) score 0 and take no
-    // part (as does a candidate with G exactly at the mean)
-    const float idp = cur.dp != __builtin_inff() ? 1.0f / cur.dp : 0.0f;
+    // flat domains and padding columns (sqrt(D') = +inf) score 0 and take no
+    // part (as does a candidate with H = 0)
+    const float idp =
+        cur.sc != __builtin_inff() ? 1.0f / (cur.sc * cur.sc) : 0.0f;
 #pragma unroll
     for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int s = 2 * rb + e;
-        const float c = cur.sa * bbar[s];
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
           const float gv = acc[rb][8 * e + k];
-          const float d = gv - c;
-          const float v = d * d * idp;
+          const float v = gv * gv * idp;
           const bool up = v > best[s];
           best[s] = up ? v : best[s];
           bestg[s] = up ? gv : bestg[s];
@@ -395,7 +406,8 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
   for (int s = 0; s < kSlots; ++s) {
     sc_tab[(w.h * kSlots + s) * 32 + w.cl] = best[s];
     gk_tab[(w.h * kSlots + s) * 32 + w.cl] =
-        ((bestk[s] >> 3) << 27) | ((unsigned)bestg[s] << 3) | (bestk[s] & 7);
+        ((bestk[s] >> 3) << 27) | ((unsigned)((int)bestg[s] + kHBias) << 3) |
+        (bestk[s] & 7);
   }
   __builtin_amdgcn_wave_barrier();
   if (w.lane < kWaveRanges) {
@@ -415,8 +427,9 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
       const unsigned t = gk_tab[(h * kSlots + s) * 32 + bc];
       const ColRec cr = col_tab[(t >> 27) * 32 + bc];
       const double2 rs = w.rstat[lr];
-      const Fit f = fit_exact((double)((t >> 3) & 0xFFFFFFu), (double)cr.sa,
-                              (double)cr.saa, rs.x, rs.y, g);
+      const float hv = (float)((int)((t >> 3) & 0xFFFFFFu) - kHBias);
+      const Fit f = fit_exact(g_from_centred((double)hv, (double)cr.sa, rs.x, g),
+                              (double)cr.sa, (double)cr.saa, rs.x, rs.y, g);
       const unsigned long long key =
           make_key(f.err, 8ll * cr.dom + (t & 7), g);
       if (key < w.best[lr]) w.best[lr] = key;
@@ -446,7 +459,6 @@ struct SearchLds {
   QEntry queue[4][kQueue];
   Cand cands[4][8 * 64];
   float wtab[4][2 * kSlots];
-  float btab[4][2 * kSlots];
   int slots[4][kWaveRanges];
 };
 
@@ -455,7 +467,8 @@ struct SearchLds {
 // pixels in LDS (the empty queue), once row by row and once transposed, so
 // that every transform of a fragment row is one 8-byte read of a range row or
 // column, forward or reversed (sigma_k^-1 of the row, Section V).  Bytes
-// become FP16 exactly: 0x64xx is 1024 + xx, and 1024 is then subtracted.
+// become FP16 exactly: 0x64xx is 1024 + xx, and 1024 + m_r is then
+// subtracted (an exact difference of two FP16 integers in [1024, 2047]).
 __device__ __forceinline__ void range_fragments_from_pixels(
     const Geo &g, const uint8_t *img, WaveState &w, half8 (&af)[kRB][4]) {
   uint2 *rows = (uint2 *)w.queue;  // [16 ranges][8 rows], 8 pixels each
@@ -496,9 +509,12 @@ __device__ __forceinline__ void range_fragments_from_pixels(
   const unsigned c64 = 0x64646464u;
   const unsigned s0 = rev ? 0x04020403u : 0x04010400u;
   const unsigned s1 = rev ? 0x04000401u : 0x04030402u;
-  const half8 k1024 = half8{1024, 1024, 1024, 1024, 1024, 1024, 1024, 1024};
 #pragma unroll
-  for (int rb = 0; rb < kRB; ++rb)
+  for (int rb = 0; rb < kRB; ++rb) {
+    // the range's rounded mean m_r is subtracted together with the 1024
+    const _Float16 off = (_Float16)(
+        1024.0f + centre_f((float)w.rstat[4 * rb + rl].x, 1.0f / 64.0f));
+    const half8 koff = half8{off, off, off, off, off, off, off, off};
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int pi = 2 * kk + w.h;
@@ -508,8 +524,9 @@ __device__ __forceinline__ void range_fragments_from_pixels(
                             __builtin_amdgcn_perm(c64, lo, s1),
                             __builtin_amdgcn_perm(c64, hi, s0),
                             __builtin_amdgcn_perm(c64, hi, s1)};
-      af[rb][kk] = __builtin_bit_cast(half8, u) - k1024;
+      af[rb][kk] = __builtin_bit_cast(half8, u) - koff;
     }
+  }
   __builtin_amdgcn_wave_barrier();
 }
 
@@ -534,7 +551,6 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.queue = lds.queue[wave];
   w.cands = lds.cands[wave];
   w.wtab = lds.wtab[wave];
-  w.btab = lds.btab[wave];
   w.slots = lds.slots[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
@@ -580,17 +596,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
         af[rb][kk] = sl >= 0 ? gld((const half8 *)(src + 16 * kk)) : half8{};
     }
   }
-  // per lane: wave ranges 4 rb + 2 h + e for slot s = 2 rb + e; the range
-  // means go to LDS in the weights' layout
-  if (w.lane < kWaveRanges)
-    w.btab[((w.lane >> 1) & 1) * kSlots + 2 * (w.lane >> 2) + (w.lane & 1)] =
-        (float)(w.rstat[w.lane].x * g.invK);
-  __builtin_amdgcn_wave_barrier();
-  {
-    float bbar[kSlots];
-    read_slots(w.btab, w.h, bbar);
-    seed_blocks<K>(g, b, w, af, bbar, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
-  }
+  seed_blocks<K>(g, b, w, af, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
   refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, bA, sdA, bB, sdB, cb, c0, c1);

@@ -37,7 +37,7 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   constexpr int PER = K / 8;                      // 16-byte words per row
   __shared__ __attribute__((aligned(16))) half2_t sA[NP][KP][64];
   __shared__ __attribute__((aligned(16))) half2_t sB[NP][KP][32];
-  __shared__ float s_sa[32], s_idp[32];
+  __shared__ float s_sa[32], s_idp[32], s_dd[32];
   const int t = threadIdx.x;
   const int row = t >> 2, cgp = t & 3;
   const int rl = row >> 3, k = row & 7;
@@ -45,6 +45,8 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
 
   const double Sb = b.rng_sb[r], Sbb = b.rng_sbb[r];
   const float sbf = (float)Sb;
+  // centred 8-bit operands (g.ctr): N' = K H - (SA - K m_d)(Sb - K m_r)
+  const float dr = fmaf(-(float)K, centre_f(sbf, 1.0f / K), sbf);
   // the workgroup's 64 rows (8 ranges x 8 transforms) of the range operand
   for (int i = t; nblocks > 0 && i < NP * 64 * PER; i += 256) {
     const int pl = i / (64 * PER), ii = i % (64 * PER);
@@ -77,6 +79,7 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     if (t < 32) {
       const float2 sadp = b.col_sadp[cb * 32 + t];
       s_sa[t] = sadp.x;
+      s_dd[t] = fmaf(-(float)K, centre_f(sadp.x, 1.0f / K), sadp.x);
       // flat domains are seeded separately; padding columns are not domains
       s_idp[t] = sadp.y == __builtin_inff() ? -1.0f : 1.0f / sadp.y;
     }
@@ -121,7 +124,8 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
                                        fmaf(64.0f, acc[0][NP - 1][c],
                                             acc[NP - 1][NP - 1][c])))
                            : acc[0][0][c];
-      const float np = fmaf((float)g.K, gf, -s_sa[cc] * sbf);
+      const float np = (!B12 && g.ctr) ? fmaf((float)g.K, gf, -s_dd[cc] * dr)
+                                        : fmaf((float)g.K, gf, -s_sa[cc] * sbf);
       const float score = idp < 0.0f ? -1.0f : np * np * idp;
       if (score > bscore) {
         bscore = score;
@@ -144,9 +148,11 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
   if ((t & 31) != __builtin_ctz(grp)) return;
   unsigned long long key = ~0ull;
   if (bcol >= 0) {
-    const double G = B12 ? 8192.0 * bg[0] + 128.0 * bg[2] + 64.0 * bg[1] +
-                               (double)bg[3]
-                         : (double)bg[0];
+    const double G =
+        B12 ? 8192.0 * bg[0] + 128.0 * bg[2] + 64.0 * bg[1] + (double)bg[3]
+            : (g.ctr ? g_from_centred((double)bg[0], (double)b.col_sadp[bcol].x,
+                                      Sb, g)
+                     : (double)bg[0]);
     const Fit f = fit_exact(G, (double)b.col_sadp[bcol].x, b.col_saa[bcol],
                             Sb, Sbb, g);
     const unsigned long long k2 = make_key(f.err, 8ll * b.col_dom[bcol] + k, g);
