@@ -60,6 +60,19 @@ __device__ __forceinline__ double g_from_centred(double h, double sa,
   return h + mr * sa + md * sb - (double)g.K * md * mr;
 }
 
+// Position of k-element p of sweep column c in the domain operand.  A full
+// 8-bit matrix-core search (its column list is the identity) stores the
+// operand in MFMA fragment order: block c / 32, k-step p / 16, lane
+// (p / 8 mod 2) 32 + c mod 32, element p mod 8, so that the 64 lanes of a
+// wave read one contiguous run per k-step.  Otherwise each column holds its
+// K elements in order.
+__host__ __device__ inline size_t bop_index(const Geo &g, long long c, int p) {
+  if (g.ctr && g.full)
+    return (size_t)(c >> 5) * 32 * g.K + (size_t)(p >> 4) * 512 +
+           (size_t)((((p >> 3) & 1) << 5) | (int)(c & 31)) * 8 + (p & 7);
+  return (size_t)c * g.K + p;
+}
+
 // Result of the exact fit of one candidate.
 struct Fit {
   double err;  // eq. (8) with quantised s, o

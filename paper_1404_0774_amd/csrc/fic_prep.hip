@@ -82,7 +82,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     for (int j = 0; j < N; ++j) vh[j] = (_Float16)(float)(Av[j] - m);
   }
   if (live) {
-    *(halfN *)(b.bop + (size_t)col * K + i * N) = vh;
+    *(halfN *)(b.bop + bop_index(g, col, i * N)) = vh;
     if (g.bits == 12)
       *(halfN *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + i * N) = vl;
     if (g.i8) {

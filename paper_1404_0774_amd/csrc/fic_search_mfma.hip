@@ -199,6 +199,7 @@ struct WaveState {
   int *slots;                // LDS: range slot of each wave range (-1: none)
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
+  bool frag;                 // domain operand in fragment order
   int qn;                    // queued pairs (wave-uniform)
   unsigned long long gsnap;  // global keys as last read (lanes < 16)
   int wr0, h, cl, lane;
@@ -206,13 +207,20 @@ struct WaveState {
 
 // Column ci of the domain operand and its record; ci < 0 (past the searched
 // columns) reads column 0 and marks it flat, so it never passes the prune.
+// frag: the operand is in fragment order (a full search), where lane
+// (h, c mod 32) of k-step kk reads 16 bytes at block offset kk 1024 + 16 lane.
 template <int K>
 __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
-                                            half8 (&bn)[K / 16], ColRec &nsd) {
+                                            bool frag, half8 (&bn)[K / 16],
+                                            ColRec &nsd) {
   const int c = ci >= 0 ? ci : 0;
-  const _Float16 *bsrc = b.bop + (size_t)c * K + 8 * h;
+  const _Float16 *bsrc =
+      frag ? b.bop + (size_t)(c >> 5) * 32 * K + ((h << 5) | (c & 31)) * 8
+           : b.bop + (size_t)c * K + 8 * h;
+  const int kstep = frag ? 512 : 16;
 #pragma unroll
-  for (int kk = 0; kk < K / 16; ++kk) bn[kk] = gld((const half8 *)(bsrc + 16 * kk));
+  for (int kk = 0; kk < K / 16; ++kk)
+    bn[kk] = gld((const half8 *)(bsrc + kstep * kk));
   // as one 16-byte vector: a struct copy would go through a generic reference
   nsd = __builtin_bit_cast(ColRec, gld((const u32x4 *)&b.col_rec[c]));
   if (ci < 0) nsd.sc = __builtin_inff();
@@ -241,21 +249,23 @@ __device__ __forceinline__ void sweep_block(
   {
     // the next block (its column index came a block earlier) and the index
     // of the block after it
-    load_column<K>(b, w.ci_next, w.h, bn, nsd);
+    load_column<K>(b, w.ci_next, w.h, w.frag, bn, nsd);
     w.ci_next = cb + 2 < c1 ? column_of(b, w.nD, cb + 2, w.cl) : -1;
   }
   // keep the prefetch ahead of the matrix-core work
   __builtin_amdgcn_sched_barrier(0);
 
+  // k-step outer, row block inner: the four accumulator chains interleave,
+  // so no MFMA waits for the one before it
   f32x16 acc[kRB];
 #pragma unroll
-  for (int rb = 0; rb < kRB; ++rb) {
-    acc[rb] = f32x16{};
+  for (int rb = 0; rb < kRB; ++rb) acc[rb] = f32x16{};
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk)
+  for (int kk = 0; kk < KS; ++kk)
+#pragma unroll
+    for (int rb = 0; rb < kRB; ++rb)
       acc[rb] = __builtin_amdgcn_mfma_f32_32x32x16_f16(af[rb][kk], bf[kk],
                                                        acc[rb], 0, 0, 0);
-  }
   const float csa = sd.sa, csc = sd.sc;
 
   // Per (range, domain) pair: max_k |H_k| + K/4 bounds |G_k - SA Sb/K| for
@@ -381,7 +391,8 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     const ColRec cur = sd;
     if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
     if (blk + 1 < nb)
-      load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, bf, sd);
+      load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, w.frag,
+                     bf, sd);
     // flat domains and padding columns (sqrt(D') = +inf) score 0 and take no
     // part (as does a candidate with H = 0)
     const float idp =
@@ -555,6 +566,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.qn = 0;
   w.gsnap = ~0ull;
   w.nD = nD;
+  w.frag = g.ctr && g.full;
   if (c0 >= c1) return;
 
   // the wave's range slots, their keys and sums; the first two columns
@@ -575,7 +587,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.ci_next = c0 + 1 < c1 ? column_of(b, nD, c0 + 1, w.cl) : -1;
   half8 bA[KS], bB[KS];  // two buffers for the streamed domain operand
   ColRec sdA, sdB;
-  load_column<K>(b, ci0, w.h, bA, sdA);
+  load_column<K>(b, ci0, w.h, w.frag, bA, sdA);
   __builtin_amdgcn_wave_barrier();
 
   half8 af[kRB][KS];

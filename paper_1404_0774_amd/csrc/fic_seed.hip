@@ -70,8 +70,8 @@ __device__ __forceinline__ void seed_dense_body(const Geo &g, const EncBufs &b,
     for (int i = t; i < NP * 32 * PER; i += 256) {
       const int pl = i / (32 * PER), ii = i % (32 * PER);
       const int col = ii / PER, p0 = (ii % PER) * 8;
-      const half8_t v = *(const half8_t *)(b.bop + (size_t)pl * g.NC_pad * K +
-                                           ((size_t)cb * 32 + col) * K + p0);
+      const half8_t v = *(const half8_t *)(
+          b.bop + (size_t)pl * g.NC_pad * K + bop_index(g, (long long)cb * 32 + col, p0));
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         sB[pl][p0 / 2 + e][col] = half2_t{v[2 * e], v[2 * e + 1]};
