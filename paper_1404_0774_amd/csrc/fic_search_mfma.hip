@@ -18,9 +18,10 @@
 // stays below 2^22 in magnitude, so v_mfma_f32_32x32x16_f16 with FP32
 // accumulation produces H exactly, and
 //       G = H + m_r SA + m_d Sb - K m_d m_r            (exact in FP64),
-//       G - SA Sb / K = H - K delta_d delta_r,
+//       G - SA Sb / K = H - c,   c = K delta_d delta_r,
 // with delta_d = SA/K - m_d and delta_r = Sb/K - m_r in [-1/2, 1/2], so the
-// least-squares quantity of the prune differs from H by at most K/4.
+// least-squares quantity of the prune differs from H by the same small c
+// (|c| <= K/4) for all 8 transforms of a pair.
 //
 // The output is never stored.  Each 32x32 MFMA tile holds, per lane, one
 // domain column and the 8 transforms of two ranges (the row order of the
@@ -28,8 +29,9 @@
 // exact-safe least-squares bound shared by the 8 transforms: a candidate can
 // only tie or beat the range's best residual if
 //       |G - SA Sb / K| >= sqrt(W' D'),
-// so a (range, domain) pair can be skipped when max_k |H_k| + K/4 is below
-// that threshold: one max-of-absolute-values and one fused compare per pair.
+// so a (range, domain) pair can be skipped when max_k |H_k| + |c| is below
+// that threshold: one max of absolute values, one product and one fused
+// compare per pair.
 // Pairs that pass are appended, with their 8 H values and the column's
 // statistics, to a per-wave LDS queue; 64 at a time they are re-tested per
 // transform, the surviving transforms are compacted into a list and fitted
@@ -195,7 +197,8 @@ struct WaveState {
   double2 *rstat;            // LDS: (Sb, Sbb) per range
   QEntry *queue;             // LDS: queued pairs
   Cand *cands;               // LDS: drain candidates
-  float *wtab;               // LDS: prune weights [2][kSlots]
+  float *wtab;               // LDS: prune thresholds sqrt(W') [2][kSlots]
+  float *dtab;               // LDS: (Sb - K m_r) / K per range [2][kSlots]
   int *slots;                // LDS: range slot of each wave range (-1: none)
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
@@ -243,8 +246,9 @@ __device__ __forceinline__ void sweep_block(
     ColRec &nsd, int cb, int c0, int c1) {
   constexpr int KS = K / 16;
   // the lane's 8 prune thresholds sqrt(W'), kept in LDS between blocks
-  float sw[kSlots];
+  float sw[kSlots], rd[kSlots];
   read_slots(w.wtab, w.h, sw);
+  read_slots(w.dtab, w.h, rd);
   const int slot = (cb - c0) % kSync;
   {
     // the next block (its column index came a block earlier) and the index
@@ -268,21 +272,37 @@ __device__ __forceinline__ void sweep_block(
                                                        acc[rb], 0, 0, 0);
   const float csa = sd.sa, csc = sd.sc;
 
-  // Per (range, domain) pair: max_k |H_k| + K/4 bounds |G_k - SA Sb/K| for
-  // all 8 transforms, so the pair can only matter if max_k |H_k| >=
-  // sqrt(W') sqrt(D') - K/4 (both roots rounded down; +inf for a flat
-  // domain or range, and 0 * inf = NaN for a flat domain against a useless
-  // bound: the compare fails both times).  Wave masks of the passing pairs,
-  // one per slot, in scalar registers.
-  constexpr float kq = 0.25f * K;
+  // Per (range, domain) pair: G_k - SA Sb/K = H_k - c with
+  // c = (SA - K m_d)(Sb - K m_r)/K, the same c for all 8 transforms (the
+  // column's SA - K m_d times the slot's (Sb - K m_r) / K, exact).  The pair
+  // can only matter if max_k |H_k - c| >= sqrt(W') sqrt(D') (both roots
+  // rounded down; +inf for a flat domain or range, and 0 * inf = NaN for a
+  // flat domain against a useless bound: the compare fails both times).
+  // 8x8 ranges bound max_k |H_k - c| by max_k |H_k| + |c| (|c| is small
+  // against the thresholds there); 4x4 ranges, whose thresholds are often
+  // as small as |c|, take the exact max(H_max - c, c - H_min).  Wave masks of
+  // the passing pairs, one per slot, in scalar registers.
+  const float cdd = fmaf(-(float)K, centre_f(csa, 1.0f / K), csa);
   unsigned long long pm[kSlots], anym = 0;
 #pragma unroll
   for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int s = 2 * rb + e;
-      pm[s] = __builtin_amdgcn_ballot_w64(abs_max8(acc[rb], e) >=
-                                          fmaf(sw[s], csc, -kq));
+      const float c = cdd * rd[s];
+      bool pass;
+      if constexpr (K == 64) {
+        pass = abs_max8(acc[rb], e) >= fmaf(sw[s], csc, -fabsf(c));
+      } else {
+        float hx = acc[rb][8 * e], hn = hx;
+#pragma unroll
+        for (int k = 1; k < 8; ++k) {
+          hx = fmaxf(hx, acc[rb][8 * e + k]);
+          hn = fminf(hn, acc[rb][8 * e + k]);
+        }
+        pass = fmaxf(hx - c, c - hn) >= sw[s] * csc;
+      }
+      pm[s] = __builtin_amdgcn_ballot_w64(pass);
       anym |= pm[s];
     }
 
@@ -470,6 +490,7 @@ struct SearchLds {
   QEntry queue[4][kQueue];
   Cand cands[4][8 * 64];
   float wtab[4][2 * kSlots];
+  float dtab[4][2 * kSlots];
   int slots[4][kWaveRanges];
 };
 
@@ -562,6 +583,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.queue = lds.queue[wave];
   w.cands = lds.cands[wave];
   w.wtab = lds.wtab[wave];
+  w.dtab = lds.dtab[wave];
   w.slots = lds.slots[wave];
   w.qn = 0;
   w.gsnap = ~0ull;
@@ -609,6 +631,12 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     }
   }
   seed_blocks<K>(g, b, w, af, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
+  // the range half of each pair's correction, (Sb - K m_r) / K (exact)
+  if (w.lane < kWaveRanges) {
+    const float sbf = (float)w.rstat[w.lane].x, ik = (float)g.invK;
+    w.dtab[((w.lane >> 1) & 1) * kSlots + 2 * (w.lane >> 2) + (w.lane & 1)] =
+        fmaf(-(float)g.K, centre_f(sbf, ik), sbf) * ik;
+  }
   refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
     sweep_block<K>(g, b, w, af, bA, sdA, bB, sdB, cb, c0, c1);
