@@ -104,6 +104,36 @@ def pmc_summary(fetch_dir, write_dir):
     return "\n".join(lines) + "\n"
 
 
+def counters_summary(dirs):
+    """Markdown summary of rocprofv3 --pmc runs of `bench.py --no-extras`
+    (the full 512x512 u8 search): the SQ counters of the search kernel per
+    wave, averaged over its dispatches."""
+    vals = {}
+    waves = None
+    for d in dirs:
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if SEARCH_KERNEL not in r["Kernel_Name"].replace("(anonymous namespace)::", ""):
+                    continue
+                vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if "SQ_WAVES" in vals:
+        waves = sum(vals["SQ_WAVES"]) / len(vals["SQ_WAVES"])
+    lines = [f"# SQ counters of {SEARCH_KERNEL}, 512x512 u8 full search (rocprofv3 --pmc)", "",
+             "Commands (from /tmp, TMPDIR=/tmp), one per counter group:", "",
+             "    rocprofv3 --pmc <counters> --output-format csv -d <dir> -o run -- "
+             "/usr/bin/python3 /root/repo/bench.py --steps 3 --warmup 1 --no-extras --no-cpu-baseline",
+             "    python bench.py --counters-summary <dir> [<dir> ...]", "",
+             f"Waves per dispatch: {waves:.0f}" if waves else "Waves per dispatch: (not collected)", "",
+             "| counter | mean per dispatch | per wave |", "|---|---|---|"]
+    for c in sorted(vals):
+        m = sum(vals[c]) / len(vals[c])
+        pw = f"{m / waves:.1f}" if waves else "-"
+        lines.append(f"| {c} | {m:.0f} | {pw} |")
+    lines += ["", "SQ_*_CYCLES, SQ_WAIT_* and SQ_ACTIVE_* count quad-cycles (4 clocks) summed "
+              "over waves; SQ_VALU_MFMA_BUSY_CYCLES counts clocks summed over SIMDs (1024)."]
+    return "\n".join(lines) + "\n"
+
+
 def psnr(x, ref, peak):
     mse = float(((x - ref) ** 2).mean())
     return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
@@ -212,6 +242,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=4096, help="ranges timed on the CPU oracle")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="print the traffic summary of two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--counters-summary", nargs="+", metavar="PMC_DIR",
+                    help="print the search kernel's SQ counters from rocprofv3 --pmc runs and exit")
     ap.add_argument("--trace-summary", nargs=2, metavar=("STATS_DIR", "COMMAND"),
                     help="print the kernel-duration summary of a rocprofv3 --stats run and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -220,6 +252,9 @@ def main():
     args = ap.parse_args()
     if args.pmc_summary:
         sys.stdout.write(pmc_summary(*args.pmc_summary))
+        return
+    if args.counters_summary:
+        sys.stdout.write(counters_summary(args.counters_summary))
         return
     if args.trace_summary:
         sys.stdout.write(trace_summary(*args.trace_summary))
