@@ -301,7 +301,7 @@ int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes);
  *   *out.n_leaves (device) receives the leaf count.
  * Errors: FIC_E_INVALID (null pointers, tau NaN, min_range_size not a
  * power-of-two fraction of range_size, workspace misaligned),
- * FIC_E_UNSUPPORTED (sides other than 4 and 8, parameters as fic_query),
+ * FIC_E_UNSUPPORTED (sides other than 4, 8 and 16, parameters as fic_query),
  * FIC_E_WORKSPACE, FIC_E_HIP.
  */
 typedef struct {
