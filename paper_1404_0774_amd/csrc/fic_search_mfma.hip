@@ -202,7 +202,6 @@ struct WaveState {
   int *slots;                // LDS: range slot of each wave range (-1: none)
   int ci_next;               // column of the next block (-1: none)
   int nD;                    // searched domain columns
-  bool frag;                 // domain operand in fragment order
   int qn;                    // queued pairs (wave-uniform)
   unsigned long long gsnap;  // global keys as last read (lanes < 16)
   int wr0, h, cl, lane;
@@ -210,17 +209,16 @@ struct WaveState {
 
 // Column ci of the domain operand and its record; ci < 0 (past the searched
 // columns) reads column 0 and marks it flat, so it never passes the prune.
-// frag: the operand is in fragment order (a full search), where lane
+// FRAG: the operand is in fragment order (a full search), where lane
 // (h, c mod 32) of k-step kk reads 16 bytes at block offset kk 1024 + 16 lane.
-template <int K>
+template <int K, bool FRAG>
 __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
-                                            bool frag, half8 (&bn)[K / 16],
-                                            ColRec &nsd) {
+                                            half8 (&bn)[K / 16], ColRec &nsd) {
   const int c = ci >= 0 ? ci : 0;
   const _Float16 *bsrc =
-      frag ? b.bop + (size_t)(c >> 5) * 32 * K + ((h << 5) | (c & 31)) * 8
+      FRAG ? b.bop + (size_t)(c >> 5) * 32 * K + ((h << 5) | (c & 31)) * 8
            : b.bop + (size_t)c * K + 8 * h;
-  const int kstep = frag ? 512 : 16;
+  constexpr int kstep = FRAG ? 512 : 16;
 #pragma unroll
   for (int kk = 0; kk < K / 16; ++kk)
     bn[kk] = gld((const half8 *)(bsrc + kstep * kk));
@@ -239,7 +237,7 @@ __device__ __forceinline__ int column_of(const EncBufs &b, int nD, int cb,
 // One 32-column block: prefetch the next block's operand and column records
 // into (bn, nsd), run the MFMA
 // contraction with (bf, sd), prune, queue survivors, sync every few blocks.
-template <int K>
+template <int K, bool FRAG>
 __device__ __forceinline__ void sweep_block(
     const Geo &g, const EncBufs &b, WaveState &w, const half8 (&af)[kRB][K / 16],
     const half8 (&bf)[K / 16], const ColRec &sd, half8 (&bn)[K / 16],
@@ -248,12 +246,12 @@ __device__ __forceinline__ void sweep_block(
   // the lane's 8 prune thresholds sqrt(W'), kept in LDS between blocks
   float sw[kSlots], rd[kSlots];
   read_slots(w.wtab, w.h, sw);
-  read_slots(w.dtab, w.h, rd);
+  if constexpr (K != 64) read_slots(w.dtab, w.h, rd);
   const int slot = (cb - c0) % kSync;
   {
     // the next block (its column index came a block earlier) and the index
     // of the block after it
-    load_column<K>(b, w.ci_next, w.h, w.frag, bn, nsd);
+    load_column<K, FRAG>(b, w.ci_next, w.h, bn, nsd);
     w.ci_next = cb + 2 < c1 ? column_of(b, w.nD, cb + 2, w.cl) : -1;
   }
   // keep the prefetch ahead of the matrix-core work
@@ -278,22 +276,25 @@ __device__ __forceinline__ void sweep_block(
   // can only matter if max_k |H_k - c| >= sqrt(W') sqrt(D') (both roots
   // rounded down; +inf for a flat domain or range, and 0 * inf = NaN for a
   // flat domain against a useless bound: the compare fails both times).
-  // 8x8 ranges bound max_k |H_k - c| by max_k |H_k| + |c| (|c| is small
-  // against the thresholds there); 4x4 ranges, whose thresholds are often
-  // as small as |c|, take the exact max(H_max - c, c - H_min).  Wave masks of
-  // the passing pairs, one per slot, in scalar registers.
+  // 8x8 ranges bound max_k |H_k - c| by max_k |H_k| + |SA - K m_d| / 2
+  // (>= |c|, small against the thresholds there); 4x4 ranges, whose
+  // thresholds are often as small as |c|, take the exact
+  // max(H_max - c, c - H_min).  Wave masks of the passing pairs, one per
+  // slot, in scalar registers.
   const float cdd = fmaf(-(float)K, centre_f(csa, 1.0f / K), csa);
+  const float cdh = 0.5f * fabsf(cdd);
   unsigned long long pm[kSlots], anym = 0;
 #pragma unroll
   for (int rb = 0; rb < kRB; ++rb)
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const int s = 2 * rb + e;
-      const float c = cdd * rd[s];
       bool pass;
       if constexpr (K == 64) {
-        pass = abs_max8(acc[rb], e) >= fmaf(sw[s], csc, -fabsf(c));
+        // |c| <= |SA - K m_d| / 2, one bound per column
+        pass = abs_max8(acc[rb], e) >= fmaf(sw[s], csc, -cdh);
       } else {
+        const float c = cdd * rd[s];
         float hx = acc[rb][8 * e], hn = hx;
 #pragma unroll
         for (int k = 1; k < 8; ++k) {
@@ -373,7 +374,7 @@ __device__ __forceinline__ void sweep_block(
 constexpr int kSeedBlocks = 1;
 constexpr int kHBias = 1 << 22;  // |H| < 2^22: H + 2^22 fits 23 bits
 
-template <int K>
+template <int K, bool FRAG>
 __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
                                             WaveState &w,
                                             const half8 (&af)[kRB][K / 16],
@@ -411,8 +412,8 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     const ColRec cur = sd;
     if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
     if (blk + 1 < nb)
-      load_column<K>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h, w.frag,
-                     bf, sd);
+      load_column<K, FRAG>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h,
+                           bf, sd);
     // flat domains and padding columns (sqrt(D') = +inf) score 0 and take no
     // part (as does a candidate with H = 0)
     const float idp =
@@ -566,7 +567,7 @@ __device__ __forceinline__ void range_fragments_from_pixels(
 // list) against searched column blocks [c0, c1).  nA, nD: lengths of the two
 // lists.  img: the 8-bit image when the range fragments come from pixels
 // (K = 64), else null (read the range operand).
-template <int K>
+template <int K, bool FRAG>
 __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
                                             const uint8_t *img,
                                             SearchLds &lds, int row0, int nA,
@@ -588,7 +589,6 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.qn = 0;
   w.gsnap = ~0ull;
   w.nD = nD;
-  w.frag = g.ctr && g.full;
   if (c0 >= c1) return;
 
   // the wave's range slots, their keys and sums; the first two columns
@@ -609,7 +609,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   w.ci_next = c0 + 1 < c1 ? column_of(b, nD, c0 + 1, w.cl) : -1;
   half8 bA[KS], bB[KS];  // two buffers for the streamed domain operand
   ColRec sdA, sdB;
-  load_column<K>(b, ci0, w.h, w.frag, bA, sdA);
+  load_column<K, FRAG>(b, ci0, w.h, bA, sdA);
   __builtin_amdgcn_wave_barrier();
 
   half8 af[kRB][KS];
@@ -630,7 +630,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
         af[rb][kk] = sl >= 0 ? gld((const half8 *)(src + 16 * kk)) : half8{};
     }
   }
-  seed_blocks<K>(g, b, w, af, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
+  seed_blocks<K, FRAG>(g, b, w, af, bA, sdA, c0, min(kSeedBlocks, c1 - c0));
   // the range half of each pair's correction, (Sb - K m_r) / K (exact)
   if (w.lane < kWaveRanges) {
     const float sbf = (float)w.rstat[w.lane].x, ik = (float)g.invK;
@@ -639,9 +639,9 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   }
   refresh_weights(w.best, w.rstat, w.wtab, w.lane, g);
   for (int cb = c0; cb < c1; cb += 2) {
-    sweep_block<K>(g, b, w, af, bA, sdA, bB, sdB, cb, c0, c1);
+    sweep_block<K, FRAG>(g, b, w, af, bA, sdA, bB, sdB, cb, c0, c1);
     if (cb + 1 < c1)
-      sweep_block<K>(g, b, w, af, bB, sdB, bA, sdA, cb + 1, c0, c1);
+      sweep_block<K, FRAG>(g, b, w, af, bB, sdB, bA, sdA, cb + 1, c0, c1);
   }
 }
 
@@ -662,7 +662,11 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   if (rg >= rows) return;
   const int cbpc = (ncb + chunks - 1) / chunks;
   const int c0 = chunk * cbpc, c1 = min(c0 + cbpc, ncb);
-  search_rows<K>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0, c1);
+  if (g.ctr && g.full)
+    search_rows<K, true>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0, c1);
+  else
+    search_rows<K, false>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0,
+                          c1);
 }
 
 // Spin limit of a code-extraction item's wait (about a second): the wait
@@ -723,9 +727,14 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const int nD = __builtin_amdgcn_readfirstlane(gld(&b.n_act[1]));
     const int row0 = w.y * kMfmaRangesPerWG;
     const int c1 = min(w.w, (nD + 31) / 32);
-    if (row0 < nA && w.z < c1)
-      search_rows<K>(g, b, g.pix_a ? img : nullptr, lds, row0, nA, nD, w.z,
-                     c1);
+    if (row0 < nA && w.z < c1) {
+      if (g.ctr && g.full)
+        search_rows<K, true>(g, b, g.pix_a ? img : nullptr, lds, row0, nA, nD,
+                             w.z, c1);
+      else
+        search_rows<K, false>(g, b, g.pix_a ? img : nullptr, lds, row0, nA,
+                              nD, w.z, c1);
+    }
     // every wave's key updates are complete and visible device-wide before
     // the count that lets code extraction start
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
