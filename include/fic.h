@@ -250,6 +250,9 @@ int fic_decode_scaled(const fic_params *p, int32_t scale_num,
  * (height*width floats), writes dL/ds and dL/do (n_ranges floats each,
  * overwritten).  Deterministic: repeated calls give identical bits.
  *   workspace  device, >= backward_ws_bytes from fic_query
+ * Errors: FIC_E_INVALID (null pointers, iters < 0, workspace not 256-byte
+ * aligned), FIC_E_UNSUPPORTED (16x16 ranges, more than 2^28 pixels),
+ * FIC_E_WORKSPACE.
  */
 int fic_decode_backward(const fic_params *p, const int32_t *domain,
                         const uint8_t *iso, const float *s, const float *o,
@@ -270,7 +273,7 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
  *   loss      device, steps + 1 doubles: L before each step and after the last
  *   workspace device, >= fic_refine_workspace bytes, 256-byte aligned
  * Errors: FIC_E_INVALID (null pointers, negative iters/steps/rates),
- * FIC_E_WORKSPACE.
+ * FIC_E_UNSUPPORTED (16x16 ranges, more than 2^28 pixels), FIC_E_WORKSPACE.
  */
 int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
                float *s, float *o, const void *image, int32_t iters, float x0,

@@ -535,6 +535,8 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
   if (st) return st;
   if (g.n == 16)
     return fail(FIC_E_UNSUPPORTED, "the adjoint takes 4x4 or 8x8 ranges");
+  if ((long long)g.H * g.W > (1ll << 28))
+    return fail(FIC_E_UNSUPPORTED, "the adjoint takes at most 2^28 pixels");
   if (!domain || !iso || !s || !o || !traj || !grad_xT || !grad_s || !grad_o ||
       !workspace)
     return fail(FIC_E_INVALID, "null pointer argument");
@@ -571,6 +573,8 @@ int fic_refine(const fic_params *p, const int32_t *domain, const uint8_t *iso,
   if (st) return st;
   if (g.n == 16)
     return fail(FIC_E_UNSUPPORTED, "refinement takes 4x4 or 8x8 ranges");
+  if ((long long)g.H * g.W > (1ll << 28))
+    return fail(FIC_E_UNSUPPORTED, "refinement takes at most 2^28 pixels");
   if (!domain || !iso || !s || !o || !image || !loss || !workspace)
     return fail(FIC_E_INVALID, "null pointer argument");
   if (iters < 0 || steps < 0)

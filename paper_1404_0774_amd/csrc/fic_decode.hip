@@ -12,14 +12,14 @@
 //   dL/ds_r += sum_{p in r} g_{t+1}[p] u_t[p],  dL/do_r += sum_{p in r} g_{t+1}[p]
 //   g_t[q]   = sum over range pixels p whose cell contains q of s_r g_{t+1}[p] / 4.
 // The last sum is a gather, never a float atomic.  A table lists, for every
-// domain, the ranges that use it in increasing range order (a stable radix
-// sort of the range -> domain map).  The lists are cut into segments of
-// kSeg ranges; per step, one thread per (segment, cell) sums the segment's
-// contributions to that cell, and one thread per pixel q adds the segments
-// of the domains covering q, domains and segments in increasing order.  A
-// domain shared by thousands of ranges (flat background) thus costs a short
-// sum per pixel, and every sum has a fixed order, so the result is bitwise
-// reproducible.
+// domain, the ranges that use it in increasing range order (a stable sort of
+// the range -> domain map, in one workgroup's LDS when it fits).  The gather
+// runs over units (the 2x2 cells of an even domain grid, else pixels): a
+// padded table holds each light unit's (pixel, weight) entries, and each
+// heavy unit (a domain shared by many ranges, such as flat background) gets
+// a workgroup of its own.  One launch per reverse step does the heavy units,
+// dL/ds and dL/do, and the light units; every sum has a fixed order, so the
+// result is bitwise reproducible.
 #include <algorithm>
 #include <utility>
 
@@ -170,9 +170,10 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
 }
 
 // --- the domain -> ranges table --------------------------------------------
-
-constexpr int kSeg = 16;     // ranges per list segment
-constexpr int kGather = 32;  // segment partials loaded per round
+//
+// srt[e], e < R: the ranges sorted by domain, in increasing range order within
+// a domain (a stable sort of the range -> domain map); domain d's entries are
+// srt[off[d] .. off[d + 1]).  Built once per set of domains.
 
 // Number of entries of the sorted keys key[0 .. n) below v.
 __device__ __forceinline__ int lower_bound(const int32_t *key, int n, int v) {
@@ -187,29 +188,24 @@ __device__ __forceinline__ int lower_bound(const int32_t *key, int n, int v) {
   return lo;
 }
 
-// From the ranges sorted by domain: where each domain's list starts
-// (off[0 .. ND]) and its length (cnt[0 .. ND)).  A binary search per domain
+// off[0 .. ND] from the ranges sorted by domain (a binary search per domain
 // instead of counting with atomics, which would queue up on a domain that
-// thousands of ranges share.
-__global__ void k_bounds(Geo g, const int32_t *sorted, int32_t *off,
-                         int32_t *cnt) {
+// thousands of ranges share).
+__global__ void k_bounds(Geo g, const int32_t *sorted, int32_t *off) {
   const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d > g.ND) return;
-  const int a = lower_bound(sorted, g.R, d);
-  off[d] = a;
-  if (d < g.ND) cnt[d] = lower_bound(sorted, g.R, d + 1) - a;
+  if (d <= g.ND) off[d] = lower_bound(sorted, g.R, d);
 }
 
-// Exclusive scan of ceil(in[i] / div), i < n, into out[0..n]; one workgroup
-// of 1024 threads, each owning a contiguous slice.
+// Exclusive scan of in[i], i < n, into out[0..n]; one workgroup of 1024
+// threads, each owning a contiguous slice.
 __global__ __launch_bounds__(1024) void k_scan(const int32_t *in, int n,
-                                               int div, int32_t *out) {
+                                               int32_t *out) {
   __shared__ int part[1024];
   const int t = threadIdx.x;
   const int per = (n + 1023) / 1024;
   const int b0 = min(t * per, n), b1 = min(b0 + per, n);
   int s = 0;
-  for (int i = b0; i < b1; ++i) s += (in[i] + div - 1) / div;
+  for (int i = b0; i < b1; ++i) s += in[i];
   part[t] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -221,16 +217,18 @@ __global__ __launch_bounds__(1024) void k_scan(const int32_t *in, int n,
   int run = t ? part[t - 1] : 0;
   for (int i = b0; i < b1; ++i) {
     out[i] = run;
-    run += (in[i] + div - 1) / div;
+    run += in[i];
   }
   if (t == 1023) out[n] = part[1023];
 }
 
-// Stable LSD radix sort of (domain, range) pairs by domain, 8 bits a pass,
-// blocks of 256 pairs: block histograms, one scan, stable scatter.
+// Large tables: stable LSD radix sort of (domain, range) pairs by domain, 8
+// bits a pass, blocks of 256 pairs: block histograms, one scan, stable
+// scatter.  k_rs_init also clears the heavy-unit count.
 __global__ void k_rs_init(Geo g, const int32_t *domain, int32_t *key,
-                          int32_t *val) {
+                          int32_t *val, int32_t *nheavy) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r == 0) *nheavy = 0;
   if (r >= g.R) return;
   key[r] = clamp_dom(domain[r], g.ND);
   val[r] = r;
@@ -267,22 +265,294 @@ __global__ __launch_bounds__(256) void k_rs_scatter(const int32_t *kin,
   vout[pos] = vin[i];
 }
 
-// Segment table: segment s covers list entries [beg, end) of one domain.
-// One thread per segment; its domain is the last d with segoff[d] <= s.
-__global__ void k_seg_fill(Geo g, const int32_t *off, const int32_t *segoff,
-                           int max_seg, int2 *seg) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= max_seg || s >= segoff[g.ND]) return;
-  int lo = 0, hi = g.ND - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (segoff[mid] <= s)
-      lo = mid;
-    else
-      hi = mid - 1;
+// Small tables (R <= kSortR, ND <= kSortND): the whole sort in one
+// workgroup, in LDS.  Keys (domain << kRBits) | range, stable LSD passes of
+// at most 6 bits over the domain bits.  Wave w owns keys [w C, (w + 1) C) in
+// rounds of 64; a key's rank among the earlier keys of its wave with the
+// same digit comes from the digit's bits as ballots (the lanes agreeing on
+// every bit), plus the wave's running count of that digit in LDS.  The
+// counts, scanned digit-major and wave-minor, give every key its place:
+// equal digits keep their order, so the sort is stable and its result is
+// fixed.  Then off[d] by binary search over the sorted keys.
+constexpr int kSortR = 8192;
+constexpr int kSortND = 16384;
+constexpr int kRBits = 13;  // kSortR = 2^kRBits
+
+// Inclusive scan (sum, or minimum when MIN) across the 64 lanes of a wave:
+// shifts by 1, 2, 4, 8 within rows of 16 lanes, then each row takes the
+// last lane of the row before (row broadcasts 15 and 31).  Lanes without a
+// source take the identity.
+template <bool MIN>
+__device__ __forceinline__ int wave_scan(int v) {
+  const int id = MIN ? 0x7fffffff : 0;
+  int x;
+#define FIC_SCAN_STEP(ctrl, rows)                                      \
+  x = __builtin_amdgcn_update_dpp(id, v, ctrl, rows, 0xf, false);     \
+  v = MIN ? min(v, x) : v + x;
+  FIC_SCAN_STEP(0x111, 0xf)  // row_shr:1
+  FIC_SCAN_STEP(0x112, 0xf)  // row_shr:2
+  FIC_SCAN_STEP(0x114, 0xf)  // row_shr:4
+  FIC_SCAN_STEP(0x118, 0xf)  // row_shr:8
+  FIC_SCAN_STEP(0x142, 0xa)  // row_bcast:15 into rows 1 and 3
+  FIC_SCAN_STEP(0x143, 0xc)  // row_bcast:31 into rows 2 and 3
+#undef FIC_SCAN_STEP
+  return v;
+}
+
+// off[c0 + q] = min(st[c0 + q ..]), chunk c0 = (1023 - t) per of P >= per
+// entries a thread: the chunk's own suffix minima, then a forward minimum
+// scan over the threads (the later chunks).
+template <int P>
+__device__ __forceinline__ void suffix_min_off(const int *st, int n1, int per,
+                                               int R, int t, int *wtot,
+                                               int32_t *off) {
+  const int lane = t & 63, w = t >> 6;
+  const int c0 = (1023 - t) * per;
+  int sv[P];
+#pragma unroll
+  for (int q = 0; q < P; ++q) sv[q] = q < per && c0 + q < n1 ? st[c0 + q] : R;
+#pragma unroll
+  for (int q = P - 2; q >= 0; --q) sv[q] = min(sv[q], sv[q + 1]);
+  const int inc = wave_scan<true>(sv[0]);
+  if (lane == 63) wtot[w] = inc;
+  __syncthreads();
+  int later = R;
+#pragma unroll
+  for (int y = 0; y < 15; ++y) later = y < w ? min(later, wtot[y]) : later;
+  const int prev = __shfl_up(inc, 1);
+  if (lane > 0) later = min(later, prev);
+#pragma unroll
+  for (int q = 0; q < P; ++q)
+    if (q < per && c0 + q < n1) off[c0 + q] = min(sv[q], later);
+}
+
+__global__ __launch_bounds__(1024) void k_sort_small(Geo g,
+                                                     const int32_t *domain,
+                                                     int32_t *srt, int32_t *off,
+                                                     int32_t *nheavy) {
+  __shared__ uint32_t kb[2][kSortR];
+  __shared__ int st[kSortND + 1];  // first sorted position of each domain
+  __shared__ int cnt[16 * 64];     // [wave][digit], then the digits' bases
+  __shared__ unsigned long long msk[16 * 64];  // [wave][digit]: lanes of a round
+  __shared__ int wtot[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int R = g.R;
+  if (t == 0) *nheavy = 0;
+  msk[t] = 0;
+  {
+    int dv[kSortR / 1024];  // all loads in flight before the first store
+#pragma unroll
+    for (int u = 0; u < kSortR / 1024; ++u)
+      dv[u] = t + 1024 * u < R ? domain[t + 1024 * u] : 0;
+#pragma unroll
+    for (int u = 0; u < kSortR / 1024; ++u)
+      if (t + 1024 * u < R)
+        kb[0][t + 1024 * u] = ((uint32_t)clamp_dom(dv[u], g.ND) << kRBits) |
+                              (uint32_t)(t + 1024 * u);
   }
-  const int x = off[lo] + (s - segoff[lo]) * kSeg;
-  seg[s] = int2{x, min(x + kSeg, off[lo + 1])};
+  int bits = 0;
+  while ((1 << bits) < g.ND) ++bits;
+  const int np = (bits + 5) / 6;
+  const int wd = np ? (bits + np - 1) / np : 0;
+  const int C = (R + 15) >> 4;  // keys per wave, <= 512
+  int cur = 0;
+  for (int p = 0; p < np; ++p) {
+    const int sh = kRBits + p * wd, D = 1 << wd;
+    cnt[t] = 0;
+    __syncthreads();
+    uint32_t v[8];
+    int dg[8], loc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {  // the wave's keys, all reads in flight
+      const int ci = j * 64 + lane, i = w * C + ci;
+      const bool valid = ci < C && i < R;
+      v[j] = valid ? kb[cur][i] : 0;
+      dg[j] = valid ? (int)((v[j] >> sh) & (uint32_t)(D - 1)) : -1;
+      loc[j] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j * 64 < C && dg[j] >= 0) {  // j * 64 < C: the same for the wave
+        // the lanes with this digit: each ORs its bit into the digit's mask
+        // (one instruction for the wave; a wave's LDS operations complete in
+        // order, so the read after it sees every lane's bit)
+        const int a = w * 64 + dg[j];
+        atomicOr(&msk[a], 1ull << lane);
+        const uint64_t m = msk[a];
+        const int base = cnt[a];
+        const int below = __builtin_amdgcn_mbcnt_hi(
+            (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+        loc[j] = base + below;
+        if (below == 0) {  // the digit's first lane: count and clear
+          cnt[a] = base + __popcll(m);
+          msk[a] = 0;
+        }
+      }
+    }
+    __syncthreads();
+    // exclusive scan of the counts, digit q and wave x at position 16 q + x
+    const int q = t >> 4, x = t & 15;
+    const int val = q < D ? cnt[x * 64 + q] : 0;
+    const int inc = wave_scan<false>(val);
+    if (lane == 63) wtot[w] = inc;
+    __syncthreads();
+    int pre = 0;
+#pragma unroll
+    for (int y = 0; y < 15; ++y) pre += y < w ? wtot[y] : 0;
+    if (q < D) cnt[x * 64 + q] = pre + inc - val;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (dg[j] >= 0) kb[cur ^ 1][cnt[w * 64 + dg[j]] + loc[j]] = v[j];
+    cur ^= 1;
+    __syncthreads();
+  }
+  __syncthreads();  // with no pass (one domain), after the key loads
+  const uint32_t *ks = kb[cur];
+  for (int i = t; i < R; i += 1024)
+    srt[i] = (int)(ks[i] & ((1u << kRBits) - 1));
+  // off[d]: st[d] = the first sorted position of domain d (R if absent),
+  // then off[d] = the minimum of st over d' >= d.  Thread t takes chunk
+  // 1023 - t of per entries, so a forward minimum scan over the threads is a
+  // minimum over the later chunks.
+  const int n1 = g.ND + 1;
+  for (int d = t; d < n1; d += 1024) st[d] = R;
+  __syncthreads();
+  for (int i = t; i < R; i += 1024) {
+    const uint32_t dk = ks[i] >> kRBits;
+    if (i == 0 || (ks[i - 1] >> kRBits) != dk) st[dk] = i;
+  }
+  __syncthreads();
+  const int per = (n1 + 1023) >> 10;
+  if (per <= 4)
+    suffix_min_off<4>(st, n1, per, R, t, wtot, off);
+  else
+    suffix_min_off<(kSortND + 1 + 1023) / 1024>(st, n1, per, R, t, wtot, off);
+}
+
+// --- per-unit tables --------------------------------------------------------
+//
+// The reverse step's gather works on units: 2x2 pixel blocks when STEP is
+// even (every cell of every domain is then such a block, and its four pixels
+// receive the same sum), single pixels when STEP is odd.  A unit is covered
+// by the domains dy0..dy1 x dx0..dx1; its entries are those domains' lists
+// in that order (row-major), each list in range order.  A unit with at most
+// kEll entries is light: its entries (pixel p read by the range, weight
+// s_r / 4) sit in a padded table, slot pairs as planes of U int4, padding
+// pixel -1.  A heavier unit is marked -2 in slot 0 and listed in heavy[],
+// with the bounds of its covering lists when at most 2 x 2 domains cover a
+// unit (STEP >= n).
+
+constexpr int kEll = 16;
+
+__device__ __forceinline__ size_t ell_at(int slot, int u, int U) {
+  return ((size_t)(slot >> 1) * U + u) * 2 + (slot & 1);
+}
+
+// Domains covering pixel (qy, qx) (for a 2x2 unit at even (qy, qx) and an
+// even STEP, exactly those covering the whole unit).
+__device__ __forceinline__ void cover(const Geo &g, int qy, int qx, int &dy0,
+                                      int &dy1, int &dx0, int &dx1) {
+  const int span = 2 * g.n;
+  const int ly = qy - span + 1, lx = qx - span + 1;
+  dy0 = ly <= 0 ? 0 : (ly + g.step - 1) / g.step;
+  dx0 = lx <= 0 ? 0 : (lx + g.step - 1) / g.step;
+  dy1 = min(qy / g.step, g.NY - 1);
+  dx1 = min(qx / g.step, g.NX - 1);
+}
+
+struct UnitArgs {
+  Geo g;
+  const int32_t *domain, *srt, *off;
+  const uint8_t *iso;
+  const float *s;
+  int2 *ell;
+  int32_t *pk, *heavy, *nheavy;
+  int4 *hbeg, *hlen;
+  float *pw;
+  int U, UW, nbu;
+};
+
+// Workgroups [0, nbu): one thread per unit, padding or the heavy mark (these
+// depend on the domains only).  The rest: one thread per (list entry e,
+// domain cell c): the entry's slot in the units that cell covers, and for
+// c = 0 the entry's packed range (top-left pixel << 3 | transform) and
+// weight s_r / 4 for the heavy units.
+template <int N, int UNIT>
+__global__ __launch_bounds__(256) void k_adj_units(UnitArgs a) {
+  const Geo &g = a.g;
+  if ((int)blockIdx.x < a.nbu) {
+    const int u = blockIdx.x * 256 + threadIdx.x;
+    if (u >= a.U) return;
+    const int qy = (u / a.UW) * UNIT, qx = (u % a.UW) * UNIT;
+    int dy0, dy1, dx0, dx1;
+    cover(g, qy, qx, dy0, dy1, dx0, dx1);
+    int E = 0;
+    for (int dy = dy0; dy <= dy1; ++dy)
+      for (int dx = dx0; dx <= dx1; ++dx) {
+        const int d = dy * g.NX + dx;
+        E += a.off[d + 1] - a.off[d];
+      }
+    if (E <= kEll) {
+      for (int sl = E; sl < kEll; ++sl) a.ell[ell_at(sl, u, a.U)] = int2{-1, 0};
+    } else {
+      a.ell[ell_at(0, u, a.U)] = int2{-2, 0};
+      const int h = atomicAdd(a.nheavy, 1);
+      a.heavy[h] = u;
+      if (g.step >= g.n) {  // at most 2 x 2 covering domains: their lists
+        int b4[4], l4[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int dy = dy0 + (q >> 1), dx = dx0 + (q & 1);
+          const bool ok = dy <= dy1 && dx <= dx1;
+          const int d = ok ? dy * g.NX + dx : 0;
+          b4[q] = ok ? a.off[d] : 0;
+          l4[q] = ok ? a.off[d + 1] - b4[q] : 0;
+        }
+        a.hbeg[h] = int4{b4[0], b4[1], b4[2], b4[3]};
+        a.hlen[h] = int4{l4[0], l4[1], l4[2], l4[3]};
+      }
+    }
+    return;
+  }
+  constexpr int K = N * N;
+  const int tid = (blockIdx.x - a.nbu) * 256 + threadIdx.x;
+  const int e = tid / K, c = tid % K;
+  if (e >= g.R) return;
+  const int r = min(max(a.srt[e], 0), g.R - 1);
+  const int d = clamp_dom(a.domain[r], g.ND), k = a.iso[r];
+  const float w = a.s[r] * 0.25f;
+  const int ci = c / N, cj = c % N;
+  int i, j;
+  sigma_inv(k, ci, cj, N - 1, i, j);
+  const int ry = r / g.RW, rx = r % g.RW;
+  const int pbase = (ry * N) * g.W + rx * N;
+  if (c == 0) {
+    a.pk[e] = (pbase << 3) | k;
+    a.pw[e] = w;
+  }
+  const int p = pbase + i * g.W + j;
+  const int ddy = d / g.NX, ddx = d % g.NX;
+  const int Y = ddy * g.step + 2 * ci, X = ddx * g.step + 2 * cj;
+#pragma unroll
+  for (int sub = 0; sub < (UNIT == 1 ? 4 : 1); ++sub) {
+    const int qy = Y + (sub >> 1), qx = X + (sub & 1);
+    int dy0, dy1, dx0, dx1;
+    cover(g, qy, qx, dy0, dy1, dx0, dx1);
+    int pre = 0, E = 0;
+    for (int dy = dy0; dy <= dy1; ++dy)
+      for (int dx = dx0; dx <= dx1; ++dx) {
+        const int dd = dy * g.NX + dx;
+        const int b = a.off[dd], L = a.off[dd + 1] - b;
+        if (dy < ddy || (dy == ddy && dx < ddx)) pre += L;
+        if (dd == d) pre += e - b;
+        E += L;
+      }
+    if (E <= kEll && pre >= 0 && pre < E) {
+      const int u = (qy / UNIT) * a.UW + qx / UNIT;
+      a.ell[ell_at(pre, u, a.U)] = int2{p, __float_as_int(w)};
+    }
+  }
 }
 
 // --- reverse steps ----------------------------------------------------------
@@ -330,118 +600,200 @@ __device__ __forceinline__ void grad_so_body(Geo g, const int32_t *domain,
   }
 }
 
-// One thread per (segment, cell): the segment's share of s_r g_{t+1}[p] / 4
-// over the range pixels p that read that cell of the domain.
-// `nseg` points at the segment count the table build wrote (the grid is
-// sized for the largest possible count).  The segment's entries are loaded
-// in three independent batches (list, codes, gradient) before the ordered
-// sum, so a thread waits for three memory round trips, not 3 kSeg.
-template <int N>
-__device__ __forceinline__ void seg_partial_body(
-    Geo g, const int32_t *nseg, const int2 *seg, const int32_t *list,
-    const uint8_t *iso, const float *s, const float *gnext, float *partial,
-    int bid) {
-  constexpr int K = N * N;
-  const int tid = bid * blockDim.x + threadIdx.x;
-  const int sg = tid / K, c = tid % K, ci = c / N, cj = c % N;
-  if (sg >= *nseg) return;
-  const int2 be = seg[sg];
-  int rr[kSeg];
-#pragma unroll
-  for (int u = 0; u < kSeg; ++u)
-    rr[u] = be.x + u < be.y ? list[be.x + u] : -1;
-  float w[kSeg];
-  int pix[kSeg];
-#pragma unroll
-  for (int u = 0; u < kSeg; ++u) {
-    const int r = rr[u] < 0 ? rr[0] : rr[u];
-    int i, j;
-    sigma_inv(iso[r], ci, cj, N - 1, i, j);
-    const int ry = r / g.RW, rx = r % g.RW;
-    pix[u] = (ry * N + i) * g.W + rx * N + j;
-    w[u] = s[r] * 0.25f;
+struct StepArgs {
+  Geo g;
+  const int32_t *domain;
+  const uint8_t *iso;
+  const float *x, *gnext;
+  float *grad_s, *grad_o, *gout;
+  const int32_t *off, *pk, *heavy, *nheavy;
+  const int4 *hbeg, *hlen;
+  const float *pw;
+  const int2 *ell;
+  int first, nb_hv, nb_so, U, UW;
+};
+
+// g_t over the unit whose top-left pixel is (qy, qx).
+template <int UNIT>
+__device__ __forceinline__ void put_unit(const Geo &g, float *gout, int qy,
+                                         int qx, float v) {
+  float *q = gout + (size_t)qy * g.W + qx;
+  if constexpr (UNIT == 2) {
+    *(float2 *)q = float2{v, v};
+    *(float2 *)(q + g.W) = float2{v, v};
+  } else {
+    *q = v;
   }
-  float gv[kSeg];
-#pragma unroll
-  for (int u = 0; u < kSeg; ++u) gv[u] = gnext[pix[u]];
-  float acc = 0.0f;
-#pragma unroll
-  for (int u = 0; u < kSeg; ++u)
-    if (rr[u] >= 0) acc = fmaf(w[u], gv[u], acc);
-  partial[tid] = acc;
 }
 
-// One launch for the two independent parts of a reverse step: workgroups
-// [0, nb_so) form dL/ds and dL/do, the rest (if any) the segment partials.
+// Entry e of a list, read for the unit cell (cy, cx) of its domain:
+// weight * g_{t+1}[the range pixel that reads that cell].
 template <int N>
-__global__ __launch_bounds__(256) void k_adj_step(
-    Geo g, const int32_t *domain, const uint8_t *iso, const float *x,
-    const float *gnext, float *grad_s, float *grad_o, int first, int nb_so,
-    const int32_t *nseg, const int2 *seg, const int32_t *list, const float *s,
-    float *partial) {
-  if ((int)blockIdx.x < nb_so)
-    grad_so_body<N>(g, domain, iso, x, gnext, grad_s, grad_o, first,
-                    blockIdx.x);
-  else
-    seg_partial_body<N>(g, nseg, seg, list, iso, s, gnext, partial,
-                        blockIdx.x - nb_so);
+__device__ __forceinline__ int entry_pixel(const Geo &g, int pk, int cy,
+                                           int cx) {
+  int i, j;
+  sigma_inv(pk & 7, cy, cx, N - 1, i, j);
+  return min(max((pk >> 3) + i * g.W + j, 0), g.H * g.W - 1);
 }
 
-// One thread per pixel q: g_t[q] = sum of the segment partials of the
-// cells containing q, over the domains covering q (loads batched by
-// kGather: a domain shared by a thousand flat ranges has ~100 segments, and
-// the pixels it covers would otherwise wait for ~13 rounds of loads).
-template <int N>
-__device__ __forceinline__ void grad_x_body(const Geo &g,
-                                            const int32_t *segoff,
-                                            const float *partial, float *gout,
-                                            int bid) {
-  constexpr int K = N * N;
-  const int q = bid * blockDim.x + threadIdx.x;
-  if (q >= g.H * g.W) return;
-  const int qy = q / g.W, qx = q % g.W;
-  const int span = 2 * N;
-  int dy0 = qy - span + 1;
-  dy0 = dy0 <= 0 ? 0 : (dy0 + g.step - 1) / g.step;
-  int dx0 = qx - span + 1;
-  dx0 = dx0 <= 0 ? 0 : (dx0 + g.step - 1) / g.step;
-  const int dy1 = min(qy / g.step, g.NY - 1), dx1 = min(qx / g.step, g.NX - 1);
-  float acc = 0.0f;
-  for (int dy = dy0; dy <= dy1; ++dy)
-    for (int dx = dx0; dx <= dx1; ++dx) {
-      const int d = dy * g.NX + dx;
-      const int s0 = segoff[d], s1 = segoff[d + 1];
-      const int cell = ((qy - dy * g.step) >> 1) * N + ((qx - dx * g.step) >> 1);
-      for (int sb = s0; sb < s1; sb += kGather) {
-        float v[kGather];
+// One workgroup per heavy unit (a loop when there are more heavy units than
+// workgroups): lane l sums the unit's entries l, l + 256, ... in order, in
+// batches of 8 independent loads, then a fixed butterfly per wave and the
+// four waves in order.  C2: at most 2 x 2 domains cover a unit (STEP >= n),
+// and their list bounds are loaded together.
+template <int N, int UNIT, bool C2>
+__device__ __forceinline__ void heavy_body(const StepArgs &a, int hb) {
+  __shared__ float red[4];
+  const Geo &g = a.g;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the first unit's records are read with the count (hb < nb_hv <= U keeps
+  // them inside the arrays; they are used only if hb < nh)
+  const int u_first = a.heavy[hb];
+  int4 b_first, l_first;
+  if constexpr (C2) {
+    b_first = a.hbeg[hb];
+    l_first = a.hlen[hb];
+  }
+  const int nh = *a.nheavy;
+  for (int h = hb; h < nh; h += a.nb_hv) {
+    const int u = h == hb ? u_first : a.heavy[h];
+    const int qy = (u / a.UW) * UNIT, qx = (u % a.UW) * UNIT;
+    int dy0, dy1, dx0, dx1;
+    cover(g, qy, qx, dy0, dy1, dx0, dx1);
+    float acc = 0.0f;
+    if constexpr (C2) {
+      const int4 B = h == hb ? b_first : a.hbeg[h];
+      const int4 Lq = h == hb ? l_first : a.hlen[h];
+      const int beg[4] = {B.x, B.y, B.z, B.w};
+      const int len[4] = {Lq.x, Lq.y, Lq.z, Lq.w};
+      int cy[4], cx[4];
 #pragma unroll
-        for (int u = 0; u < kGather; ++u)
-          v[u] = sb + u < s1 ? partial[(size_t)(sb + u) * K + cell] : 0.0f;
-#pragma unroll
-        for (int u = 0; u < kGather; ++u)
-          if (sb + u < s1) acc += v[u];
+      for (int q = 0; q < 4; ++q) {
+        cy[q] = (qy - (dy0 + (q >> 1)) * g.step) >> 1;
+        cx[q] = (qx - (dx0 + (q & 1)) * g.step) >> 1;
       }
+      const int c1 = len[0], c2 = c1 + len[1], c3 = c2 + len[2];
+      const int E = c3 + len[3];
+      for (int f0 = threadIdx.x; f0 < E; f0 += 256 * 8) {
+        int pkv[8], qv[8];
+        float wv8[8], gv[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int f = f0 + 256 * j;
+          const int q = (f >= c1) + (f >= c2) + (f >= c3);
+          const int b = q == 0 ? beg[0] : q == 1 ? beg[1] : q == 2 ? beg[2] : beg[3];
+          const int o = q == 0 ? 0 : q == 1 ? c1 : q == 2 ? c2 : c3;
+          const int e = min(max(b + f - o, 0), g.R - 1);
+          qv[j] = q;
+          pkv[j] = f < E ? a.pk[e] : 0;
+          wv8[j] = f < E ? a.pw[e] : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int q = qv[j];
+          const int y = q == 0 ? cy[0] : q == 1 ? cy[1] : q == 2 ? cy[2] : cy[3];
+          const int x = q == 0 ? cx[0] : q == 1 ? cx[1] : q == 2 ? cx[2] : cx[3];
+          gv[j] = f0 + 256 * j < E ? a.gnext[entry_pixel<N>(g, pkv[j], y, x)]
+                                   : 0.0f;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          if (f0 + 256 * j < E) acc = fmaf(wv8[j], gv[j], acc);
+      }
+    } else {
+      for (int dy = dy0; dy <= dy1; ++dy)
+        for (int dx = dx0; dx <= dx1; ++dx) {
+          const int d = dy * g.NX + dx;
+          const int b = a.off[d], L = a.off[d + 1] - b;
+          const int y = (qy - dy * g.step) >> 1, x = (qx - dx * g.step) >> 1;
+          for (int f0 = threadIdx.x; f0 < L; f0 += 256 * 8) {
+            int pkv[8];
+            float wv8[8], gv[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int f = f0 + 256 * j;
+              const int e = min(max(b + f, 0), g.R - 1);
+              pkv[j] = f < L ? a.pk[e] : 0;
+              wv8[j] = f < L ? a.pw[e] : 0.0f;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              gv[j] = f0 + 256 * j < L
+                          ? a.gnext[entry_pixel<N>(g, pkv[j], y, x)]
+                          : 0.0f;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              if (f0 + 256 * j < L) acc = fmaf(wv8[j], gv[j], acc);
+          }
+        }
     }
-  gout[q] = acc;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+    if (lane == 0) red[wv] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      put_unit<UNIT>(g, a.gout, qy, qx, (red[0] + red[1]) + (red[2] + red[3]));
+    __syncthreads();
+  }
 }
 
-template <int N>
-__global__ __launch_bounds__(256) void k_grad_x(Geo g, const int32_t *segoff,
-                                                const float *partial,
-                                                float *gout) {
-  grad_x_body<N>(g, segoff, partial, gout, blockIdx.x);
+// One lane per light unit: its kEll slots (one load per slot pair), then
+// g_{t+1} at the slots' pixels, summed in slot order.
+template <int N, int UNIT>
+__device__ __forceinline__ void light_body(const StepArgs &a, int lb) {
+  const int u = lb * 256 + threadIdx.x;
+  if (u >= a.U) return;
+  const int4 *e4 = (const int4 *)a.ell;
+  int4 sl[kEll / 2];
+#pragma unroll
+  for (int q = 0; q < kEll / 2; ++q) sl[q] = e4[(size_t)q * a.U + u];
+  if (sl[0].x == -2) return;  // a heavy unit
+  float gv[kEll];
+  const int last = a.g.H * a.g.W - 1;  // entries are pixels of the image
+#pragma unroll
+  for (int q = 0; q < kEll / 2; ++q) {
+    gv[2 * q] = sl[q].x >= 0 ? a.gnext[min(sl[q].x, last)] : 0.0f;
+    gv[2 * q + 1] = sl[q].z >= 0 ? a.gnext[min(sl[q].z, last)] : 0.0f;
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int q = 0; q < kEll / 2; ++q) {
+    if (sl[q].x >= 0) acc = fmaf(__int_as_float(sl[q].y), gv[2 * q], acc);
+    if (sl[q].z >= 0) acc = fmaf(__int_as_float(sl[q].w), gv[2 * q + 1], acc);
+  }
+  const int qy = (u / a.UW) * UNIT, qx = (u % a.UW) * UNIT;
+  put_unit<UNIT>(a.g, a.gout, qy, qx, acc);
+}
+
+// One reverse step in one launch: workgroups [0, nb_hv) take the heavy
+// units, the next nb_so form dL/ds and dL/do, the rest the light units (the
+// unit parts only while g_t is needed, t > 0).
+template <int N, int UNIT, bool C2>
+__global__ __launch_bounds__(256) void k_adj_step(StepArgs a) {
+  const int b = blockIdx.x;
+  if (b < a.nb_hv)
+    heavy_body<N, UNIT, C2>(a, b);
+  else if (b < a.nb_hv + a.nb_so)
+    grad_so_body<N>(a.g, a.domain, a.iso, a.x, a.gnext, a.grad_s, a.grad_o,
+                    a.first, b - a.nb_hv);
+  else
+    light_body<N, UNIT>(a, b - a.nb_hv - a.nb_so);
 }
 
 size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// Workspace of the adjoint: the table (built once per code set) and the
-// per-step buffers.
+// Workspace of the adjoint: the domain table (built once per set of
+// domains), the per-unit tables (again whenever s changes) and the two
+// gradient images.
 struct AdjWs {
-  int32_t *cnt, *off, *segoff, *key0, *val0, *key1, *val1, *hist, *base;
-  int2 *seg;
-  float *partial, *gbuf0, *gbuf1;
-  int32_t *list;  // points at val0 or val1 after the sort
-  int nbr, max_seg;
+  int32_t *off, *key0, *val0, *key1, *val1, *hist, *base, *pk, *heavy,
+      *nheavy;
+  float *pw, *gbuf0, *gbuf1;
+  int4 *hbeg, *hlen;  // heavy units' covering lists (at most 2 x 2 domains)
+  int2 *ell;
+  int32_t *srt;  // val0, val1 or the small sort's output
+  int nbr, unit, U, UW;
+  bool small;
   size_t total;
 };
 
@@ -449,37 +801,52 @@ AdjWs adj_layout(const Geo &g, void *ws) {
   const size_t HW = (size_t)g.H * g.W;
   AdjWs a;
   a.nbr = (g.R + 255) / 256;
-  a.max_seg = g.R + (g.R + kSeg - 1) / kSeg;  // non-empty domains <= R
+  a.unit = g.step % 2 == 0 ? 2 : 1;
+  a.UW = g.W / a.unit;
+  a.U = (g.H / a.unit) * a.UW;
+  a.small = g.R <= kSortR && g.ND <= kSortND;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
     off += a256(bytes);
     return ws ? (char *)ws + at : nullptr;
   };
-  a.cnt = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
   a.off = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
-  a.segoff = (int32_t *)take(sizeof(int32_t) * (g.ND + 1));
-  a.key0 = (int32_t *)take(sizeof(int32_t) * g.R);
   a.val0 = (int32_t *)take(sizeof(int32_t) * g.R);
-  a.key1 = (int32_t *)take(sizeof(int32_t) * g.R);
-  a.val1 = (int32_t *)take(sizeof(int32_t) * g.R);
-  a.hist = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
-  a.base = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
-  a.seg = (int2 *)take(sizeof(int2) * a.max_seg);
-  a.partial = (float *)take(sizeof(float) * (size_t)a.max_seg * g.K);
+  a.key0 = a.key1 = a.val1 = a.hist = a.base = nullptr;
+  if (!a.small) {
+    a.key0 = (int32_t *)take(sizeof(int32_t) * g.R);
+    a.key1 = (int32_t *)take(sizeof(int32_t) * g.R);
+    a.val1 = (int32_t *)take(sizeof(int32_t) * g.R);
+    a.hist = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
+    a.base = (int32_t *)take(sizeof(int32_t) * (256 * (size_t)a.nbr + 1));
+  }
+  a.pk = (int32_t *)take(sizeof(int32_t) * g.R);
+  a.pw = (float *)take(sizeof(float) * g.R);
+  a.heavy = (int32_t *)take(sizeof(int32_t) * a.U);
+  a.hbeg = (int4 *)take(sizeof(int4) * a.U);
+  a.hlen = (int4 *)take(sizeof(int4) * a.U);
+  a.nheavy = (int32_t *)take(sizeof(int32_t));
+  a.ell = (int2 *)take(sizeof(int2) * kEll * (size_t)a.U);
   a.gbuf0 = (float *)take(sizeof(float) * HW);
   a.gbuf1 = (float *)take(sizeof(float) * HW);
-  a.list = a.val0;
+  a.srt = a.val0;
   a.total = off;
   return a;
 }
 
-// Build the domain -> ranges table for these codes.
+// The domain -> ranges table for these domains (clears the heavy count).
 void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
                          hipStream_t st) {
+  if (a.small) {
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, g, domain,
+                       a.val0, a.off, a.nheavy);
+    a.srt = a.val0;
+    return;
+  }
   const int bs = 256;
   hipLaunchKernelGGL(k_rs_init, dim3((g.R + bs - 1) / bs), dim3(bs), 0, st, g,
-                     domain, a.key0, a.val0);
+                     domain, a.key0, a.val0, a.nheavy);
   int bits = 0;
   while ((1ll << bits) < (long long)g.ND) ++bits;
   int32_t *kin = a.key0, *vin = a.val0, *kout = a.key1, *vout = a.val1;
@@ -487,48 +854,127 @@ void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
     hipLaunchKernelGGL(k_rs_hist, dim3(a.nbr), dim3(256), 0, st, kin, g.R,
                        shift, a.hist);
     hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.hist, 256 * a.nbr,
-                       1, a.base);
+                       a.base);
     hipLaunchKernelGGL(k_rs_scatter, dim3(a.nbr), dim3(256), 0, st, kin, vin,
                        g.R, shift, a.base, kout, vout);
     std::swap(kin, kout);
     std::swap(vin, vout);
   }
-  a.list = vin;
+  a.srt = vin;
   hipLaunchKernelGGL(k_bounds, dim3((g.ND + 1 + bs - 1) / bs), dim3(bs), 0, st,
-                     g, kin, a.off, a.cnt);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a.cnt, g.ND, kSeg,
-                     a.segoff);
-  hipLaunchKernelGGL(k_seg_fill, dim3((a.max_seg + bs - 1) / bs), dim3(bs), 0,
-                     st, g, a.off, a.segoff, a.max_seg, a.seg);
+                     g, kin, a.off);
 }
 
-// The reverse steps, with the table already built.
+// The per-unit tables for the current s; with_units also writes the padding
+// and the heavy list (once per domain table).
 template <int N>
-void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
-                   const float *s, int iters, const float *traj,
-                   const float *grad_xT, float *grad_s, float *grad_o,
-                   const AdjWs &a, hipStream_t st) {
+void build_unit_tables(const Geo &g, const int32_t *domain,
+                       const uint8_t *iso, const float *s, const AdjWs &a,
+                       bool with_units, hipStream_t st) {
+  UnitArgs u;
+  u.g = g;
+  u.domain = domain;
+  u.srt = a.srt;
+  u.off = a.off;
+  u.iso = iso;
+  u.s = s;
+  u.ell = a.ell;
+  u.pk = a.pk;
+  u.heavy = a.heavy;
+  u.nheavy = a.nheavy;
+  u.hbeg = a.hbeg;
+  u.hlen = a.hlen;
+  u.pw = a.pw;
+  u.U = a.U;
+  u.UW = a.UW;
+  u.nbu = with_units ? (a.U + 255) / 256 : 0;
+  const long long ne = (long long)g.R * N * N;
+  const unsigned grid = (unsigned)(u.nbu + (ne + 255) / 256);
+  if (a.unit == 2)
+    hipLaunchKernelGGL((k_adj_units<N, 2>), dim3(grid), dim3(256), 0, st, u);
+  else
+    hipLaunchKernelGGL((k_adj_units<N, 1>), dim3(grid), dim3(256), 0, st, u);
+}
+
+// The reverse steps, with the tables built.
+template <int N, int UNIT, bool C2>
+void adjoint_steps_t(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                     int iters, const float *traj, const float *grad_xT,
+                     float *grad_s, float *grad_o, const AdjWs &a,
+                     hipStream_t st) {
   const size_t HW = (size_t)g.H * g.W;
-  const int bs = 256;
+  StepArgs p;
+  p.g = g;
+  p.domain = domain;
+  p.iso = iso;
+  p.grad_s = grad_s;
+  p.grad_o = grad_o;
+  p.off = a.off;
+  p.pk = a.pk;
+  p.heavy = a.heavy;
+  p.nheavy = a.nheavy;
+  p.hbeg = a.hbeg;
+  p.hlen = a.hlen;
+  p.pw = a.pw;
+  p.ell = a.ell;
+  p.U = a.U;
+  p.UW = a.UW;
+  p.nb_so = (int)(((long long)g.R * N * N + 255) / 256);
+  const int nb_lt = (a.U + 255) / 256;
+  const int nb_hv = std::min(a.U, 256);
   const float *gnext = grad_xT;
   float *bufs[2] = {a.gbuf0, a.gbuf1};
   for (int t = iters - 1; t >= 0; --t) {
-    const float *x = traj + (size_t)t * HW;
-    const long long nso = (long long)g.R * N * N;
-    const int nb_so = (int)((nso + bs - 1) / bs);
-    // the segment partials feed g_t, needed only while t > 0
-    const long long np = t > 0 ? (long long)a.max_seg * N * N : 0;
-    const int nb_sp = (int)((np + bs - 1) / bs);
-    hipLaunchKernelGGL((k_adj_step<N>), dim3((unsigned)(nb_so + nb_sp)),
-                       dim3(bs), 0, st, g, domain, iso, x, gnext, grad_s,
-                       grad_o, t == iters - 1 ? 1 : 0, nb_so,
-                       a.segoff + g.ND, a.seg, a.list, s, a.partial);
-    if (t > 0) {
-      float *gout = bufs[t & 1];
-      hipLaunchKernelGGL((k_grad_x<N>), dim3((HW + bs - 1) / bs), dim3(bs), 0,
-                         st, g, a.segoff, a.partial, gout);
-      gnext = gout;
-    }
+    p.x = traj + (size_t)t * HW;
+    p.gnext = gnext;
+    p.gout = bufs[t & 1];
+    p.first = t == iters - 1 ? 1 : 0;
+    // g_t is needed only while t > 0
+    p.nb_hv = t > 0 ? nb_hv : 0;
+    const int nb = p.nb_hv + p.nb_so + (t > 0 ? nb_lt : 0);
+    hipLaunchKernelGGL((k_adj_step<N, UNIT, C2>), dim3((unsigned)nb),
+                       dim3(256), 0, st, p);
+    gnext = p.gout;
+  }
+}
+
+template <int N>
+void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
+                   int iters, const float *traj, const float *grad_xT,
+                   float *grad_s, float *grad_o, const AdjWs &a,
+                   hipStream_t st) {
+  const bool c2 = g.step >= N;
+  if (a.unit == 2) {
+    if (c2)
+      adjoint_steps_t<N, 2, true>(g, domain, iso, iters, traj, grad_xT, grad_s,
+                                  grad_o, a, st);
+    else
+      adjoint_steps_t<N, 2, false>(g, domain, iso, iters, traj, grad_xT,
+                                   grad_s, grad_o, a, st);
+  } else {
+    if (c2)
+      adjoint_steps_t<N, 1, true>(g, domain, iso, iters, traj, grad_xT, grad_s,
+                                  grad_o, a, st);
+    else
+      adjoint_steps_t<N, 1, false>(g, domain, iso, iters, traj, grad_xT,
+                                   grad_s, grad_o, a, st);
+  }
+}
+
+// Tables for these codes and s, then the reverse steps.
+void adjoint(const Geo &g, const int32_t *domain, const uint8_t *iso,
+             const float *s, int iters, const float *traj,
+             const float *grad_xT, float *grad_s, float *grad_o, AdjWs &a,
+             bool table_built, hipStream_t st) {
+  if (!table_built) build_adjoint_table(g, domain, a, st);
+  if (g.n == 8) {
+    build_unit_tables<8>(g, domain, iso, s, a, !table_built, st);
+    adjoint_steps<8>(g, domain, iso, iters, traj, grad_xT, grad_s, grad_o, a,
+                     st);
+  } else {
+    build_unit_tables<4>(g, domain, iso, s, a, !table_built, st);
+    adjoint_steps<4>(g, domain, iso, iters, traj, grad_xT, grad_s, grad_o, a,
+                     st);
   }
 }
 
@@ -732,13 +1178,8 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
     return hipGetLastError();
   }
   AdjWs a = adj_layout(g, ws);
-  build_adjoint_table(g, domain, a, st);
-  if (g.n == 8)
-    adjoint_steps<8>(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o,
-                     a, st);
-  else
-    adjoint_steps<4>(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o,
-                     a, st);
+  adjoint(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o, a, false,
+          st);
   return hipGetLastError();
 }
 
@@ -788,18 +1229,14 @@ hipError_t launch_refine(const Geo &g, const int32_t *domain, const uint8_t *iso
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, st, part, nb,
                        (long long)HW, loss, step);
     if (step == steps) break;
-    // the codes' domains do not change: the table is built once
     if (iters == 0) {
       zero_grads(g, gso, gso + g.R, st);
     } else {
-      if (!table_built) build_adjoint_table(g, domain, adj, st);
+      // the domains do not change: their table is built once; the
+      // per-unit tables follow s
+      adjoint(g, domain, iso, s, iters, traj, gx, gso, gso + g.R, adj,
+              table_built, st);
       table_built = true;
-      if (g.n == 8)
-        adjoint_steps<8>(g, domain, iso, s, iters, traj, gx, gso, gso + g.R,
-                         adj, st);
-      else
-        adjoint_steps<4>(g, domain, iso, s, iters, traj, gx, gso, gso + g.R,
-                         adj, st);
     }
     p1 *= b1;
     p2 *= b2;

@@ -181,14 +181,22 @@ def test_backward_matches_fp64_gradient_and_fd():
     assert rel(gs[idx], np.array(fs)) <= 1e-3 and rel(go[idx], np.array(fo)) <= 1e-3
 
 
-@pytest.mark.parametrize("case", ["one_domain", "few_domains", "ragged_rect"])
+@pytest.mark.parametrize("case", ["one_domain", "few_domains", "ragged_rect",
+                                  "odd_step", "n8_step4", "n8_step8",
+                                  "many_ranges"])
 def test_backward_shared_domains(case):
-    """Many ranges on one domain (long lists, many segments) and domain
-    counts that need one, two and three radix passes."""
+    """Many ranges on one domain (heavy units, each summed by a workgroup),
+    the in-LDS sort (up to 8,192 ranges and 16,384 domains) and the radix
+    sort beyond it, 2x2-cell units (even STEP) and pixel units (odd STEP),
+    with at most 2 x 2 covering domains (STEP >= n) or more."""
     rng = np.random.default_rng(41)
-    H, W, n, step = {"one_domain": (64, 48, 4, 4),      # 165 domains: one pass
-                     "few_domains": (128, 96, 4, 2),    # 2,745 domains: two passes
-                     "ragged_rect": (264, 272, 4, 1),   # 68,105 domains: three passes
+    H, W, n, step = {"one_domain": (64, 48, 4, 4),      # 165 domains
+                     "few_domains": (128, 96, 4, 2),    # 2,745 domains
+                     "ragged_rect": (264, 272, 4, 1),   # 68,105 domains: radix sort
+                     "odd_step": (72, 64, 4, 5),        # pixel units, 2 x 2 cover
+                     "n8_step4": (128, 128, 8, 4),      # 8x8 ranges, 4 x 4 cover
+                     "n8_step8": (128, 96, 8, 8),       # 8x8 ranges, 2 x 2 cover
+                     "many_ranges": (512, 512, 4, 8),   # 16,384 ranges: radix sort
                      }[case]
     p = F.Params(H, W, 8, n, step)
     R, ND = F.query(p)[:2]
@@ -198,7 +206,7 @@ def test_backward_shared_domains(case):
         d = rng.choice(np.array([0, 5, ND - 1], dtype=np.int32), R)
     else:
         d = rng.integers(0, ND, R).astype(np.int32)
-        d[: R // 3] = 7                           # one long list among many short
+        d[: R // 3] = min(7, ND - 1)              # one long list among many short
     k = rng.integers(0, 8, R).astype(np.uint8)
     s = rng.uniform(-0.8, 0.8, R)
     o = rng.uniform(-40, 200, R)
