@@ -158,6 +158,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.pix_a = 0;
   g.full = p->full_search;
   g.i8 = p->method == FIC_METHOD_MFMA_I8 && g.bits == 12;
+  g.ident = 0;
   g.ctr = p->method == FIC_METHOD_MFMA && g.bits == 8 && n != 16;
   return FIC_OK;
 }
@@ -328,6 +329,9 @@ int encode_launch(const fic_params *p, Geo g, const void *image,
   // the (8-byte aligned) image
   g.pix_a = p->method == FIC_METHOD_MFMA && g.bits == 8 && g.n == 8 &&
             ((uintptr_t)image & 7) == 0;
+  // every range against every domain with no padding slots: the work lists
+  // are the identity, written by the preparation
+  g.ident = g.full && !rmask && g.R == g.R_pad ? 1 : 0;
   timing_mark(0, s);
   hipError_t e = launch_prep(g, image, b, s);
   if (e != hipSuccess) return hip_fail(e, "prep");
@@ -337,8 +341,10 @@ int encode_launch(const fic_params *p, Geo g, const void *image,
   const Tune t = resolve_tune(g, p->method);
   // both searches walk the lists of range slots and domain columns they
   // visit (all of them, or those with variance), built here in order
-  e = launch_compact(g, b, s);
-  if (e != hipSuccess) return hip_fail(e, "compact");
+  if (!g.ident) {
+    e = launch_compact(g, b, s);
+    if (e != hipSuccess) return hip_fail(e, "compact");
+  }
   e = launch_seed_dense(g, b, t.seed_blocks, s);
   if (e != hipSuccess) return hip_fail(e, "seed");
   timing_mark(2, s);

@@ -33,6 +33,10 @@ struct Geo {
                      //   too (0: they are left out; their outcome is fixed)
   int i8;            // 1: 12-bit operands also as int8 hi/lo planes (the
                      //   int8 matrix-core search)
+  int ident;         // 1: the searched range slots and domain columns are
+                     //   all of them, in order (a full search of every range
+                     //   with no padding slots): the preparation writes the
+                     //   lists and their lengths, with no compaction pass
   int ctr;           // 1: 8-bit matrix-core operands (4x4, 8x8 ranges) are
                      //   centred on each block's rounded mean:
                      //   A - round(SA/K) and b - round(Sb/K), exact FP16

@@ -119,6 +119,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     b.col_rec[col] = rec;
     // searched: a domain with variance, or any domain in a full search
     b.col_flag[col] = d >= 0 && (g.full || dp != __builtin_inff()) ? 1 : 0;
+    if (g.ident) b.act_col[col] = (int)col;  // columns 0 .. ND - 1 are real
   }
   __syncthreads();
   if (threadIdx.x == 0) b.flat_min[bid] = s_flat;
@@ -220,6 +221,7 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
                          (g.full || (Acc)K * Sbb - Sb * Sb != 0)
                      ? 1
                      : 0;
+  if (g.ident) b.act_slot[r] = r;  // every slot holds a real range
   if (ri >= g.R) {
     b.best[r] = ~0ull;
     return;
@@ -234,6 +236,10 @@ __device__ __forceinline__ void prep_ranges_body(const Geo &g, const Pix *img,
 template <typename Pix, int N>
 __global__ __launch_bounds__(256) void k_prep(Geo g, const Pix *img,
                                               EncBufs b) {
+  if (g.ident && blockIdx.x == 0 && threadIdx.x == 0) {
+    b.n_act[0] = g.R_pad;
+    b.n_act[1] = g.ND;
+  }
   if ((int)blockIdx.x < g.n_dwg) {
     prep_domains_body<Pix, N>(g, img, b, blockIdx.x);
   } else if (g.pix_a || N == 16) {
