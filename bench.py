@@ -92,7 +92,7 @@ def pmc_summary(fetch_dir, write_dir):
             continue
         f = sum(fetch.get(name, [0])) / max(1, len(fetch.get(name, [])))
         w = sum(write.get(name, [0])) / max(1, len(write.get(name, [])))
-        short = name.split("(anonymous namespace)::")[-1].split("(")[0]
+        short = name.split("(anonymous namespace)::", 1)[-1].split("(")[0]
         lines.append(f"| {short} | {len(fetch.get(name, []))} | {f:.1f} | {w:.1f} | "
                      f"{f * sf * 1024 / 1e6:.2f} | {w * sw * 1024 / 1e6:.2f} |")
         if short == SEARCH_KERNEL:
@@ -152,7 +152,7 @@ def trace_summary(stats_dir, command):
              "Command (from /tmp, TMPDIR=/tmp):", "", "    " + command, "",
              "| kernel | calls | average us | total us |", "|---|---|---|---|"]
     for name, calls, avg, tot in rows:
-        short = name.split("(anonymous namespace)::")[-1].split("(")[0]
+        short = name.split("(anonymous namespace)::", 1)[-1].split("(")[0]
         lines.append(f"| {short} | {calls} | {avg:.2f} | {tot:.1f} |")
     return "\n".join(lines) + "\n"
 
