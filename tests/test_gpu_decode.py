@@ -183,7 +183,8 @@ def test_backward_matches_fp64_gradient_and_fd():
 
 @pytest.mark.parametrize("case", ["one_domain", "few_domains", "ragged_rect",
                                   "odd_step", "n8_step4", "n8_step8",
-                                  "many_ranges"])
+                                  "many_ranges", "single_domain_image",
+                                  "one_domain_column"])
 def test_backward_shared_domains(case):
     """Many ranges on one domain (heavy units, each summed by a workgroup),
     the in-LDS sort (up to 8,192 ranges and 16,384 domains) and the radix
@@ -197,6 +198,8 @@ def test_backward_shared_domains(case):
                      "n8_step4": (128, 128, 8, 4),      # 8x8 ranges, 4 x 4 cover
                      "n8_step8": (128, 96, 8, 8),       # 8x8 ranges, 2 x 2 cover
                      "many_ranges": (512, 512, 4, 8),   # 16,384 ranges: radix sort
+                     "single_domain_image": (8, 8, 4, 4),  # one domain, no sort pass
+                     "one_domain_column": (16, 8, 4, 3),   # 1 x 3 domains, pixel units
                      }[case]
     p = F.Params(H, W, 8, n, step)
     R, ND = F.query(p)[:2]
