@@ -227,10 +227,12 @@ __device__ __forceinline__ void load_column(const EncBufs &b, int ci, int h,
   if (ci < 0) nsd.sc = __builtin_inff();
 }
 
-// Column of searched block cb for lane column cl (-1 past the list).
+// Column of searched block cb for lane column cl (-1 past the list); with
+// identity lists (ident) the list entry is its own index and is not read.
 __device__ __forceinline__ int column_of(const EncBufs &b, int nD, int cb,
-                                         int cl) {
+                                         int cl, int ident) {
   const int j = cb * 32 + cl;
+  if (ident) return j < nD ? j : -1;
   return j < nD ? gld(&b.act_col[j]) : -1;
 }
 
@@ -252,7 +254,7 @@ __device__ __forceinline__ void sweep_block(
     // the next block (its column index came a block earlier) and the index
     // of the block after it
     load_column<K, FRAG>(b, w.ci_next, w.h, bn, nsd);
-    w.ci_next = cb + 2 < c1 ? column_of(b, w.nD, cb + 2, w.cl) : -1;
+    w.ci_next = cb + 2 < c1 ? column_of(b, w.nD, cb + 2, w.cl, g.ident) : -1;
   }
   // keep the prefetch ahead of the matrix-core work
   __builtin_amdgcn_sched_barrier(0);
@@ -412,8 +414,8 @@ __device__ __forceinline__ void seed_blocks(const Geo &g, const EncBufs &b,
     const ColRec cur = sd;
     if (w.h == 0) col_tab[blk * 32 + w.cl] = cur;
     if (blk + 1 < nb)
-      load_column<K, FRAG>(b, column_of(b, w.nD, c0 + blk + 1, w.cl), w.h,
-                           bf, sd);
+      load_column<K, FRAG>(
+          b, column_of(b, w.nD, c0 + blk + 1, w.cl, g.ident), w.h, bf, sd);
     // flat domains and padding columns (sqrt(D') = +inf) score 0 and take no
     // part (as does a candidate with H = 0)
     const float idp =
@@ -594,7 +596,7 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
   // the wave's range slots, their keys and sums; the first two columns
   if (w.lane < kWaveRanges) {
     const int j = w.wr0 + w.lane;
-    const int sl = j < nA ? gld(&b.act_slot[j]) : -1;
+    const int sl = j < nA ? (g.ident ? j : gld(&b.act_slot[j])) : -1;
     w.slots[w.lane] = sl;
     double sb = 0.0, sbb = 0.0;
     if (sl >= 0) {
@@ -605,8 +607,8 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
     w.best[w.lane] = w.gsnap;
     w.rstat[w.lane] = double2{sb, sbb};
   }
-  const int ci0 = column_of(b, nD, c0, w.cl);
-  w.ci_next = c0 + 1 < c1 ? column_of(b, nD, c0 + 1, w.cl) : -1;
+  const int ci0 = column_of(b, nD, c0, w.cl, g.ident);
+  w.ci_next = c0 + 1 < c1 ? column_of(b, nD, c0 + 1, w.cl, g.ident) : -1;
   half8 bA[KS], bB[KS];  // two buffers for the streamed domain operand
   ColRec sdA, sdB;
   load_column<K, FRAG>(b, ci0, w.h, bA, sdA);
