@@ -473,6 +473,13 @@ def main():
         bsv, bov = bsv.contiguous(), bov.contiguous()
         ms_bdec = mean_ms(torch, dev, lambda: F.decode_batch(bd, bk, bsv, bov, p5, T, 128.0), 10, 2)
         bdec_bytes = NB * dec_bytes
+        # the same 64 images' adjoint: one launch per reverse step for the batch
+        btraj = F.decode_batch(bd, bk, bsv, bov, p5, T, 128.0)
+        bgx = (torch.randn((NB, 256, 256), device=dev) * (2.0 / HW)).contiguous()
+        ms_bbwd = mean_ms(torch, dev, lambda: F.decode_backward_batch(bd, bk, bsv, bov, btraj, bgx,
+                                                                      p5), 10, 2)
+        bbwd_bytes = NB * bwd_bytes
+        del btraj, bgx
         del dbat, dimgs
         x0 = tr5[-1].double().cpu().numpy()
         ref5 = img5.astype(np.float64)
@@ -501,6 +508,11 @@ def main():
                              "hbm_frac": bdec_bytes / (ms_bdec / 1e3) / HBM_PEAK,
                              "note": "64 different 256x256 slices with their own codes, "
                                      "one launch per iteration for the batch"},
+            "batch_adjoint": {"images": NB, "ms": ms_bbwd,
+                              "gbps": bbwd_bytes / (ms_bbwd / 1e3) / 1e9,
+                              "hbm_frac": bbwd_bytes / (ms_bbwd / 1e3) / HBM_PEAK,
+                              "note": "the same 64 slices' adjoint (tables built per call), "
+                                      "one launch per reverse step for the batch"},
             "refine": {"steps": 50, "lr_s": 5e-3, "lr_o": 0.5, "ms": ms_ref,
                        "loss_first": float(loss[0]), "loss_last": float(loss[-1]),
                        "psnr_db": psnr(xr, ref5, 255.0), "psnr_requantised_db": psnr(xq, ref5, 255.0)}}

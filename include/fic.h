@@ -261,6 +261,32 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
                         size_t ws_bytes, void *stream);
 
 /*
+ * fic_decode_backward_batch -- fic_decode_backward of n_images images that
+ * share `p`, each with its own codes, one launch per reverse step for the
+ * whole batch.  Codes, dL/ds and dL/do are packed image after image
+ * (b * n_ranges + r); traj is fic_decode_batch's output (image b at
+ * traj + b * (iters + 1) * height * width); grad_xT holds image b's dL/dx_T
+ * at grad_xT + b * height * width.  Each image's result is bitwise the
+ * single call's.
+ *   workspace  device, >= fic_decode_backward_batch_workspace bytes,
+ *              256-byte aligned
+ * Errors: FIC_E_INVALID (null pointers, iters < 0, n_images < 1, workspace
+ * not 256-byte aligned), FIC_E_UNSUPPORTED (more than 65535 images or 2^31
+ * pixels in all, 16x16 ranges, more than 8192 ranges or 16384 domains per
+ * image), FIC_E_WORKSPACE.
+ */
+int fic_decode_backward_batch(const fic_params *p, int32_t n_images,
+                              const int32_t *domain, const uint8_t *iso,
+                              const float *s, const float *o, int32_t iters,
+                              const float *traj, const float *grad_xT,
+                              float *grad_s, float *grad_o, void *workspace,
+                              size_t ws_bytes, void *stream);
+
+/* Workspace bytes fic_decode_backward_batch needs (host only). */
+int fic_decode_backward_batch_workspace(const fic_params *p,
+                                        int32_t n_images, size_t *bytes);
+
+/*
  * fic_refine -- adjust s and o of fixed codes to lower the error of their
  * decoded attractor against the image (the collage theorem of Section III
  * bounds that error; here it is minimised directly).  Domain and transform

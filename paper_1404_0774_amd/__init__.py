@@ -5,6 +5,7 @@ The compute path lives in libfic.so (hand-written HIP for gfx950, built by
 ABI.  PyTorch provides device memory and streams.
 """
 from ._lib import (FicError, Params, encode, decode, decode_batch, decode_scaled, decode_backward,
+                   decode_backward_batch,
                    query,
                    dequantize, FicDecode, lib, METHOD_MFMA, METHOD_DIRECT,
                    METHOD_MFMA_I8,
@@ -14,6 +15,7 @@ from ._lib import (FicError, Params, encode, decode, decode_batch, decode_scaled
                    encode_quadtree)
 
 __all__ = ["FicError", "Params", "encode", "decode", "decode_batch", "decode_scaled", "decode_backward",
+           "decode_backward_batch",
            "query",
            "dequantize", "FicDecode", "lib", "METHOD_MFMA", "METHOD_DIRECT",
            "METHOD_MFMA_I8",

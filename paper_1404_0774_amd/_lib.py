@@ -119,6 +119,11 @@ def lib():
         L.fic_stream_unpack.argtypes = [P, vp, sz, vp, vp, vp, vp, vp]
         L.fic_decode_backward.restype = ctypes.c_int
         L.fic_decode_backward.argtypes = [P, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.fic_decode_backward_batch.restype = ctypes.c_int
+        L.fic_decode_backward_batch.argtypes = [P, i32, vp, vp, vp, vp, i32, vp, vp, vp, vp, vp,
+                                                sz, vp]
+        L.fic_decode_backward_batch_workspace.restype = ctypes.c_int
+        L.fic_decode_backward_batch_workspace.argtypes = [P, i32, ctypes.POINTER(sz)]
         PP = ctypes.POINTER(_Params)
         L.fic_batch_query.restype = ctypes.c_int
         L.fic_batch_query.argtypes = [PP, i32, ctypes.POINTER(sz)]
@@ -473,6 +478,31 @@ def decode_backward(domain, iso, s, o, traj, grad_xT, p: Params):
                                      _dev_ptr(g, torch.float32, "grad_xT"), gs.data_ptr(),
                                      go.data_ptr(), ctypes.c_void_p(ws), ctypes.c_size_t(bw),
                                      _stream(dev)))
+    del keep
+    return gs, go
+
+
+def decode_backward_batch(domain, iso, s, o, traj, grad_xT, p: Params):
+    """dL/ds, dL/do of B decoders of one geometry (codes (B, n_ranges), traj
+    (B, iters+1, H, W) as decode_batch returns, grad_xT (B, H, W)); returns
+    two (B, n_ranges) tensors."""
+    B = domain.shape[0]
+    iters = traj.shape[1] - 1
+    dev = s.device
+    nr = query(p)[0]
+    cp = p.c()
+    nbytes = ctypes.c_size_t()
+    _check(lib().fic_decode_backward_batch_workspace(ctypes.byref(cp), B, ctypes.byref(nbytes)))
+    gs = torch.empty((B, nr), dtype=torch.float32, device=dev)
+    go = torch.empty((B, nr), dtype=torch.float32, device=dev)
+    keep, ws = _workspace(nbytes.value, dev)
+    g = grad_xT.contiguous()
+    _check(lib().fic_decode_backward_batch(
+        ctypes.byref(cp), B, _dev_ptr(domain, torch.int32, "domain"),
+        _dev_ptr(iso, torch.uint8, "iso"), _dev_ptr(s, torch.float32, "s"),
+        _dev_ptr(o, torch.float32, "o"), iters, _dev_ptr(traj, torch.float32, "traj"),
+        _dev_ptr(g, torch.float32, "grad_xT"), gs.data_ptr(), go.data_ptr(),
+        ctypes.c_void_p(ws), nbytes, _stream(dev)))
     del keep
     return gs, go
 

@@ -560,6 +560,56 @@ int fic_decode_backward(const fic_params *p, const int32_t *domain,
   return ok();
 }
 
+int fic_decode_backward_batch_workspace(const fic_params *p,
+                                        int32_t n_images, size_t *bytes) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!bytes) return fail(FIC_E_INVALID, "bytes is NULL");
+  if (n_images < 1) return fail(FIC_E_INVALID, "n_images %d < 1", n_images);
+  *bytes = decode_backward_batch_ws_bytes(g, n_images);
+  return ok();
+}
+
+int fic_decode_backward_batch(const fic_params *p, int32_t n_images,
+                              const int32_t *domain, const uint8_t *iso,
+                              const float *s, const float *o, int32_t iters,
+                              const float *traj, const float *grad_xT,
+                              float *grad_s, float *grad_o, void *workspace,
+                              size_t ws_bytes, void *stream) {
+  Geo g;
+  int st = make_geo(p, g, /*for_encode=*/false);
+  if (st) return st;
+  if (!domain || !iso || !s || !o || !traj || !grad_xT || !grad_s || !grad_o ||
+      !workspace)
+    return fail(FIC_E_INVALID, "null pointer argument");
+  if (iters < 0) return fail(FIC_E_INVALID, "iters %d < 0", iters);
+  if (n_images < 1) return fail(FIC_E_INVALID, "n_images %d < 1", n_images);
+  if (((uintptr_t)workspace) & 255)
+    return fail(FIC_E_INVALID, "workspace is not 256-byte aligned");
+  if (n_images > 65535)
+    return fail(FIC_E_UNSUPPORTED, "n_images %d > 65535", n_images);
+  if (g.n == 16)
+    return fail(FIC_E_UNSUPPORTED, "the adjoint takes 4x4 or 8x8 ranges");
+  if ((long long)g.H * g.W * n_images > (1ll << 31))
+    return fail(FIC_E_UNSUPPORTED, "%d images of %dx%d exceed 2^31 pixels",
+                n_images, g.H, g.W);
+  if (!decode_backward_batch_ok(g))
+    return fail(FIC_E_UNSUPPORTED,
+                "the batched adjoint takes up to 8192 ranges and 16384 "
+                "domains per image");
+  const size_t need = decode_backward_batch_ws_bytes(g, n_images);
+  if (ws_bytes < need)
+    return fail(FIC_E_WORKSPACE, "workspace %zu bytes < %zu needed", ws_bytes,
+                need);
+  (void)o;
+  hipError_t e = launch_decode_backward_batch(
+      g, n_images, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o,
+      workspace, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(e, "decode_backward_batch");
+  return ok();
+}
+
 int fic_refine_workspace(const fic_params *p, int32_t iters, size_t *bytes) {
   Geo g;
   int st = make_geo(p, g, /*for_encode=*/false);

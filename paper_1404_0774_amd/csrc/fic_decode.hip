@@ -169,6 +169,12 @@ __global__ void k_fill_f32(float *p, long long n, float v) {
   if (i < n) p[i] = v;
 }
 
+// Pointer p moved by `bytes` (per-image offsets of batched calls).
+template <class T>
+__device__ __forceinline__ T *bump(T *p, long long bytes) {
+  return reinterpret_cast<T *>(reinterpret_cast<uintptr_t>(p) + bytes);
+}
+
 // --- the domain -> ranges table --------------------------------------------
 //
 // srt[e], e < R: the ranges sorted by domain, in increasing range order within
@@ -326,10 +332,13 @@ __device__ __forceinline__ void suffix_min_off(const int *st, int n1, int per,
     if (q < per && c0 + q < n1) off[c0 + q] = min(sv[q], later);
 }
 
+// Batches: image blockIdx.y reads its codes at domain + y R and writes its
+// table ws_stride bytes after the previous image's.
 __global__ __launch_bounds__(1024) void k_sort_small(Geo g,
                                                      const int32_t *domain,
                                                      int32_t *srt, int32_t *off,
-                                                     int32_t *nheavy) {
+                                                     int32_t *nheavy,
+                                                     long long ws_stride) {
   __shared__ uint32_t kb[2][kSortR];
   __shared__ int st[kSortND + 1];  // first sorted position of each domain
   __shared__ int cnt[16 * 64];     // [wave][digit], then the digits' bases
@@ -337,6 +346,10 @@ __global__ __launch_bounds__(1024) void k_sort_small(Geo g,
   __shared__ int wtot[16];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int R = g.R;
+  domain += (size_t)blockIdx.y * R;
+  srt = bump(srt, blockIdx.y * ws_stride);
+  off = bump(off, blockIdx.y * ws_stride);
+  nheavy = bump(nheavy, blockIdx.y * ws_stride);
   if (t == 0) *nheavy = 0;
   msk[t] = 0;
   {
@@ -471,6 +484,7 @@ struct UnitArgs {
   int4 *hbeg, *hlen;
   float *pw;
   int U, UW, nbu;
+  long long ws_stride;  // bytes between images' tables (batches)
 };
 
 // Workgroups [0, nbu): one thread per unit, padding or the heavy mark (these
@@ -481,6 +495,22 @@ struct UnitArgs {
 template <int N, int UNIT>
 __global__ __launch_bounds__(256) void k_adj_units(UnitArgs a) {
   const Geo &g = a.g;
+  if (blockIdx.y > 0) {  // image blockIdx.y of a batch
+    const long long wb = blockIdx.y * a.ws_stride;
+    const size_t rb = (size_t)blockIdx.y * g.R;
+    a.domain += rb;
+    a.iso += rb;
+    a.s += rb;
+    a.srt = bump(a.srt, wb);
+    a.off = bump(a.off, wb);
+    a.ell = bump(a.ell, wb);
+    a.pk = bump(a.pk, wb);
+    a.heavy = bump(a.heavy, wb);
+    a.nheavy = bump(a.nheavy, wb);
+    a.hbeg = bump(a.hbeg, wb);
+    a.hlen = bump(a.hlen, wb);
+    a.pw = bump(a.pw, wb);
+  }
   if ((int)blockIdx.x < a.nbu) {
     const int u = blockIdx.x * 256 + threadIdx.x;
     if (u >= a.U) return;
@@ -611,6 +641,9 @@ struct StepArgs {
   const float *pw;
   const int2 *ell;
   int first, nb_hv, nb_so, U, UW;
+  // batches: bytes between images' tables and between their g_{t+1}
+  // images, floats between their trajectories
+  long long ws_stride, gn_stride, x_stride;
 };
 
 // g_t over the unit whose top-left pixel is (qy, qx).
@@ -770,6 +803,25 @@ __device__ __forceinline__ void light_body(const StepArgs &a, int lb) {
 // unit parts only while g_t is needed, t > 0).
 template <int N, int UNIT, bool C2>
 __global__ __launch_bounds__(256) void k_adj_step(StepArgs a) {
+  if (blockIdx.y > 0) {  // image blockIdx.y of a batch
+    const long long wb = blockIdx.y * a.ws_stride;
+    const size_t rb = (size_t)blockIdx.y * a.g.R;
+    a.domain += rb;
+    a.iso += rb;
+    a.grad_s += rb;
+    a.grad_o += rb;
+    a.x += (size_t)blockIdx.y * a.x_stride;
+    a.gnext = bump(a.gnext, blockIdx.y * a.gn_stride);
+    a.gout = bump(a.gout, wb);
+    a.off = bump(a.off, wb);
+    a.pk = bump(a.pk, wb);
+    a.heavy = bump(a.heavy, wb);
+    a.nheavy = bump(a.nheavy, wb);
+    a.hbeg = bump(a.hbeg, wb);
+    a.hlen = bump(a.hlen, wb);
+    a.pw = bump(a.pw, wb);
+    a.ell = bump(a.ell, wb);
+  }
   const int b = blockIdx.x;
   if (b < a.nb_hv)
     heavy_body<N, UNIT, C2>(a, b);
@@ -837,10 +889,11 @@ AdjWs adj_layout(const Geo &g, void *ws) {
 
 // The domain -> ranges table for these domains (clears the heavy count).
 void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
-                         hipStream_t st) {
+                         hipStream_t st, int n_img = 1) {
   if (a.small) {
-    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, st, g, domain,
-                       a.val0, a.off, a.nheavy);
+    hipLaunchKernelGGL(k_sort_small, dim3(1, (unsigned)n_img), dim3(1024), 0,
+                       st, g, domain, a.val0, a.off, a.nheavy,
+                       (long long)a.total);
     a.srt = a.val0;
     return;
   }
@@ -870,7 +923,7 @@ void build_adjoint_table(const Geo &g, const int32_t *domain, AdjWs &a,
 template <int N>
 void build_unit_tables(const Geo &g, const int32_t *domain,
                        const uint8_t *iso, const float *s, const AdjWs &a,
-                       bool with_units, hipStream_t st) {
+                       bool with_units, hipStream_t st, int n_img = 1) {
   UnitArgs u;
   u.g = g;
   u.domain = domain;
@@ -888,12 +941,13 @@ void build_unit_tables(const Geo &g, const int32_t *domain,
   u.U = a.U;
   u.UW = a.UW;
   u.nbu = with_units ? (a.U + 255) / 256 : 0;
+  u.ws_stride = (long long)a.total;
   const long long ne = (long long)g.R * N * N;
-  const unsigned grid = (unsigned)(u.nbu + (ne + 255) / 256);
+  const dim3 grid((unsigned)(u.nbu + (ne + 255) / 256), (unsigned)n_img);
   if (a.unit == 2)
-    hipLaunchKernelGGL((k_adj_units<N, 2>), dim3(grid), dim3(256), 0, st, u);
+    hipLaunchKernelGGL((k_adj_units<N, 2>), grid, dim3(256), 0, st, u);
   else
-    hipLaunchKernelGGL((k_adj_units<N, 1>), dim3(grid), dim3(256), 0, st, u);
+    hipLaunchKernelGGL((k_adj_units<N, 1>), grid, dim3(256), 0, st, u);
 }
 
 // The reverse steps, with the tables built.
@@ -901,9 +955,11 @@ template <int N, int UNIT, bool C2>
 void adjoint_steps_t(const Geo &g, const int32_t *domain, const uint8_t *iso,
                      int iters, const float *traj, const float *grad_xT,
                      float *grad_s, float *grad_o, const AdjWs &a,
-                     hipStream_t st) {
+                     hipStream_t st, int n_img) {
   const size_t HW = (size_t)g.H * g.W;
   StepArgs p;
+  p.ws_stride = (long long)a.total;
+  p.x_stride = (long long)HW * (iters + 1);
   p.g = g;
   p.domain = domain;
   p.iso = iso;
@@ -921,19 +977,26 @@ void adjoint_steps_t(const Geo &g, const int32_t *domain, const uint8_t *iso,
   p.UW = a.UW;
   p.nb_so = (int)(((long long)g.R * N * N + 255) / 256);
   const int nb_lt = (a.U + 255) / 256;
+  // heavy-unit workgroups (each loops over the units past the first pass;
+  // those past the count leave at once)
   const int nb_hv = std::min(a.U, 256);
   const float *gnext = grad_xT;
   float *bufs[2] = {a.gbuf0, a.gbuf1};
   for (int t = iters - 1; t >= 0; --t) {
     p.x = traj + (size_t)t * HW;
     p.gnext = gnext;
+    // the caller's dL/dx_T images are HW floats apart, the workspace's
+    // gradient images a workspace apart
+    p.gn_stride = t == iters - 1 ? (long long)(HW * sizeof(float))
+                                 : (long long)a.total;
     p.gout = bufs[t & 1];
     p.first = t == iters - 1 ? 1 : 0;
     // g_t is needed only while t > 0
     p.nb_hv = t > 0 ? nb_hv : 0;
     const int nb = p.nb_hv + p.nb_so + (t > 0 ? nb_lt : 0);
-    hipLaunchKernelGGL((k_adj_step<N, UNIT, C2>), dim3((unsigned)nb),
-                       dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_adj_step<N, UNIT, C2>),
+                       dim3((unsigned)nb, (unsigned)n_img), dim3(256), 0, st,
+                       p);
     gnext = p.gout;
   }
 }
@@ -942,39 +1005,41 @@ template <int N>
 void adjoint_steps(const Geo &g, const int32_t *domain, const uint8_t *iso,
                    int iters, const float *traj, const float *grad_xT,
                    float *grad_s, float *grad_o, const AdjWs &a,
-                   hipStream_t st) {
+                   hipStream_t st, int n_img) {
   const bool c2 = g.step >= N;
   if (a.unit == 2) {
     if (c2)
       adjoint_steps_t<N, 2, true>(g, domain, iso, iters, traj, grad_xT, grad_s,
-                                  grad_o, a, st);
+                                  grad_o, a, st, n_img);
     else
       adjoint_steps_t<N, 2, false>(g, domain, iso, iters, traj, grad_xT,
-                                   grad_s, grad_o, a, st);
+                                   grad_s, grad_o, a, st, n_img);
   } else {
     if (c2)
       adjoint_steps_t<N, 1, true>(g, domain, iso, iters, traj, grad_xT, grad_s,
-                                  grad_o, a, st);
+                                  grad_o, a, st, n_img);
     else
       adjoint_steps_t<N, 1, false>(g, domain, iso, iters, traj, grad_xT,
-                                   grad_s, grad_o, a, st);
+                                   grad_s, grad_o, a, st, n_img);
   }
 }
 
-// Tables for these codes and s, then the reverse steps.
+// Tables for these codes and s, then the reverse steps; n_img images (a
+// batch needs the one-workgroup sort: the workspace holds one table per
+// image, a.total bytes apart).
 void adjoint(const Geo &g, const int32_t *domain, const uint8_t *iso,
              const float *s, int iters, const float *traj,
              const float *grad_xT, float *grad_s, float *grad_o, AdjWs &a,
-             bool table_built, hipStream_t st) {
-  if (!table_built) build_adjoint_table(g, domain, a, st);
+             bool table_built, hipStream_t st, int n_img = 1) {
+  if (!table_built) build_adjoint_table(g, domain, a, st, n_img);
   if (g.n == 8) {
-    build_unit_tables<8>(g, domain, iso, s, a, !table_built, st);
+    build_unit_tables<8>(g, domain, iso, s, a, !table_built, st, n_img);
     adjoint_steps<8>(g, domain, iso, iters, traj, grad_xT, grad_s, grad_o, a,
-                     st);
+                     st, n_img);
   } else {
-    build_unit_tables<4>(g, domain, iso, s, a, !table_built, st);
+    build_unit_tables<4>(g, domain, iso, s, a, !table_built, st, n_img);
     adjoint_steps<4>(g, domain, iso, iters, traj, grad_xT, grad_s, grad_o, a,
-                     st);
+                     st, n_img);
   }
 }
 
@@ -1180,6 +1245,36 @@ hipError_t launch_decode_backward(const Geo &g, const int32_t *domain,
   AdjWs a = adj_layout(g, ws);
   adjoint(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o, a, false,
           st);
+  return hipGetLastError();
+}
+
+size_t decode_backward_batch_ws_bytes(const Geo &g, int n_images) {
+  return adj_layout(g, nullptr).total * (size_t)n_images;
+}
+
+bool decode_backward_batch_ok(const Geo &g) {
+  return adj_layout(g, nullptr).small;
+}
+
+hipError_t launch_decode_backward_batch(const Geo &g, int n_images,
+                                        const int32_t *domain,
+                                        const uint8_t *iso, const float *s,
+                                        int iters, const float *traj,
+                                        const float *grad_xT, float *grad_s,
+                                        float *grad_o, void *ws,
+                                        hipStream_t st) {
+  const int bs = 256;
+  const long long nR = (long long)g.R * n_images;
+  if (iters == 0) {
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((nR + bs - 1) / bs)),
+                       dim3(bs), 0, st, grad_s, nR, 0.0f);
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)((nR + bs - 1) / bs)),
+                       dim3(bs), 0, st, grad_o, nR, 0.0f);
+    return hipGetLastError();
+  }
+  AdjWs a = adj_layout(g, ws);
+  adjoint(g, domain, iso, s, iters, traj, grad_xT, grad_s, grad_o, a, false,
+          st, n_images);
   return hipGetLastError();
 }
 

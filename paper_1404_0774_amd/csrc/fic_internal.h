@@ -197,6 +197,15 @@ hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
                                 const float *o, int iters, float x0,
                                 float *traj, hipStream_t st);
 size_t decode_backward_ws_bytes(const Geo &g);
+size_t decode_backward_batch_ws_bytes(const Geo &g, int n_images);
+bool decode_backward_batch_ok(const Geo &g);
+hipError_t launch_decode_backward_batch(const Geo &g, int n_images,
+                                        const int32_t *domain,
+                                        const uint8_t *iso, const float *s,
+                                        int iters, const float *traj,
+                                        const float *grad_xT, float *grad_s,
+                                        float *grad_o, void *ws,
+                                        hipStream_t st);
 hipError_t launch_qt_split(int RW, int R, const uint8_t *mask,
                            const double *err, double lim, uint8_t *split,
                            uint8_t *mask_next, hipStream_t st);

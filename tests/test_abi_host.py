@@ -97,6 +97,25 @@ def test_decode_validates_before_gpu_work():
                                  fake, fake, 0, None) == 3
 
 
+def test_backward_batch_validates_before_gpu_work():
+    L = F.lib()
+    p = F.Params(64, 64, 8, 4, 4).c()
+    fake = ctypes.c_void_p(1 << 20)
+    one, four = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.fic_decode_backward_batch_workspace(ctypes.byref(p), 1, ctypes.byref(one)) == 0
+    assert L.fic_decode_backward_batch_workspace(ctypes.byref(p), 4, ctypes.byref(four)) == 0
+    assert four.value == 4 * one.value and one.value % 256 == 0
+    assert L.fic_decode_backward_batch_workspace(ctypes.byref(p), 0, ctypes.byref(one)) == 1
+    args = lambda n, ws_bytes: [ctypes.byref(p), n, fake, fake, fake, fake, 12, fake, fake, fake,
+                                fake, fake, ws_bytes, None]
+    assert L.fic_decode_backward_batch(*args(0, four.value)) == 1          # no images
+    assert L.fic_decode_backward_batch(*args(4, four.value - 1)) == 3      # workspace
+    assert L.fic_decode_backward_batch(*args(70000, 1 << 40)) == 2         # > 65535 images
+    big = F.Params(264, 272, 8, 4, 1).c()                                  # 68,105 domains
+    assert L.fic_decode_backward_batch(ctypes.byref(big), 2, fake, fake, fake, fake, 12, fake,
+                                       fake, fake, fake, fake, 1 << 40, None) == 2
+
+
 def test_refine_validates_before_gpu_work():
     L = F.lib()
     p = F.Params(64, 64, 8, 4, 4).c()

@@ -231,6 +231,38 @@ def test_backward_shared_domains(case):
     assert rel(go.cpu().numpy().astype(np.float64), ro) <= 1e-4
 
 
+@pytest.mark.parametrize("H,W,n,step", [(64, 48, 4, 4), (96, 64, 8, 2), (40, 56, 4, 3)])
+def test_backward_batch_matches_single_calls(H, W, n, step):
+    """The batched adjoint: every image's dL/ds, dL/do bitwise equal to the
+    single call's, with one image of the batch on a single shared domain
+    (heavy units) and the others random."""
+    rng = np.random.default_rng(77)
+    p = F.Params(H, W, 8, n, step)
+    R, ND = F.query(p)[:2]
+    B, T = 5, 6
+    d = rng.integers(0, ND, (B, R)).astype(np.int32)
+    d[2] = 0
+    k = rng.integers(0, 8, (B, R)).astype(np.uint8)
+    s = rng.uniform(-0.8, 0.8, (B, R)).astype(np.float32)
+    o = rng.uniform(-40, 200, (B, R)).astype(np.float32)
+    dd, kd, sd, od = dev(d, torch.int32), dev(k, torch.uint8), dev(s, torch.float32), dev(o, torch.float32)
+    traj = F.decode_batch(dd, kd, sd, od, p, T, 128.0)
+    g = dev(rng.normal(size=(B, H, W)), torch.float32)
+    gs, go = F.decode_backward_batch(dd, kd, sd, od, traj, g, p)
+    for b in range(B):
+        s1, o1 = F.decode_backward(dd[b], kd[b], sd[b], od[b], traj[b].contiguous(), g[b], p)
+        assert torch.equal(gs[b], s1) and torch.equal(go[b], o1), b
+    # and one image against the FP64 gradient
+    rtraj = O.decode(H, W, n, step, d[1], k[1], s[1].astype(np.float64), o[1].astype(np.float64),
+                     T, 128.0)
+    rs, ro = O.decode_backward(H, W, n, step, d[1], k[1], s[1].astype(np.float64),
+                               o[1].astype(np.float64), T, rtraj,
+                               g[1].cpu().numpy().astype(np.float64))
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(gs[1].cpu().numpy().astype(np.float64), rs) <= 1e-4
+    assert rel(go[1].cpu().numpy().astype(np.float64), ro) <= 1e-4
+
+
 def test_backward_bitwise_reproducible_and_autograd():
     H = W = 64
     n, step, T = 4, 2, 12
