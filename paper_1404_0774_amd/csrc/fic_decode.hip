@@ -50,14 +50,18 @@ __device__ __forceinline__ int clamp_dom(int d, int nd) {
 // 8): workgroups go to the 8 XCDs in turn, so each XCD then holds a run of
 // whole images and reads iterate t from the L2 that wrote it.
 //
-// FIRST: the first iteration from the constant start x0, with no reads of an
-// iterate: every cell pools to u0 (the same expression on four x0), and the
-// launch writes both x_0 = x0 (at xs) and x_1 (at ys) over its ranges.
-template <int N, int V, bool FIRST>
+// MODE 0: one iteration, x_{t+1} at ys from x_t at xs.  MODE 1: the first
+// iteration from the constant start x0, with no reads of an iterate: every
+// cell pools to u0 (the same expression on four x0); the launch writes
+// x_0 = x0 (at xs) and x_1 (at ys) over its ranges.  MODE 2: the first two
+// iterations: as MODE 1, and x_2 (at ys + tstride) from x_1, whose pixels
+// phase 1 forms from the codes of the ranges holding them, fma(s, u0, o),
+// the value MODE 1 writes, so the result is bitwise that of two launches.
+template <int N, int V, int MODE>
 __global__ __launch_bounds__(256) void k_decode_pool(
     Geo g, int wpi, int xcd_map, const int32_t *domain, const uint8_t *iso,
     const float *s, const float *o, const float *xs, float *ys,
-    long long xstride, float x0) {
+    long long xstride, long long tstride, float x0) {
   constexpr int RPW = 256 / N;
   constexpr int PS = N * N + 1;  // padded: phase 2 reads at stride PS
   __shared__ float pool[RPW * PS];
@@ -68,28 +72,51 @@ __global__ __launch_bounds__(256) void k_decode_pool(
   const size_t cb = (size_t)b * g.R;
   const float *x = xs + (size_t)b * xstride;
   float *y = ys + (size_t)b * xstride;
-  if constexpr (!FIRST) {
+  const float u0c = ((x0 + x0) + (x0 + x0)) * 0.25f;
+  if constexpr (MODE != 1) {
     const int rl = threadIdx.x / N, a = threadIdx.x % N;
     const int r = r0 + rl;
     if (r < g.R) {
       const int d = clamp_dom(domain[cb + r], g.ND);
       const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
-      const float *p0 = x + (size_t)(Y + 2 * a) * g.W + X;
-      const float *p1 = p0 + g.W;
       float u0[2 * N], u1[2 * N];
-      if constexpr (V == 4) {
+      if constexpr (MODE == 2) {
+        // x_1 at the two cell rows: fma(s, u0, o) of the range holding each
+        // pixel; a row's 2N pixels meet at most three ranges (the two rows
+        // can lie in different rows of ranges when STEP is odd)
+        const size_t ra = cb + (size_t)((Y + 2 * a) / N) * g.RW;
+        const size_t rb = cb + (size_t)((Y + 2 * a + 1) / N) * g.RW;
+        const int rx0 = X / N;
+        float va[3], vb[3];
 #pragma unroll
-        for (int q = 0; q < 2 * N; q += 4) {
-          const float4 e = *(const float4 *)(p0 + q);
-          const float4 f = *(const float4 *)(p1 + q);
-          u0[q] = e.x; u0[q + 1] = e.y; u0[q + 2] = e.z; u0[q + 3] = e.w;
-          u1[q] = f.x; u1[q + 1] = f.y; u1[q + 2] = f.z; u1[q + 3] = f.w;
+        for (int e = 0; e < 3; ++e) {
+          const int rx = min(rx0 + e, g.RW - 1);
+          va[e] = fmaf(s[ra + rx], u0c, o[ra + rx]);
+          vb[e] = fmaf(s[rb + rx], u0c, o[rb + rx]);
         }
-      } else {
 #pragma unroll
         for (int q = 0; q < 2 * N; ++q) {
-          u0[q] = p0[q];
-          u1[q] = p1[q];
+          const int e = (X + q) / N - rx0;
+          u0[q] = e == 0 ? va[0] : (e == 1 ? va[1] : va[2]);
+          u1[q] = e == 0 ? vb[0] : (e == 1 ? vb[1] : vb[2]);
+        }
+      } else {
+        const float *p0 = x + (size_t)(Y + 2 * a) * g.W + X;
+        const float *p1 = p0 + g.W;
+        if constexpr (V == 4) {
+#pragma unroll
+          for (int q = 0; q < 2 * N; q += 4) {
+            const float4 e = *(const float4 *)(p0 + q);
+            const float4 f = *(const float4 *)(p1 + q);
+            u0[q] = e.x; u0[q + 1] = e.y; u0[q + 2] = e.z; u0[q + 3] = e.w;
+            u1[q] = f.x; u1[q + 1] = f.y; u1[q + 2] = f.z; u1[q + 3] = f.w;
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < 2 * N; ++q) {
+            u0[q] = p0[q];
+            u1[q] = p1[q];
+          }
         }
       }
 #pragma unroll
@@ -98,7 +125,7 @@ __global__ __launch_bounds__(256) void k_decode_pool(
             ((u0[2 * c] + u0[2 * c + 1]) + (u1[2 * c] + u1[2 * c + 1])) * 0.25f;
     }
   }
-  if constexpr (!FIRST) __syncthreads();
+  if constexpr (MODE != 1) __syncthreads();
   {
     const int i = threadIdx.x / RPW, rl = threadIdx.x % RPW;
     const int r = r0 + rl;
@@ -106,32 +133,39 @@ __global__ __launch_bounds__(256) void k_decode_pool(
       const int k = iso[cb + r];
       const float sv = s[cb + r], ov = o[cb + r];
       const int ry = r / g.RW, rx = r - ry * g.RW;
-      const float u0 = ((x0 + x0) + (x0 + x0)) * 0.25f;
-      float out[N];
+      float out[N], first[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) {
-        if constexpr (FIRST) {
-          out[j] = fmaf(sv, u0, ov);
-        } else {
+        first[j] = fmaf(sv, u0c, ov);  // x_1 (MODES 1 and 2)
+        if constexpr (MODE != 1) {
           int si, sj;
           sigma(k, i, j, N - 1, si, sj);
           out[j] = fmaf(sv, pool[rl * PS + si * N + sj], ov);
+        } else {
+          out[j] = first[j];
         }
       }
       const size_t off = (size_t)(ry * N + i) * g.W + rx * N;
-      float *q = y + off;
-      float *q0 = (float *)x + off;  // FIRST: x_0 is written, never read
+      // MODE 0: y gets x_{t+1}.  MODE 1: x gets x_0, y x_1.  MODE 2: x gets
+      // x_0, y x_1, y + tstride x_2 (x_0 and x_1 are written, never read).
+      float *q = MODE == 2 ? y + tstride + off : y + off;
+      float *q0 = (float *)x + off;
+      float *q1 = y + off;
       if constexpr (V == 4) {
 #pragma unroll
         for (int j = 0; j < N; j += 4) {
           *(float4 *)(q + j) = float4{out[j], out[j + 1], out[j + 2], out[j + 3]};
-          if constexpr (FIRST) *(float4 *)(q0 + j) = float4{x0, x0, x0, x0};
+          if constexpr (MODE != 0) *(float4 *)(q0 + j) = float4{x0, x0, x0, x0};
+          if constexpr (MODE == 2)
+            *(float4 *)(q1 + j) =
+                float4{first[j], first[j + 1], first[j + 2], first[j + 3]};
         }
       } else {
 #pragma unroll
         for (int j = 0; j < N; ++j) {
           q[j] = out[j];
-          if constexpr (FIRST) q0[j] = x0;
+          if constexpr (MODE != 0) q0[j] = x0;
+          if constexpr (MODE == 2) q1[j] = first[j];
         }
       }
     }
@@ -1131,7 +1165,7 @@ DecGeo dec_geo(const Geo &g) {
 
 // One iteration of n_img images (iterates at xs, ys; image stride xstride
 // floats) with the pooled range kernel.
-template <int N, bool FIRST>
+template <int N, int MODE>
 void decode_pool_step(const Geo &g, int n_img, const int32_t *domain,
                       const uint8_t *iso, const float *s, const float *o,
                       const float *xs, float *ys, long long xstride, bool vec,
@@ -1140,14 +1174,15 @@ void decode_pool_step(const Geo &g, int n_img, const int32_t *domain,
   const int wpi = (g.R + RPW - 1) / RPW;
   const long long nwg = (long long)wpi * n_img;
   const int xcd_map = n_img > 1 && nwg % 8 == 0 ? 1 : 0;
+  const long long tstride = (long long)g.H * g.W;
   if (vec)
-    hipLaunchKernelGGL((k_decode_pool<N, 4, FIRST>), dim3((unsigned)nwg),
+    hipLaunchKernelGGL((k_decode_pool<N, 4, MODE>), dim3((unsigned)nwg),
                        dim3(256), 0, st, g, wpi, xcd_map, domain, iso, s, o, xs,
-                       ys, xstride, x0);
+                       ys, xstride, tstride, x0);
   else
-    hipLaunchKernelGGL((k_decode_pool<N, 1, FIRST>), dim3((unsigned)nwg),
+    hipLaunchKernelGGL((k_decode_pool<N, 1, MODE>), dim3((unsigned)nwg),
                        dim3(256), 0, st, g, wpi, xcd_map, domain, iso, s, o, xs,
-                       ys, xstride, x0);
+                       ys, xstride, tstride, x0);
 }
 
 // 16-byte loads and stores need image rows, domain corners and range rows
@@ -1157,32 +1192,37 @@ bool decode_vec_ok(const Geo &g, const float *traj) {
          ((uintptr_t)traj & 15) == 0;
 }
 
-// All iterations, iters >= 1: the first writes x_0 and x_1.
+template <int N>
+void decode_steps_n(const Geo &g, int n_img, const int32_t *domain,
+                    const uint8_t *iso, const float *s, const float *o,
+                    int iters, float x0, float *traj, long long img_stride,
+                    bool vec, hipStream_t st) {
+  const long long HW = (long long)g.H * g.W;
+  // the first launch writes x_0 .. x_2 (x_0 and x_1 for a single iteration)
+  if (iters >= 2)
+    decode_pool_step<N, 2>(g, n_img, domain, iso, s, o, traj, traj + HW,
+                           img_stride, vec, x0, st);
+  else
+    decode_pool_step<N, 1>(g, n_img, domain, iso, s, o, traj, traj + HW,
+                           img_stride, vec, x0, st);
+  for (int t = 2; t < iters; ++t)
+    decode_pool_step<N, 0>(g, n_img, domain, iso, s, o, traj + (size_t)t * HW,
+                           traj + (size_t)(t + 1) * HW, img_stride, vec, x0,
+                           st);
+}
+
+// All iterations, iters >= 1.
 void decode_steps(const Geo &g, int n_img, const int32_t *domain,
                   const uint8_t *iso, const float *s, const float *o,
                   int iters, float x0, float *traj, long long img_stride,
                   hipStream_t st) {
-  const long long HW = (long long)g.H * g.W;
   const bool vec = decode_vec_ok(g, traj);
-  for (int t = 0; t < iters; ++t) {
-    float *x = traj + (size_t)t * HW;
-    float *y = traj + (size_t)(t + 1) * HW;
-    if (g.n == 8) {
-      if (t == 0)
-        decode_pool_step<8, true>(g, n_img, domain, iso, s, o, x, y,
-                                  img_stride, vec, x0, st);
-      else
-        decode_pool_step<8, false>(g, n_img, domain, iso, s, o, x, y,
-                                   img_stride, vec, x0, st);
-    } else {
-      if (t == 0)
-        decode_pool_step<4, true>(g, n_img, domain, iso, s, o, x, y,
-                                  img_stride, vec, x0, st);
-      else
-        decode_pool_step<4, false>(g, n_img, domain, iso, s, o, x, y,
-                                   img_stride, vec, x0, st);
-    }
-  }
+  if (g.n == 8)
+    decode_steps_n<8>(g, n_img, domain, iso, s, o, iters, x0, traj, img_stride,
+                      vec, st);
+  else
+    decode_steps_n<4>(g, n_img, domain, iso, s, o, iters, x0, traj, img_stride,
+                      vec, st);
 }
 
 hipError_t launch_decode(const Geo &g, const int32_t *domain,
