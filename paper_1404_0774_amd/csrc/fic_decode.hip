@@ -173,22 +173,51 @@ __global__ __launch_bounds__(256) void k_decode_pool(
 }
 
 // Any range size n (a decode at another scale): one thread per output pixel.
+// MODE as k_decode_pool's: 0 one iteration (x -> y); 1 the first from the
+// constant x0 (writes x_0 at x and x_1 at y, reads no iterate); 2 the first
+// two (also x_2 at y + tstride, from x_1 at the cell's four pixels formed
+// from the codes of the ranges holding them, the values MODE 1 writes).
+template <int MODE>
 __global__ void k_decode_step_any(DecGeo d, const int32_t *domain,
                                   const uint8_t *iso, const float *s,
-                                  const float *o, const float *x, float *y) {
+                                  const float *o, float *x, float *y,
+                                  long long tstride, float x0) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= d.H * d.W) return;
   const int py = p / d.W, px = p % d.W;
   const int ry = py / d.n, rx = px / d.n, i = py % d.n, j = px % d.n;
   const int r = ry * d.RW + rx;
-  const int dm = clamp_dom(domain[r], d.ND);
-  int si, sj;
-  sigma(iso[r], i, j, d.n - 1, si, sj);
-  const int cy = (dm / d.NX) * d.step + 2 * si;
-  const int cx = (dm % d.NX) * d.step + 2 * sj;
-  const float *c = x + (size_t)cy * d.W + cx;
-  const float u = ((c[0] + c[1]) + (c[d.W] + c[d.W + 1])) * 0.25f;
-  y[p] = fmaf(s[r], u, o[r]);
+  const float u0c = ((x0 + x0) + (x0 + x0)) * 0.25f;
+  float u = u0c;
+  if constexpr (MODE != 1) {
+    const int dm = clamp_dom(domain[r], d.ND);
+    int si, sj;
+    sigma(iso[r], i, j, d.n - 1, si, sj);
+    const int cy = (dm / d.NX) * d.step + 2 * si;
+    const int cx = (dm % d.NX) * d.step + 2 * sj;
+    if constexpr (MODE == 0) {
+      const float *c = x + (size_t)cy * d.W + cx;
+      u = ((c[0] + c[1]) + (c[d.W] + c[d.W + 1])) * 0.25f;
+    } else {
+      auto x1 = [&](int yy, int xx) {
+        const int rr = (yy / d.n) * d.RW + xx / d.n;
+        return fmaf(s[rr], u0c, o[rr]);
+      };
+      u = ((x1(cy, cx) + x1(cy, cx + 1)) + (x1(cy + 1, cx) + x1(cy + 1, cx + 1))) *
+          0.25f;
+    }
+  }
+  const float v = fmaf(s[r], u, o[r]);
+  if constexpr (MODE == 0) {
+    y[p] = v;
+  } else if constexpr (MODE == 1) {
+    x[p] = x0;
+    y[p] = v;
+  } else {
+    x[p] = x0;
+    y[p] = fmaf(s[r], u0c, o[r]);
+    y[tstride + p] = v;
+  }
 }
 
 // traj[b][0] = x0 for every image b: blockIdx.y is the image.
@@ -1264,11 +1293,21 @@ hipError_t launch_decode_scaled(const DecGeo &d, const int32_t *domain,
   const long long HW = (long long)d.H * d.W;
   const int bs = 256;
   const dim3 grid((unsigned)((HW + bs - 1) / bs));
-  hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
-  for (int t = 0; t < iters; ++t)
-    hipLaunchKernelGGL(k_decode_step_any, grid, dim3(bs), 0, st, d, domain,
+  if (iters == 0) {
+    hipLaunchKernelGGL(k_fill_f32, grid, dim3(bs), 0, st, traj, HW, x0);
+    return hipGetLastError();
+  }
+  // the first launch writes x_0 .. x_2 (x_0 and x_1 for a single iteration)
+  if (iters == 1)
+    hipLaunchKernelGGL(k_decode_step_any<1>, grid, dim3(bs), 0, st, d, domain,
+                       iso, s, o, traj, traj + HW, HW, x0);
+  else
+    hipLaunchKernelGGL(k_decode_step_any<2>, grid, dim3(bs), 0, st, d, domain,
+                       iso, s, o, traj, traj + HW, HW, x0);
+  for (int t = 2; t < iters; ++t)
+    hipLaunchKernelGGL(k_decode_step_any<0>, grid, dim3(bs), 0, st, d, domain,
                        iso, s, o, traj + (size_t)t * HW,
-                       traj + (size_t)(t + 1) * HW);
+                       traj + (size_t)(t + 1) * HW, HW, x0);
   return hipGetLastError();
 }
 
