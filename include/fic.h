@@ -103,8 +103,9 @@ typedef struct {
 
 /*
  * fic_query -- host only, no GPU work.  Validates `p` and reports the range
- * and domain counts and the workspace bytes that fic_encode and
- * fic_decode_backward need for these parameters.  Any output pointer may be
+ * and domain counts of the partition (Section V: non-overlapping n x n
+ * ranges, 2n x 2n domains on a grid of spacing STEP) and the workspace bytes
+ * that fic_encode and fic_decode_backward need for these parameters.  Any output pointer may be
  * NULL.  Errors: FIC_E_INVALID (null p, height or width not a multiple of n,
  * 2n larger than a side, STEP < 1, full_search not 0 or 1),
  * FIC_E_UNSUPPORTED (bit_depth not 8 or 12,
@@ -157,12 +158,23 @@ int fic_encode_noalloc(const fic_params *p, const void *image, fic_codes out,
  * Errors: FIC_E_INVALID (null pointers, workspace smaller than fic_query
  * reports), FIC_E_HIP.
  */
+/*
+ * fic_search_counts -- host, synchronous (waits for the device): how many
+ * ranges and domains the last fic_encode into this workspace put through
+ * the search.  With full_search = 0 the ranges and domains without variance
+ * are left out (their outcome is fixed, eqs. 11-12 and the shadow-block rule
+ * of Section V); with full_search = 1 every one is searched.  8 n_ranges
+ * n_domains is then the number of candidates evaluated.  `workspace` is the
+ * one the encode used.  Errors: FIC_E_INVALID (null pointers, a workspace
+ * smaller than fic_query's encode_ws_bytes), FIC_E_HIP.
+ */
 int fic_search_counts(const fic_params *p, const void *workspace,
                       size_t ws_bytes, int64_t *n_ranges, int64_t *n_domains);
 
 /*
  * Batched encode of many slices of uneven size (each slice an independent
- * fic_encode problem; the paper encodes one image per kernel launch).
+ * fic_encode problem, Alg. 2 / Alg. 3 per slice; the paper encodes one image
+ * per kernel launch, Section V).
  * All slices must share bit_depth (8), range_size, s_bits and o_bits; size
  * and domain_step may differ.
  *
@@ -431,7 +443,8 @@ int fic_load_tuning(const char *json_path);
 int fic_get_tuning(const fic_params *p, fic_tuning *out);
 
 /*
- * Benchmark support (not needed to encode).  fic_timing_begin enables and
+ * Benchmark support (not needed to encode; the per-phase times set beside
+ * the encode times of Table III).  fic_timing_begin enables and
  * resets phase timing: while enabled, every fic_encode records HIP events on
  * its own stream before operand preparation, before the list compaction and
  * seeding pass, before the search, before code extraction and at its end
