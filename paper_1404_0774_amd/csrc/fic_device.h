@@ -60,16 +60,27 @@ __device__ __forceinline__ double g_from_centred(double h, double sa,
   return h + mr * sa + md * sb - (double)g.K * md * mr;
 }
 
-// Position of k-element p of sweep column c in the domain operand.  A full
-// 8-bit matrix-core search (its column list is the identity) stores the
-// operand in MFMA fragment order: block c / 32, k-step p / 16, lane
-// (p / 8 mod 2) 32 + c mod 32, element p mod 8, so that the 64 lanes of a
-// wave read one contiguous run per k-step.  Otherwise each column holds its
-// K elements in order.
+// Position of k-element p of sweep column c in (a plane of) the FP16 domain
+// operand.  The matrix-core searches that sweep columns in (nearly) index
+// order (a full 8-bit centred search, whose column list is the identity,
+// and the 12-bit searches) store the operand in MFMA fragment order: block
+// c / 32, k-step p / 16, lane (p / 8 mod 2) 32 + c mod 32, element p mod 8,
+// so that the 64 lanes of a wave read one contiguous run per k-step.
+// Otherwise each column holds its K elements in order.
 __host__ __device__ inline size_t bop_index(const Geo &g, long long c, int p) {
-  if (g.ctr && g.full)
+  if (g.frag)
     return (size_t)(c >> 5) * 32 * g.K + (size_t)(p >> 4) * 512 +
            (size_t)((((p >> 3) & 1) << 5) | (int)(c & 31)) * 8 + (p & 7);
+  return (size_t)c * g.K + p;
+}
+
+// The same for a plane of the int8 operand (k-steps of 32 one-byte elements,
+// 16 per lane): block c / 32, k-step p / 32, lane (p / 16 mod 2) 32 +
+// c mod 32, element p mod 16.
+__host__ __device__ inline size_t bop8_index(const Geo &g, long long c, int p) {
+  if (g.frag)
+    return (size_t)(c >> 5) * 32 * g.K + (size_t)(p >> 5) * 1024 +
+           (size_t)((((p >> 4) & 1) << 5) | (int)(c & 31)) * 16 + (p & 15);
   return (size_t)c * g.K + p;
 }
 

@@ -40,6 +40,10 @@ struct Geo {
   int ctr;           // 1: 8-bit matrix-core operands (4x4, 8x8 ranges) are
                      //   centred on each block's rounded mean:
                      //   A - round(SA/K) and b - round(Sb/K), exact FP16
+  int frag;          // 1: the domain operand planes are stored in MFMA
+                     //   fragment order (full matrix-core searches of 8-bit
+                     //   centred images, and the 12-bit matrix-core
+                     //   searches; bop_index and bop8_index give the layout)
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step

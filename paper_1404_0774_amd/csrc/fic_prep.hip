@@ -84,10 +84,10 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   if (live) {
     *(halfN *)(b.bop + bop_index(g, col, i * N)) = vh;
     if (g.bits == 12)
-      *(halfN *)(b.bop + (size_t)g.NC_pad * K + (size_t)col * K + i * N) = vl;
+      *(halfN *)(b.bop + (size_t)g.NC_pad * K + bop_index(g, col, i * N)) = vl;
     if (g.i8) {
       // the same pieces as int8 (both <= 127) for the int8 search
-      int8_t *dh = b.bop8 + (size_t)col * K + i * N;
+      int8_t *dh = b.bop8 + bop8_index(g, col, i * N);
       int8_t *dl = dh + (size_t)g.NC_pad * K;
 #pragma unroll
       for (int j = 0; j < N; ++j) {

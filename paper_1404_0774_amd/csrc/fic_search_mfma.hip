@@ -664,7 +664,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   if (rg >= rows) return;
   const int cbpc = (ncb + chunks - 1) / chunks;
   const int c0 = chunk * cbpc, c1 = min(c0 + cbpc, ncb);
-  if (g.ctr && g.full)
+  if (g.frag)
     search_rows<K, true>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0, c1);
   else
     search_rows<K, false>(g, b, img, lds, rg * kMfmaRangesPerWG, nA, nD, c0,
@@ -730,7 +730,7 @@ __global__ __launch_bounds__(256, 2) void k_search_batch_u8(BatchDev bd) {
     const int row0 = w.y * kMfmaRangesPerWG;
     const int c1 = min(w.w, (nD + 31) / 32);
     if (row0 < nA && w.z < c1) {
-      if (g.ctr && g.full)
+      if (g.frag)
         search_rows<K, true>(g, b, g.pix_a ? img : nullptr, lds, row0, nA, nD,
                              w.z, c1);
       else

@@ -112,10 +112,12 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
 }
 
 // Column ci of the searched list for block cb and lane column cl (-1 past
-// the list).
+// the list); with identity lists (ident) the entry is its own index and
+// is not read.
 __device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
-                                        int cl) {
+                                        int cl, int ident) {
   const int j = cb * 32 + cl;
+  if (ident) return j < nD ? j : -1;
   return j < nD ? b.act_col[j] : -1;
 }
 
@@ -126,7 +128,7 @@ __device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
 // lane layout as the 8-bit kernel: accumulator v of lane l holds transform
 // v mod 8 of range 2 (l / 32) + v / 8 of the wave, for domain column
 // l mod 32.
-template <int K>
+template <int K, bool FRAG>
 __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
   constexpr int KS = K / 16;
   __shared__ unsigned long long s_best[4][kWR];
@@ -202,48 +204,53 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
     wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
   }
 
-  // a column past the searched list reads column 0 and is marked flat
-  // (D' = +inf), so it never passes the prune
-  half8 bh[KS], bl[KS];
-  float csa, cdp;
-  int cdom;
-  double csaa;
-  {
-    const int ci = column12(b, nD, c0, cl);
+  // A column past the searched list reads column 0 and is marked flat
+  // (D' = +inf), so it never passes the prune.
+  struct Col12 {
+    float sa, dp;
+    int dom;
+    double saa;
+  };
+  // FRAG: the operand planes are in fragment order (a full search), where
+  // lane (h, c mod 32) of k-step kk reads 16 bytes at block offset
+  // kk 1024 + 16 lane, one contiguous run per wave and k-step
+  auto load_col = [&](int ci, half8 (&hh)[KS], half8 (&ll)[KS], Col12 &c) {
     const int col = ci >= 0 ? ci : 0;
-    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
+    const _Float16 *bsrc =
+        FRAG ? b.bop + (size_t)(col >> 5) * 32 * K + ((h << 5) | (col & 31)) * 8
+             : b.bop + (size_t)col * K + 8 * h;
+    constexpr int kstep = FRAG ? 512 : 16;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      bh[kk] = *(const half8 *)(bsrc + 16 * kk);
-      bl[kk] = *(const half8 *)(bsrc + bplane + 16 * kk);
+      hh[kk] = *(const half8 *)(bsrc + kstep * kk);
+      ll[kk] = *(const half8 *)(bsrc + bplane + kstep * kk);
     }
     const float2 sadp = b.col_sadp[col];
-    csa = sadp.x;
-    cdp = ci >= 0 ? sadp.y : __builtin_inff();
-    cdom = b.col_dom[col];
-    csaa = b.col_saa[col];
-  }
+    c.sa = sadp.x;
+    c.dp = ci >= 0 ? sadp.y : __builtin_inff();
+    c.dom = b.col_dom[col];
+    c.saa = b.col_saa[col];
+  };
+  // two operand buffers: a block reads one while the next block's column
+  // streams into the other (no register copies, so no wait for the loads
+  // within the block that issued them)
+  half8 bhA[KS], blA[KS], bhB[KS], blB[KS];
+  Col12 colA, colB;
+  load_col(column12(b, nD, c0, cl, g.ident), bhA, blA, colA);
   // column index of the next block, read a block ahead
-  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl) : -1;
+  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl, g.ident) : -1;
 
-  for (int cb = c0; cb < c1; ++cb) {
+  auto block = [&](int cb, const half8 (&bh)[KS], const half8 (&bl)[KS],
+                   const Col12 &cc, half8 (&bhn)[KS], half8 (&bln)[KS],
+                   Col12 &nc) {
     const int slot = (cb - c0) % kSync;
-    half8 bhn[KS], bln[KS];
-    const int ncol = ci_next >= 0 ? ci_next : 0;
-    const bool nlive = ci_next >= 0;
-    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl) : -1;
-    {
-      const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        bhn[kk] = *(const half8 *)(bsrc + 16 * kk);
-        bln[kk] = *(const half8 *)(bsrc + bplane + 16 * kk);
-      }
-    }
-    const float2 nsadp = b.col_sadp[ncol];
-    const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
-    const int ndom = b.col_dom[ncol];
-    const double nsaa = b.col_saa[ncol];
+    load_col(ci_next, bhn, bln, nc);
+    // the column of the block after next, read after this block's loads so
+    // that waiting for them never waits for it
+    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl, g.ident) : -1;
+    const float csa = cc.sa, cdp = cc.dp;
+    const int cdom = cc.dom;
+    const double csaa = cc.saa;
 
     f32x16 ghh = f32x16{}, gmid = f32x16{}, gll = f32x16{};
 #pragma unroll
@@ -337,16 +344,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
         wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
       }
     }
-
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      bh[kk] = bhn[kk];
-      bl[kk] = bln[kk];
-    }
-    csa = nsa;
-    cdp = ndp;
-    cdom = ndom;
-    csaa = nsaa;
+  };
+  for (int cb = c0; cb < c1; cb += 2) {
+    block(cb, bhA, blA, colA, bhB, blB, colB);
+    if (cb + 1 < c1) block(cb + 1, bhB, blB, colB, bhA, blA, colA);
   }
 }
 
@@ -357,7 +358,10 @@ hipError_t launch_search_mfma12(const Geo &g, const EncBufs &b,
   if (g.bits != 12) return hipErrorInvalidValue;
   static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
   if (workgroups < 1) workgroups = 1;
-  auto kern = g.K == 64 ? k_search_mfma_12<64> : k_search_mfma_12<16>;
+  auto kern = g.K == 64 ? (g.frag ? k_search_mfma_12<64, true>
+                                  : k_search_mfma_12<64, false>)
+                        : (g.frag ? k_search_mfma_12<16, true>
+                                  : k_search_mfma_12<16, false>);
   hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b);
   return hipGetLastError();
 }

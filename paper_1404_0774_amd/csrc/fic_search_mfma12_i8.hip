@@ -113,10 +113,12 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
 }
 
 // Column ci of the searched list for block cb and lane column cl (-1 past
-// the list).
+// the list); with identity lists (ident) the entry is its own index and
+// is not read.
 __device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
-                                        int cl) {
+                                        int cl, int ident) {
   const int j = cb * 32 + cl;
+  if (ident) return j < nD ? j : -1;
   return j < nD ? b.act_col[j] : -1;
 }
 
@@ -208,48 +210,51 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) 
     wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
   }
 
-  // a column past the searched list reads column 0 and is marked flat
-  // (D' = +inf), so it never passes the prune
-  i32x4 bh[KS], bl[KS];
-  float csa, cdp;
-  int cdom;
-  double csaa;
-  {
-    const int ci = column12(b, nD, c0, cl);
+  // A column past the searched list reads column 0 and is marked flat
+  // (D' = +inf), so it never passes the prune.
+  struct ColStat {
+    float sa, dp;
+    int dom;
+    double saa;
+  };
+  // the operand planes are in fragment order (bop8_index): lane
+  // (h, c mod 32) of k-step kk reads 16 bytes at block offset
+  // kk 1024 + 16 lane, one contiguous run per wave and k-step
+  auto load_col = [&](int ci, i32x4 (&hh)[KS], i32x4 (&ll)[KS], ColStat &c) {
     const int col = ci >= 0 ? ci : 0;
-    const int8_t *bsrc = b.bop8 + (size_t)col * K + 16 * h;
+    const int8_t *bsrc =
+        b.bop8 + (size_t)(col >> 5) * 32 * K + ((h << 5) | (col & 31)) * 16;
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      bh[kk] = *(const i32x4 *)(bsrc + 32 * kk);
-      bl[kk] = *(const i32x4 *)(bsrc + bplane + 32 * kk);
+      hh[kk] = *(const i32x4 *)(bsrc + 1024 * kk);
+      ll[kk] = *(const i32x4 *)(bsrc + bplane + 1024 * kk);
     }
     const float2 sadp = b.col_sadp[col];
-    csa = sadp.x;
-    cdp = ci >= 0 ? sadp.y : __builtin_inff();
-    cdom = b.col_dom[col];
-    csaa = b.col_saa[col];
-  }
+    c.sa = sadp.x;
+    c.dp = ci >= 0 ? sadp.y : __builtin_inff();
+    c.dom = b.col_dom[col];
+    c.saa = b.col_saa[col];
+  };
+  // two operand buffers: a block reads one while the next block's column
+  // streams into the other (no register copies, so no wait for the loads
+  // within the block that issued them)
+  i32x4 bhA[KS], blA[KS], bhB[KS], blB[KS];
+  ColStat colA, colB;
+  load_col(column12(b, nD, c0, cl, g.ident), bhA, blA, colA);
   // column index of the next block, read a block ahead
-  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl) : -1;
+  int ci_next = c0 + 1 < c1 ? column12(b, nD, c0 + 1, cl, g.ident) : -1;
 
-  for (int cb = c0; cb < c1; ++cb) {
+  auto block = [&](int cb, const i32x4 (&bh)[KS], const i32x4 (&bl)[KS],
+                   const ColStat &cc, i32x4 (&bhn)[KS], i32x4 (&bln)[KS],
+                   ColStat &nc) {
     const int slot = (cb - c0) % kSync;
-    i32x4 bhn[KS], bln[KS];
-    const int ncol = ci_next >= 0 ? ci_next : 0;
-    const bool nlive = ci_next >= 0;
-    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl) : -1;
-    {
-      const int8_t *bsrc = b.bop8 + (size_t)ncol * K + 16 * h;
-#pragma unroll
-      for (int kk = 0; kk < KS; ++kk) {
-        bhn[kk] = *(const i32x4 *)(bsrc + 32 * kk);
-        bln[kk] = *(const i32x4 *)(bsrc + bplane + 32 * kk);
-      }
-    }
-    const float2 nsadp = b.col_sadp[ncol];
-    const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
-    const int ndom = b.col_dom[ncol];
-    const double nsaa = b.col_saa[ncol];
+    load_col(ci_next, bhn, bln, nc);
+    // the column of the block after next, read after this block's loads so
+    // that waiting for them never waits for it
+    ci_next = cb + 2 < c1 ? column12(b, nD, cb + 2, cl, g.ident) : -1;
+    const float csa = cc.sa, cdp = cc.dp;
+    const int cdom = cc.dom;
+    const double csaa = cc.saa;
 
     i32x16 ghh = i32x16{}, gmid = i32x16{}, gll = i32x16{};
 #pragma unroll
@@ -341,16 +346,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) 
         wp[e] = weight_from_key(my_best[2 * h + e], Kd * rs.y - rs.x * rs.x, g);
       }
     }
-
-#pragma unroll
-    for (int kk = 0; kk < KS; ++kk) {
-      bh[kk] = bhn[kk];
-      bl[kk] = bln[kk];
-    }
-    csa = nsa;
-    cdp = ndp;
-    cdom = ndom;
-    csaa = nsaa;
+  };
+  for (int cb = c0; cb < c1; cb += 2) {
+    block(cb, bhA, blA, colA, bhB, blB, colB);
+    if (cb + 1 < c1) block(cb + 1, bhB, blB, colB, bhA, blA, colA);
   }
 }
 
@@ -362,6 +361,8 @@ hipError_t launch_search_mfma12_i8(const Geo &g, const EncBufs &b,
   if (g.bits != 12 || !g.i8 || g.K != 64) return hipErrorInvalidValue;
   static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
   if (workgroups < 1) workgroups = 1;
+  // the kernel reads the operand planes in fragment order only
+  if (!g.frag) return hipErrorInvalidValue;
   auto kern = k_search_mfma_12_i8<64>;
   hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b);
   return hipGetLastError();

@@ -112,10 +112,12 @@ __device__ __forceinline__ void drain16(QEntry16 *queue, unsigned *cands,
 }
 
 // Column ci of the searched list for block cb and lane column cl (-1 past
-// the list).
+// the list); with identity lists (ident) the entry is its own index and
+// is not read.
 __device__ __forceinline__ int column16(const EncBufs &b, int nD, int cb,
-                                        int cl) {
+                                        int cl, int ident) {
   const int j = cb * 32 + cl;
+  if (ident) return j < nD ? j : -1;
   return j < nD ? b.act_col[j] : -1;
 }
 
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_16(Geo g, EncBufs b) {
   int cdom;
   double csaa;
   {
-    const int ci = column16(b, nD, c0, cl);
+    const int ci = column16(b, nD, c0, cl, g.ident);
     const int col = ci >= 0 ? ci : 0;
     const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
 #pragma unroll
@@ -221,14 +223,13 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_16(Geo g, EncBufs b) {
     csaa = b.col_saa[col];
   }
   // column index of the next block, read a block ahead
-  int ci_next = c0 + 1 < c1 ? column16(b, nD, c0 + 1, cl) : -1;
+  int ci_next = c0 + 1 < c1 ? column16(b, nD, c0 + 1, cl, g.ident) : -1;
 
   for (int cb = c0; cb < c1; ++cb) {
     const int slot = (cb - c0) % kSync;
     half8 bhn[KS];
     const int ncol = ci_next >= 0 ? ci_next : 0;
     const bool nlive = ci_next >= 0;
-    ci_next = cb + 2 < c1 ? column16(b, nD, cb + 2, cl) : -1;
     {
       const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
 #pragma unroll
@@ -238,6 +239,9 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_16(Geo g, EncBufs b) {
     const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
     const int ndom = b.col_dom[ncol];
     const double nsaa = b.col_saa[ncol];
+    // the column of the block after next, read after this block's loads so
+    // that waiting for them never waits for it
+    ci_next = cb + 2 < c1 ? column16(b, nD, cb + 2, cl, g.ident) : -1;
 
     f32x16 gp = f32x16{};
 #pragma unroll
