@@ -8,8 +8,8 @@
 //     M    = sum (A_hi * 2 b_lo + A_lo * b_hi),
 // where every partial sum is an integer below 64 * 127 * 189 < 2^24, so three
 // FP16 MFMA chains with FP32 accumulation give the three partials exactly
-// (M runs over K' = 2K products).  The factor 2 is applied to the streamed
-// A_hi fragment with packed FP16 adds (exact: values <= 254).
+// (M runs over K' = 2K products).  The factor 2 is applied once to the
+// resident b_lo fragment (exact: values <= 126), not to the streamed operand.
 //
 // The prune uses G rebuilt in FP32 (rounding error below 2^-22 G) with a
 // matching margin; queued pairs carry G rebuilt exactly in FP64, and drains
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
 
   const size_t aplane = (size_t)g.R_pad * 8 * K;
   const size_t bplane = (size_t)g.NC_pad * K;
-  half8 ah[KS], al[KS];
+  half8 ah[KS], al[KS], al2[KS];  // al2 = 2 b_lo
   {
     const int rho = lane & 31;
     const int gg = rho >> 3, hh = (rho >> 2) & 1, q = rho & 3;
@@ -192,6 +192,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
     for (int kk = 0; kk < KS; ++kk) {
       ah[kk] = sl >= 0 ? *(const half8 *)(src + 16 * kk) : half8{};
       al[kk] = sl >= 0 ? *(const half8 *)(src + aplane + 16 * kk) : half8{};
+      al2[kk] = al[kk] + al[kk];
     }
   }
 
@@ -255,10 +256,9 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
     f32x16 ghh = f32x16{}, gmid = f32x16{}, gll = f32x16{};
 #pragma unroll
     for (int kk = 0; kk < KS; ++kk) {
-      const half8 b2 = bh[kk] + bh[kk];
       ghh = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[kk], bh[kk], ghh, 0, 0, 0);
       gll = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[kk], bl[kk], gll, 0, 0, 0);
-      gmid = __builtin_amdgcn_mfma_f32_32x32x16_f16(al[kk], b2, gmid, 0, 0, 0);
+      gmid = __builtin_amdgcn_mfma_f32_32x32x16_f16(al2[kk], bh[kk], gmid, 0, 0, 0);
       gmid = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah[kk], bl[kk], gmid, 0, 0, 0);
     }
 
