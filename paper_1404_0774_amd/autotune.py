@@ -9,8 +9,9 @@ that too, so a shape that changed a code would stop it.
     python -m paper_1404_0774_amd.autotune [--out PATH] [--reps N]
 
 Workloads: the 512x512 8-bit slice with 8x8 ranges at domain stride 4 (both
-methods), the 512x512 12-bit slice at stride 2, the 256x256 8-bit slice with
-4x4 ranges, and a batch of 64 uneven 8-bit slices at stride 8.
+methods), the 512x512 12-bit slice at stride 2 (FP16 and int8 matrix-core
+searches), the 256x256 8-bit slice with 4x4 ranges, and a batch of 64 uneven
+8-bit slices at stride 8.
 """
 import argparse
 import json
@@ -142,6 +143,10 @@ def main(argv=None):
     img12 = torch.from_numpy(gen_image(512, 512, 12, 3).astype(np.int16)).to(dev)
     e, r = tune_single("ct12_512 mfma", img12, F.Params(512, 512, 12, 8, 2), [1, 2, 4, 8, 16, 32],
                        [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
+    entries.append(e); records.append(r)
+    e, r = tune_single("ct12_512 mfma_i8", img12,
+                       F.Params(512, 512, 12, 8, 2, method=F.METHOD_MFMA_I8),
+                       [1, 2, 4, 8, 16, 32], [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
     entries.append(e); records.append(r)
     img5 = torch.from_numpy(gen_image(256, 256, 8, 5)).to(dev)
     e, r = tune_single("u8_256 n4 mfma", img5, F.Params(256, 256, 8, 4, 4), chunks, [0, 1, 2, 4],

@@ -11,9 +11,11 @@
 // per 32-deep k-step, two k-steps for 8x8 ranges).  Integer accumulation is
 // exact whatever the size of the sums; the int8 rate is twice the FP16 rate
 // and each instruction is twice as deep, so the contraction takes a quarter
-// of the FP16 kernel's matrix-core instructions.  Everything after the
-// contraction (prune with a margin, queue of exact FP64 G, drains, key
-// updates) is the FP16 kernel's.  The doubling of b_lo is a shift of each
+// of the FP16 kernel's matrix-core instructions.  G itself is rebuilt in
+// unsigned 32-bit integers (exact: it stays below 2^32), so only the per-pair
+// maximum and minimum are converted for the prune; everything after that
+// (prune with a margin, queue of exact FP64 G, drains, key updates) is the
+// FP16 kernel's.  The doubling of b_lo is a shift of each
 // packed byte (no carries: bytes <= 63).
 #include <math.h>
 
@@ -265,30 +267,32 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) 
       gmid = __builtin_amdgcn_mfma_i32_32x32x32_i8(ah[kk], bl[kk], gmid, 0, 0, 0);
     }
 
-    // G in FP32 (non-negative), max/min over the 8 transforms on bit patterns
-    float gap[16];
+    // G exactly, in unsigned 32-bit integers (G <= 64 * 16380 * 4095 <
+    // 2^32, and every partial is non-negative); max/min over the 8
+    // transforms, then only those two go to FP32 (rounding below 2^-24 G)
+    unsigned gu[16];
 #pragma unroll
     for (int v = 0; v < 16; ++v)
-      gap[v] = fmaf(8192.0f, (float)ghh[v], fmaf(64.0f, (float)gmid[v], (float)gll[v]));
+      gu[v] = ((unsigned)ghh[v] << 13) + ((unsigned)gmid[v] << 6) +
+              (unsigned)gll[v];
     float gmx[2], gmn[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      unsigned ux = __float_as_uint(gap[8 * e]), un = ux;
+      unsigned ux = gu[8 * e], un = ux;
 #pragma unroll
       for (int k = 1; k < 8; ++k) {
-        const unsigned u = __float_as_uint(gap[8 * e + k]);
-        ux = max(ux, u);
-        un = min(un, u);
+        ux = max(ux, gu[8 * e + k]);
+        un = min(un, gu[8 * e + k]);
       }
-      gmx[e] = __uint_as_float(ux);
-      gmn[e] = __uint_as_float(un);
+      gmx[e] = (float)ux;
+      gmn[e] = (float)un;
     }
     bool ps[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       const float a0 = fmaf(-csa, bbar[e], gmx[e]);
       const float a1 = fmaf(-csa, bbar[e], gmn[e]);
-      // margin for the FP32 rebuild of G and the rounding of a
+      // margin for the FP32 conversion of G and the rounding of a
       const float mm = fmaf(fmaxf(fabsf(a0), fabsf(a1)), 1.0f + 0x1p-20f,
                             gmx[e] * 0x1p-20f);
       ps[e] = mm * mm >= wp[e] * cdp;
@@ -306,8 +310,7 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) 
           QEntry12 *q = &queue[qn + off];
 #pragma unroll
           for (int k = 0; k < 8; ++k)
-            q->g[k] = (double)(8192ll * ghh[8 * e + k] +
-                               64ll * gmid[8 * e + k] + gll[8 * e + k]);
+            q->g[k] = (double)gu[8 * e + k];
           q->saa = csaa;
           q->sa = csa;
           q->dp = cdp;
