@@ -403,8 +403,10 @@ int fic_stream_unpack(const fic_params *p, const void *in, size_t in_bytes,
  * Launch-shape tuning (host only; no GPU work).  The search grid splits the
  * candidate table of eq. (8) into row groups of ranges and column chunks of
  * domains; these entries choose how many chunks (the matrix-core searches
- * launch col_chunks workgroups per row group of all ranges and spread them
- * over the row groups of the ranges they search), how many leading 32-column
+ * launch col_chunks workgroups per row group of all ranges; the 8-bit ones
+ * spread them over the row groups of the ranges they search, the 12-bit ones
+ * give each searched row group col_chunks chunks and leave the rest idle),
+ * how many leading 32-column
  * blocks a seed pass ranks first to give each range a starting bound (the
  * search still covers every block; the 8-bit, n = 8 matrix-core search seeds
  * itself and always resolves this to 0), and how many

@@ -141,12 +141,12 @@ def main(argv=None):
                            [4, 8, 16, 32], [1], max(3, args.reps // 3), dev, log)
         entries.append(e); records.append(r)
     img12 = torch.from_numpy(gen_image(512, 512, 12, 3).astype(np.int16)).to(dev)
-    e, r = tune_single("ct12_512 mfma", img12, F.Params(512, 512, 12, 8, 2), [1, 2, 4, 8, 16, 32],
+    e, r = tune_single("ct12_512 mfma", img12, F.Params(512, 512, 12, 8, 2), [2, 4, 8, 12, 16, 20, 24, 32],
                        [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
     entries.append(e); records.append(r)
     e, r = tune_single("ct12_512 mfma_i8", img12,
                        F.Params(512, 512, 12, 8, 2, method=F.METHOD_MFMA_I8),
-                       [1, 2, 4, 8, 16, 32], [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
+                       [2, 4, 8, 12, 16, 20, 24, 32], [1, 2, 4, 8], max(3, args.reps // 3), dev, log)
     entries.append(e); records.append(r)
     img5 = torch.from_numpy(gen_image(256, 256, 8, 5)).to(dev)
     e, r = tune_single("u8_256 n4 mfma", img5, F.Params(256, 256, 8, 4, 4), chunks, [0, 1, 2, 4],

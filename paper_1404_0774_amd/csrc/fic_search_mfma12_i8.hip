@@ -126,8 +126,9 @@ __device__ __forceinline__ int column12(const EncBufs &b, int nD, int cb,
 
 // A 1-D grid of G workgroups over the searched lists (ranges and domains
 // with variance, built by the compaction; the lengths are read on the
-// device): rows of 16 searched ranges, each split into G / rows chunks of
-// 32-column blocks (at least one).  Block: 4 waves of 4 ranges each.  Same
+// device): rows of 16 searched ranges, each split into G / (R_pad / 16)
+// chunks of 32-column blocks (between one and the number of blocks); with
+// fewer searched rows than R_pad / 16 the workgroups left over return.  Block: 4 waves of 4 ranges each.  Same
 // lane layout as the 8-bit kernel: accumulator v of lane l holds transform
 // v mod 8 of range 2 (l / 32) + v / 8 of the wave, for domain column
 // l mod 32.
@@ -145,7 +146,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12_i8(Geo g, EncBufs b) 
   const int rows = (nA + 4 * kWR - 1) / (4 * kWR);
   const int ncb = (nD + 31) / 32;
   if (rows == 0 || ncb == 0) return;
-  const int chunks = max(1, min((int)gridDim.x / rows, ncb));
+  // G / (R_pad / 16) chunks per row (the launch's col_chunks): rows of
+  // searched ranges do not take more, the workgroups left over return
+  const int cmax = max(1, (int)gridDim.x / max(1, g.R_pad / (4 * kWR)));
+  const int chunks = max(1, min(min((int)gridDim.x / rows, cmax), ncb));
   const int rg = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
   if (rg >= rows) return;
   const int cbpc = (ncb + chunks - 1) / chunks;

@@ -31,8 +31,10 @@ constexpr int kMaxSeedBlocks = 64;
 constexpr int kMaxItemBlocks = 4096;
 
 // Built-in defaults: about two workgroups per compute unit (256 CUs) in the
-// search launch, one seed block (ranked for a starting bound) once there are
-// 16 or more column blocks, 16 column blocks per batched work item.
+// search launch (the 12-bit matrix-core searches about 24, which the compute
+// units take in turn, so the launch ends evenly), one seed block (ranked for
+// a starting bound) once there are 16 or more column blocks, 16 column
+// blocks per batched work item.
 Tune default_tune(const Geo &g, int method) {
   const int per_wg =
       ((g.bits == 12 && method != FIC_METHOD_DIRECT) || g.n == 16)
@@ -41,7 +43,8 @@ Tune default_tune(const Geo &g, int method) {
   const int row_groups = std::max(1, g.R_pad / per_wg);
   Tune t;
   t.seed_blocks = g.NCB >= 16 ? 1 : 0;
-  t.chunks = (512 + row_groups - 1) / row_groups;
+  const int target = g.bits == 12 && method != FIC_METHOD_DIRECT ? 6144 : 512;
+  t.chunks = (target + row_groups - 1) / row_groups;
   t.item_blocks = 16;
   return t;
 }

@@ -180,9 +180,10 @@ def test_tuning_defaults(clean_tuning):
                      col_chunks=8, seed_blocks=0, item_blocks=16)
     td = F.get_tuning(F.Params(512, 512, 8, 8, 4, method=F.METHOD_DIRECT))
     assert td["seed_blocks"] == 1
-    # 12-bit matrix-core search uses 16-range row groups: 256 groups -> 2 chunks
+    # 12-bit matrix-core searches use 16-range row groups and about 24
+    # workgroups per CU: 256 groups -> 6144 / 256 = 24 chunks
     t12 = F.get_tuning(F.Params(512, 512, 12, 8, 2))
-    assert t12["col_chunks"] == 2 and t12["seed_blocks"] == 1
+    assert t12["col_chunks"] == 24 and t12["seed_blocks"] == 1
     # fewer than 16 column blocks: no seed pass; chunks clamped to the blocks
     t1 = F.get_tuning(F.Params(64, 64, 8, 4, 4))   # 225 domains -> 8 blocks
     assert t1["seed_blocks"] == 0 and t1["col_chunks"] == 8
