@@ -30,7 +30,7 @@ constexpr int kSync = 4;    // column blocks between global syncs
 constexpr int kQueue = 128; // pairs; >= 63 + 64 lanes
 
 struct __attribute__((aligned(16))) QEntry12 {
-  double g[8];  // exact G of the 8 transforms
+  unsigned g[8];  // exact G of the 8 transforms (G <= 64 16380 4095 < 2^32)
   double saa;
   float sa, dp;
   int dom, lr;
@@ -62,7 +62,7 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
       if (i < n) {
         const QEntry12 &q = queue[i];
 #pragma unroll
-        for (int k = 0; k < 8; ++k) gv[k] = q.g[k];
+        for (int k = 0; k < 8; ++k) gv[k] = (double)q.g[k];
         const double2 rs = rstat[q.lr];
         const float t =
             weight_from_key(best[q.lr], K * rs.y - rs.x * rs.x, g) * q.dp;
@@ -87,26 +87,26 @@ __device__ __forceinline__ void drain12(QEntry12 *queue, unsigned *cands,
       const unsigned pk = cands[c];
       const QEntry12 &q = queue[pk >> 3];
       const double2 rs = rstat[q.lr];
-      const Fit f = fit_exact(q.g[pk & 7], (double)q.sa, q.saa, rs.x, rs.y, g);
+      const Fit f = fit_exact((double)q.g[pk & 7], (double)q.sa, q.saa, rs.x, rs.y, g);
       atomicMin(&best[q.lr], make_key(f.err, 8ll * q.dom + (pk & 7), g));
     }
     __builtin_amdgcn_wave_barrier();
   }
   const int rem = qn - n;
-  static_assert(sizeof(QEntry12) == 96, "entry is six 16-byte words");
-  uint4 t[6];
+  static_assert(sizeof(QEntry12) == 64, "entry is four 16-byte words");
+  uint4 t[4];
 #pragma unroll
-  for (int w = 0; w < 6; ++w) t[w] = uint4{0, 0, 0, 0};
+  for (int w = 0; w < 4; ++w) t[w] = uint4{0, 0, 0, 0};
   if (lane < rem) {
     const uint4 *src = (const uint4 *)&queue[n + lane];
 #pragma unroll
-    for (int w = 0; w < 6; ++w) t[w] = src[w];
+    for (int w = 0; w < 4; ++w) t[w] = src[w];
   }
   __builtin_amdgcn_wave_barrier();
   if (lane < rem) {
     uint4 *dst = (uint4 *)&queue[lane];
 #pragma unroll
-    for (int w = 0; w < 6; ++w) dst[w] = t[w];
+    for (int w = 0; w < 4; ++w) dst[w] = t[w];
   }
   qn = rem;
 }
@@ -307,9 +307,9 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_12(Geo g, EncBufs b) {
           QEntry12 *q = &queue[qn + off];
 #pragma unroll
           for (int k = 0; k < 8; ++k)
-            q->g[k] = fma(8192.0, (double)ghh[8 * e + k],
-                          fma(64.0, (double)gmid[8 * e + k],
-                              (double)gll[8 * e + k]));
+            q->g[k] = (unsigned)fma(8192.0, (double)ghh[8 * e + k],
+                                    fma(64.0, (double)gmid[8 * e + k],
+                                        (double)gll[8 * e + k]));
           q->saa = csaa;
           q->sa = csa;
           q->dp = cdp;
