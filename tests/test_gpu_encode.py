@@ -197,6 +197,29 @@ def test_parity_12bit_small(method, H, W, n, step, seed, full):
                 f"12b {H}x{W}")
 
 
+@pytest.fixture
+def restore_tuning():
+    yield
+    F.set_tuning([])
+    F.load_tuning(F._lib.TUNING_PATH)
+
+
+@pytest.mark.parametrize("full", [0, 1])
+@pytest.mark.parametrize("method", [F.METHOD_MFMA, F.METHOD_MFMA_I8])
+def test_12bit_launch_shapes_give_oracle_codes(method, full, restore_tuning):
+    """Every chunk count gives the oracle's codes: one chunk per row group,
+    chunks that do not divide the column blocks, the tuned 24, and more than
+    there are blocks (clamped); without the full flag fewer row groups are
+    searched than the grid holds, and the workgroups left over return."""
+    img = gen_image(96, 80, 12, 44)   # 120 ranges, 1,353 domains (43 blocks)
+    ref = O.encode(img, 8, 2, bits=12)
+    for chunks in (1, 5, 24, 200):
+        F.set_tuning([dict(bit_depth=12, range_size=8, method=method, min_domains=0,
+                           col_chunks=chunks, seed_blocks=1)])
+        assert_same(gpu_encode(img, 8, 2, 12, method, full=full), ref,
+                    f"12b chunks={chunks}")
+
+
 @pytest.mark.parametrize("full", [0, 1])
 @pytest.mark.parametrize("method", METHODS12)
 @pytest.mark.parametrize("kind", ["zeros", "max", "noise", "checker"])
