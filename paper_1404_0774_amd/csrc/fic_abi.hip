@@ -161,6 +161,7 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   g.ident = 0;
   g.ctr = p->method == FIC_METHOD_MFMA && g.bits == 8 && n != 16;
   g.frag = (g.ctr && g.full) ||
+           (g.bits == 8 && n == 16 && p->method == FIC_METHOD_MFMA) ||
            (g.bits == 12 && (p->method == FIC_METHOD_MFMA || g.i8));
   return FIC_OK;
 }

@@ -63,9 +63,10 @@ __device__ __forceinline__ double g_from_centred(double h, double sa,
 // Position of k-element p of sweep column c in (a plane of) the FP16 domain
 // operand.  The matrix-core searches that sweep columns in (nearly) index
 // order (a full 8-bit centred search, whose column list is the identity,
-// and the 12-bit searches) store the operand in MFMA fragment order: block
-// c / 32, k-step p / 16, lane (p / 8 mod 2) 32 + c mod 32, element p mod 8,
-// so that the 64 lanes of a wave read one contiguous run per k-step.
+// the 16x16 and the 12-bit searches) store the operand in MFMA fragment
+// order: block c / 32, k-step p / 16, lane (p / 8 mod 2) 32 + c mod 32,
+// element p mod 8, so that the 64 lanes of a wave read one contiguous run
+// per k-step.
 // Otherwise each column holds its K elements in order.
 __host__ __device__ inline size_t bop_index(const Geo &g, long long c, int p) {
   if (g.frag)

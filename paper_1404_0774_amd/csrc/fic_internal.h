@@ -42,8 +42,9 @@ struct Geo {
                      //   A - round(SA/K) and b - round(Sb/K), exact FP16
   int frag;          // 1: the domain operand planes are stored in MFMA
                      //   fragment order (full matrix-core searches of 8-bit
-                     //   centred images, and the 12-bit matrix-core
-                     //   searches; bop_index and bop8_index give the layout)
+                     //   centred images, the 16x16 and the 12-bit
+                     //   matrix-core searches; bop_index and bop8_index give
+                     //   the layout)
   double escale;     // 2^(2 sb + 2): residual * escale is an integer
   double P;          // 2^bits
   double dlt;        // offset step

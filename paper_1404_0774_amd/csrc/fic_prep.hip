@@ -82,7 +82,16 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     for (int j = 0; j < N; ++j) vh[j] = (_Float16)(float)(Av[j] - m);
   }
   if (live) {
-    *(halfN *)(b.bop + bop_index(g, col, i * N)) = vh;
+    if constexpr (N == 16) {
+      // fragment order keeps runs of 8 elements together, not 16
+      typedef _Float16 half8v __attribute__((ext_vector_type(8)));
+      *(half8v *)(b.bop + bop_index(g, col, i * N)) =
+          __builtin_shufflevector(vh, vh, 0, 1, 2, 3, 4, 5, 6, 7);
+      *(half8v *)(b.bop + bop_index(g, col, i * N + 8)) =
+          __builtin_shufflevector(vh, vh, 8, 9, 10, 11, 12, 13, 14, 15);
+    } else {
+      *(halfN *)(b.bop + bop_index(g, col, i * N)) = vh;
+    }
     if (g.bits == 12)
       *(halfN *)(b.bop + (size_t)g.NC_pad * K + bop_index(g, col, i * N)) = vl;
     if (g.i8) {

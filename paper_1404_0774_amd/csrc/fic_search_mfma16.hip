@@ -213,9 +213,10 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_16(Geo g, EncBufs b) {
   {
     const int ci = column16(b, nD, c0, cl, g.ident);
     const int col = ci >= 0 ? ci : 0;
-    const _Float16 *bsrc = b.bop + (size_t)col * K + 8 * h;
+    const _Float16 *bsrc =
+        b.bop + (size_t)(col >> 5) * 32 * K + ((h << 5) | (col & 31)) * 8;
 #pragma unroll
-    for (int kk = 0; kk < KS; ++kk) bh[kk] = *(const half8 *)(bsrc + 16 * kk);
+    for (int kk = 0; kk < KS; ++kk) bh[kk] = *(const half8 *)(bsrc + 512 * kk);
     const float2 sadp = b.col_sadp[col];
     csa = sadp.x;
     cdp = ci >= 0 ? sadp.y : __builtin_inff();
@@ -231,9 +232,12 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_16(Geo g, EncBufs b) {
     const int ncol = ci_next >= 0 ? ci_next : 0;
     const bool nlive = ci_next >= 0;
     {
-      const _Float16 *bsrc = b.bop + (size_t)ncol * K + 8 * h;
+      // fragment order (bop_index): lane (h, c mod 32) of k-step kk reads
+      // 16 bytes at block offset kk 1024 + 16 lane, one run per wave
+      const _Float16 *bsrc =
+          b.bop + (size_t)(ncol >> 5) * 32 * K + ((h << 5) | (ncol & 31)) * 8;
 #pragma unroll
-      for (int kk = 0; kk < KS; ++kk) bhn[kk] = *(const half8 *)(bsrc + 16 * kk);
+      for (int kk = 0; kk < KS; ++kk) bhn[kk] = *(const half8 *)(bsrc + 512 * kk);
     }
     const float2 nsadp = b.col_sadp[ncol];
     const float nsa = nsadp.x, ndp = nlive ? nsadp.y : __builtin_inff();
@@ -343,6 +347,8 @@ hipError_t launch_search_mfma16(const Geo &g, const EncBufs &b,
   if (g.bits != 8 || g.K != 256) return hipErrorInvalidValue;
   static_assert(4 * kWR == kMfma12RangesPerWG, "row group size");
   if (workgroups < 1) workgroups = 1;
+  // the kernel reads the domain operand in fragment order only
+  if (!g.frag) return hipErrorInvalidValue;
   auto kern = k_search_mfma_16<256>;
   hipLaunchKernelGGL(kern, dim3(workgroups), dim3(256), 0, st, g, b);
   return hipGetLastError();
