@@ -33,20 +33,6 @@ int ok() {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// x with (a x) mod m == 1 for a coprime to m (extended Euclid); 0 for m = 1.
-long long inverse_mod(long long a, long long m) {
-  long long r0 = m, r1 = a % m, x0 = 0, x1 = 1;
-  while (r1 != 0) {
-    const long long q = r0 / r1;
-    long long t = r0 - q * r1;
-    r0 = r1;
-    r1 = t;
-    t = x0 - q * x1;
-    x0 = x1;
-    x1 = t;
-  }
-  return m == 1 ? 0 : ((x0 % m) + m) % m;
-}
 
 long long gcd_ll(long long a, long long b) {
   while (b) {
@@ -148,7 +134,6 @@ int make_geo(const fic_params *p, Geo &g, bool for_encode) {
   if (st < 1) st = 1;
   while (gcd_ll(st, g.ND) != 1) ++st;
   g.dom_stride = (int)st;
-  g.dom_stride_inv = (int)inverse_mod(st, g.ND);
   // range slots: the same stride through the ranges, so that every search
   // row group samples the whole image and the work per workgroup evens out
   long long rs = llround(0.6180339887498949 * g.R_pad);

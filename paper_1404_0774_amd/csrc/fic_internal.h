@@ -24,7 +24,6 @@ struct Geo {
   int NC_pad;        // NCB * 32
   int cbits;         // low bits of the search key that hold the candidate
   int dom_stride;    // sweep order: column c holds domain (c * dom_stride) % ND
-  int dom_stride_inv;  // domain d sits in column (d * dom_stride_inv) % ND
   int rng_stride;    // range slots: slot i holds range (i * rng_stride) % R_pad
                      //   (slots of ranges >= R are padding)
   int pix_a;         // 1: the 8-bit n = 8 matrix-core search builds its range

@@ -11,11 +11,11 @@ namespace fic {
 
 namespace {
 
-// One thread per (domain, cell row): N threads per domain, domains in
-// natural order so that the threads of a wave read neighbouring pixels.
-// Domain d goes to sweep column (d * dom_stride_inv) mod ND, the column
-// that holds domain (c * dom_stride) mod ND; threads past ND fill the
-// padding columns.  Its 2x2 cell sums A (4x the contracted value of Alg. 1)
+// One thread per (sweep column, cell row): N threads per column, columns in
+// order, so that the threads of a wave write neighbouring operand runs and
+// records (the domains they read are scattered over the image, which stays
+// in the L2).  Column c holds domain (c * dom_stride) mod ND; threads past
+// ND fill the padding columns.  Its 2x2 cell sums A (4x the contracted value of Alg. 1)
 // are written as exact FP16 integers.  12-bit images store A = 128 A_hi +
 // A_lo as two planes.  Flat domains (no variance) get +inf as their prune
 // denominator: they all fit any range with s = 0 and the same offset (eqs.
@@ -30,7 +30,7 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
   if (threadIdx.x == 0) s_flat = INT_MAX;
   __syncthreads();
   const long long t = (long long)bid * blockDim.x + threadIdx.x;
-  const long long e = t / N;  // domain, or padding column e >= ND
+  const long long e = t / N;  // column (sweep order), or padding e >= ND
   const int i = (int)(t % N);
   const bool live = e < g.NC_pad;
   long long col = e;
@@ -44,12 +44,11 @@ __device__ __forceinline__ void prep_domains_body(const Geo &g, const Pix *img,
     Av[j] = 0;
   }
   if (live && e < g.ND) {
-    d = (int)e;
-    // 32-bit arithmetic whenever d * stride_inv < ND^2 fits
-    col = g.ND <= 65000
-              ? (long long)(((unsigned)d * (unsigned)g.dom_stride_inv) %
-                            (unsigned)g.ND)
-              : ((long long)d * g.dom_stride_inv) % g.ND;
+    // column e holds domain (e * dom_stride) mod ND; 32-bit arithmetic
+    // whenever e * dom_stride < ND^2 fits
+    d = g.ND <= 65000
+            ? (int)(((unsigned)e * (unsigned)g.dom_stride) % (unsigned)g.ND)
+            : (int)((e * g.dom_stride) % g.ND);
     const int Y = (d / g.NX) * g.step, X = (d % g.NX) * g.step;
     const Pix *r0 = img + (size_t)(Y + 2 * i) * g.W + X;
     const bool wide = domain_rows_aligned(g, img);

@@ -56,7 +56,8 @@ def test_host_abi_under_asan_ubsan(tmp_path):
     run([CLANG, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
          "-fno-sanitize-recover=undefined", "-c", os.path.join(HERE, "abi_driver.cpp"), "-o", drv])
     exe = str(tmp_path / "abi_driver")
-    run([CLANG, "--hip-link", "--offload-arch=gfx950", "-fsanitize=address,undefined", drv, *objs,
+    run([CLANG, "--hip-link", "--offload-arch=gfx950", "-fsanitize=address,undefined",
+         "-fno-gpu-sanitize", drv, *objs,
          "-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib", "-o", exe])
     # the HIP runtime keeps allocations until exit: leak checking is for the oracle
     env = dict(SAN_ENV, ASAN_OPTIONS="detect_leaks=0")
