@@ -649,7 +649,12 @@ __device__ __forceinline__ void search_rows(const Geo &g, const EncBufs &b,
 
 // One image: a grid of G workgroups over the searched ranges and columns.
 // The lists' lengths are read on the device; the rows of 64 ranges are each
-// split into G / rows chunks of column blocks (at least one).
+// split into G / rows chunks of column blocks (at least one), but no chunk
+// shorter than kMinChunkBlocks blocks: with few searched rows (a quadtree
+// level of a few hundred ranges) hundreds of workgroups would otherwise
+// share each range's key, and their syncs queue on its atomics.
+constexpr int kMinChunkBlocks = 16;
+
 template <int K>
 __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
                                                            const uint8_t *img) {
@@ -659,7 +664,8 @@ __global__ __launch_bounds__(256, 2) void k_search_mfma_u8(Geo g, EncBufs b,
   const int rows = (nA + kMfmaRangesPerWG - 1) / kMfmaRangesPerWG;
   const int ncb = (nD + 31) / 32;
   if (rows == 0 || ncb == 0) return;
-  const int chunks = max(1, min((int)gridDim.x / rows, ncb));
+  const int chunks = max(
+      1, min((int)gridDim.x / rows, (ncb + kMinChunkBlocks - 1) / kMinChunkBlocks));
   const int rg = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
   if (rg >= rows) return;
   const int cbpc = (ncb + chunks - 1) / chunks;
