@@ -291,7 +291,8 @@ hipError_t prep_impl(const Geo &g, const Pix *img, const EncBufs &b,
 // rank (set flags in lower lanes: the sum of the four ballots' mbcnt; in the
 // lane itself: the set bytes below it), so each round's stores land next to
 // each other.  A first pass counts each wave's flags, the 16 totals are
-// exchanged in LDS, and a second pass writes.
+// exchanged in LDS, and a second pass writes; up to 16 rounds a wave (65,536
+// flags an array) the words stay in registers between the passes.
 __device__ __forceinline__ unsigned flag_bits(const uint8_t *flag, int i,
                                               int end) {
   // bit e: flag i + e (i a multiple of 4, end a multiple of 16)
@@ -331,6 +332,64 @@ __device__ __forceinline__ void wave_write(const uint8_t *flag, int beg,
   }
 }
 
+// Up to R rounds a wave: every round's word is loaded at once and kept in
+// registers for both passes (one trip to memory instead of two chains of
+// dependent loads).
+template <int R>
+__device__ __forceinline__ int regs_count(const uint8_t *flag, int beg,
+                                          int end, int lane,
+                                          unsigned (&bits)[R]) {
+  int c = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    bits[r] = flag_bits(flag, beg + 256 * r + 4 * lane, end);
+    c += __builtin_popcount(bits[r]);
+  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  return c;
+}
+
+template <int R>
+__device__ __forceinline__ void regs_write(int beg, int end, int lane,
+                                           int pos, const unsigned (&bits)[R],
+                                           int32_t *out) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = beg + 256 * r + 4 * lane;
+    if (beg + 256 * r >= end) break;  // wave-uniform
+    int below = 0, total = 0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const unsigned long long m =
+          __builtin_amdgcn_ballot_w64((bits[r] >> e) & 1u);
+      below += __builtin_amdgcn_mbcnt_hi(
+          (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0));
+      total += __popcll(m);
+    }
+    int at = pos + below;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if ((bits[r] >> e) & 1u) out[at++] = i + e;
+    pos += total;
+  }
+}
+
+// Exclusive prefix of the 16 waves' counts (x, y) and their totals.
+__device__ __forceinline__ void wave_prefix(const int2 *wtot, int wave,
+                                            int &q0, int &q1, int &t0,
+                                            int &t1) {
+  q0 = q1 = t0 = t1 = 0;
+  for (int w = 0; w < 16; ++w) {
+    const int2 v = wtot[w];
+    if (w < wave) {
+      q0 += v.x;
+      q1 += v.y;
+    }
+    t0 += v.x;
+    t1 += v.y;
+  }
+}
+
 __device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
                                                int32_t *o0, int n1,
                                                const uint8_t *f1, int32_t *o1,
@@ -342,22 +401,40 @@ __device__ __forceinline__ void block_compact2(int n0, const uint8_t *f0,
   const int s1 = (n1 + 16 * 256 - 1) / (16 * 256) * 256;
   const int a0 = min(wave * s0, n0), a1 = min(a0 + s0, n0);
   const int b0 = min(wave * s1, n1), b1 = min(b0 + s1, n1);
-  const int c0 = wave_count(f0, a0, a1, lane);
-  const int c1 = wave_count(f1, b0, b1, lane);
-  if (lane == 0) wtot[wave] = int2{c0, c1};
-  __syncthreads();
-  int q0 = 0, q1 = 0, t0 = 0, t1 = 0;
-  for (int w = 0; w < 16; ++w) {
-    const int2 v = wtot[w];
-    if (w < wave) {
-      q0 += v.x;
-      q1 += v.y;
-    }
-    t0 += v.x;
-    t1 += v.y;
+  int q0, q1, t0, t1;
+  if (s0 <= 256 * 8 && s1 <= 256 * 8) {
+    // both arrays' words in registers, one exchange
+    unsigned r0[8], r1[8];
+    const int c0 = regs_count<8>(f0, a0, a1, lane, r0);
+    const int c1 = regs_count<8>(f1, b0, b1, lane, r1);
+    if (lane == 0) wtot[wave] = int2{c0, c1};
+    __syncthreads();
+    wave_prefix(wtot, wave, q0, q1, t0, t1);
+    regs_write<8>(a0, a1, lane, q0, r0, o0);
+    regs_write<8>(b0, b1, lane, q1, r1, o1);
+  } else if (s0 <= 256 * 16 && s1 <= 256 * 16) {
+    // one array at a time; the second exchange uses the other half of each
+    // entry, so it never overwrites counts another wave may still read
+    unsigned r[16];
+    const int c0 = regs_count<16>(f0, a0, a1, lane, r);
+    if (lane == 0) wtot[wave].x = c0;
+    __syncthreads();
+    wave_prefix(wtot, wave, q0, q1, t0, t1);
+    regs_write<16>(a0, a1, lane, q0, r, o0);
+    const int c1 = regs_count<16>(f1, b0, b1, lane, r);
+    if (lane == 0) wtot[wave].y = c1;
+    __syncthreads();
+    wave_prefix(wtot, wave, q0, q1, t0, t1);
+    regs_write<16>(b0, b1, lane, q1, r, o1);
+  } else {
+    const int c0 = wave_count(f0, a0, a1, lane);
+    const int c1 = wave_count(f1, b0, b1, lane);
+    if (lane == 0) wtot[wave] = int2{c0, c1};
+    __syncthreads();
+    wave_prefix(wtot, wave, q0, q1, t0, t1);
+    wave_write(f0, a0, a1, lane, q0, o0);
+    wave_write(f1, b0, b1, lane, q1, o1);
   }
-  wave_write(f0, a0, a1, lane, q0, o0);
-  wave_write(f1, b0, b1, lane, q1, o1);
   if (threadIdx.x == 0) {
     count[0] = t0;
     count[1] = t1;
