@@ -137,8 +137,11 @@ def main(argv=None):
                        args.reps, dev, log)
     entries.append(e); records.append(r)
     if not args.skip_direct:
-        e, r = tune_single("u8_512 direct", img, F.Params(512, 512, 8, 8, 4, method=F.METHOD_DIRECT),
-                           [4, 8, 16, 32], [1], max(3, args.reps // 3), dev, log)
+        # the plain method is tuned on the full search, the work it is
+        # compared on with the matrix-core search
+        e, r = tune_single("u8_512 direct", img,
+                           F.Params(512, 512, 8, 8, 4, method=F.METHOD_DIRECT, full_search=1),
+                           [4, 6, 8, 12, 16, 32], [1], max(3, args.reps // 3), dev, log)
         entries.append(e); records.append(r)
     img12 = torch.from_numpy(gen_image(512, 512, 12, 3).astype(np.int16)).to(dev)
     e, r = tune_single("ct12_512 mfma", img12, F.Params(512, 512, 12, 8, 2), [2, 4, 8, 12, 16, 20, 24, 32],
