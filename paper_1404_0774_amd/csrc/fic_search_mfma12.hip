@@ -12,8 +12,10 @@
 // resident b_lo fragment (exact: values <= 126), not to the streamed operand.
 //
 // The prune uses G rebuilt in FP32 (rounding error below 2^-22 G) with a
-// matching margin; queued pairs carry G rebuilt exactly in FP64, and drains
-// test and fit in FP64.  One row block (4 ranges x 8 transforms) per wave.
+// matching margin; queued pairs carry G exactly (an integer below 2^32), and
+// drains test and fit in FP64.  One row block (4 ranges x 8 transforms) per
+// wave; the domain operand's two planes are read in fragment order
+// (bop_index), into two register buffers in turn.
 #include <math.h>
 
 #include "fic_search_common.h"
